@@ -1,0 +1,208 @@
+/*
+ * ms.h - C ABI of libms, a two-stage multisplitting solver (synchronous or
+ * asynchronous block Jacobi outer sweep, conjugate-gradient inner solves on
+ * each block) for the 3D 7-point Laplace/Poisson system A x = b on one AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Method: Brown, Bull and Bethune, "A highly scalable approach to solving
+ * linear systems using two-stage multisplitting".  Section 2.1 defines the
+ * operator (7-point Laplace stencil, Dirichlet boundaries) and the stopping
+ * rule on ||Ax - b||_2; Section 3 gives the block Jacobi update
+ *     X_i^(k) = A_ii^{-1} (B_i - sum_{j != i} A_ij X_j^(k-1)),
+ * its loop (Listing 1: inner Krylov solve per block, halo exchange, global
+ * residual) and the global residual as the root-sum-square of the block
+ * residuals; Section 3.2 fixes a maximum number of inner iterations;
+ * Sections 2.1 and 2.3 describe the asynchronous variant in which a block
+ * uses the latest neighbour values it has.
+ *
+ * Conventions shared by every entry point
+ *   - Unknowns live on the interior points of an nx*ny*nz grid, C order,
+ *     element (i,j,k) at offset (i*ny + j)*nz + k (z fastest).
+ *   - (A u)(i,j,k) = 6 u(i,j,k) - sum of the six axis neighbours; a
+ *     neighbour outside the interior is a Dirichlet node whose value comes
+ *     from the boundary faces held by the handle and is moved to the
+ *     right-hand side: b_eff = b + sum over boundary neighbours of g.
+ *   - All vector arguments are FP64 DEVICE pointers (for instance the
+ *     data_ptr() of a contiguous torch tensor on the GPU), 8-byte aligned,
+ *     length nx*ny*nz, owned by the caller.  Nothing is retained after a
+ *     call returns.
+ *   - Relative residual = ||b_eff - A x||_2 / ||b_eff||_2 in FP64.
+ *   - Every call returns an ms_status; nothing aborts or prints.  After a
+ *     failure ms_last_error(handle) describes it.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef MS_H
+#define MS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MS_OK = 0,
+    MS_ERR_ARG = 1,           /* invalid argument; nothing was run          */
+    MS_ERR_HIP = 2,           /* a HIP runtime call failed                  */
+    MS_ERR_NOMEM = 3,         /* device allocation failed                   */
+    MS_ERR_NOT_CONVERGED = 4, /* max_sweeps reached above tol; x = last iterate */
+    MS_ERR_NONFINITE = 5,     /* residual became NaN/Inf; x unspecified     */
+    MS_ERR_DIVERGED = 6,      /* residual grew 1e6x over its start; x unspecified */
+    MS_ERR_UNSUPPORTED = 7    /* valid but not supported by this build      */
+} ms_status;
+
+typedef enum { MS_SYNC = 0, MS_ASYNC = 1 } ms_mode;
+typedef enum { MS_FP64 = 0, MS_MIXED = 1 } ms_precision;
+
+/* Interior grid size (points per axis, each >= 1). */
+typedef struct {
+    int64_t nx, ny, nz;
+} ms_grid;
+
+/* Block partition (Section 3: the unknowns split into blocks X_i): a tensor
+ * product of per-axis cuts.  gx,gy,gz = blocks per axis.  cuts_x is a HOST
+ * array of gx+1 increasing offsets 0 = c[0] < ... < c[gx] = nx (likewise y,
+ * z); NULL means a uniform split, which requires nx % gx == 0.  Every block
+ * edge must be a multiple of 2 and at most 1024 points; block (bi,bj,bk) has
+ * number (bi*gy + bj)*gz + bk. */
+typedef struct {
+    int32_t gx, gy, gz;
+    const int32_t *cuts_x, *cuts_y, *cuts_z;
+} ms_blocks;
+
+/* Dirichlet data g on the six faces, DEVICE pointers in the order
+ * -x,+x,-y,+y,-z,+z.  The x faces are [ny][nz], the y faces [nx][nz], the z
+ * faces [nx][ny] (C order).  NULL means a zero face.  Copied at ms_create /
+ * ms_set_bc; the caller may free them afterwards. */
+typedef struct {
+    const double *face[6];
+} ms_bc;
+
+/* Solver options.  Fill with ms_default_opts() and change what is needed. */
+typedef struct {
+    int32_t max_sweeps;   /* outer sweeps before MS_ERR_NOT_CONVERGED (default 100000) */
+    double inner_tol;     /* > 0: also stop a block's CG once ||r_i|| <= inner_tol*||r_i^0|| */
+    int32_t staleness;    /* async: a block may run at most this many sweeps
+                             ahead of any neighbour (default 2, >= 0) */
+    int32_t precision;    /* ms_precision (default MS_FP64) */
+    void *stream;         /* hipStream_t used for all work; NULL = null stream */
+    int32_t check_every;  /* sync: sweeps enqueued between host reads of the
+                             convergence flag (0 = automatic) */
+    int32_t group_blocks; /* sync: blocks processed together so their inner
+                             vectors stay cache resident (0 = automatic,
+                             -1 = all blocks at once) */
+    int32_t x_chunk;      /* x planes marched per workgroup (0 = automatic) */
+    int32_t profile;      /* 1: time each kernel class with HIP events */
+    int32_t use_graph;    /* sync: 1 = replay sweeps from a captured HIP graph
+                             (default 1) */
+} ms_opts;
+
+/* Kernel classes reported by the profile counters of ms_stats. */
+enum {
+    MS_K_RESID = 0,   /* outer residual r = b_eff - A x with halo reads   */
+    MS_K_STENCIL = 1, /* inner CG: p = r + beta p; sigma = p.A_ii p       */
+    MS_K_UPDATE = 2,  /* inner CG: d += alpha p; r -= alpha A_ii p; r.r   */
+    MS_K_FINAL = 3,   /* last inner step fused with x_new = x + d         */
+    MS_K_CHECK = 4,   /* global residual sum and convergence test          */
+    MS_K_OTHER = 5,
+    MS_K_COUNT = 8
+};
+
+typedef struct {
+    int32_t sweeps;            /* outer updates applied to x                 */
+    int64_t inner_iters;       /* CG iterations summed over blocks and sweeps */
+    double rel_residual;       /* true FP64 relative residual of returned x  */
+    double seconds;            /* wall time of the call                      */
+    int32_t max_staleness_seen;/* async: largest version gap observed        */
+    int32_t relaunches;        /* async: relaunches after a failed verification */
+    int32_t history_len;       /* entries written to history                 */
+    double *history;           /* HOST buffer supplied by the caller (or NULL):
+                                  relative residual at the top of each sweep */
+    int32_t history_cap;       /* its capacity                               */
+    double kernel_ms[MS_K_COUNT];       /* profile=1: summed event time      */
+    int64_t kernel_launches[MS_K_COUNT];/* profile=1: launches timed         */
+} ms_stats;
+
+typedef struct ms_handle ms_handle;
+
+/* Fill *o with the defaults listed above. */
+void ms_default_opts(ms_opts *o);
+
+/* Create a solver for one grid, partition and boundary data (Section 3:
+ * blocks X_i; Section 2.1: Laplace operator with Dirichlet boundaries).
+ * Allocates every device buffer a solve needs, so ms_solve never allocates.
+ * Errors: MS_ERR_ARG (bad sizes or cuts), MS_ERR_NOMEM, MS_ERR_HIP.  On
+ * error *out is NULL. */
+ms_status ms_create(const ms_grid *grid, const ms_blocks *blocks,
+                    const ms_bc *bc, ms_handle **out);
+
+/* Replace the boundary data (same layout as ms_create). */
+ms_status ms_set_bc(ms_handle *h, const ms_bc *bc);
+
+/* Solve A x = b_eff by two-stage multisplitting (Section 3, Listing 1):
+ * each outer sweep computes r = b_eff - A x with neighbour-block values read
+ * straight from x (the halo exchange), tests ||r|| / ||b_eff|| <= tol, runs
+ * at most inner_iters CG iterations on A_ii d_i = r_i in every block from
+ * d_i = 0, then sets x_i += d_i.
+ *   b      device, FP64: interior right-hand side before boundary lifting
+ *          (for -lap u = f with spacing h this is h*h*f).  Never written.
+ *   x      device, FP64, in/out: initial guess in, iterate out.  Must not
+ *          alias b.
+ *   tol    stop at the first iterate with relative residual <= tol; tol <= 0
+ *          runs exactly opts->max_sweeps sweeps and returns MS_OK.
+ *   inner_iters  maximum CG iterations per block per sweep (>= 1).
+ *   mode   MS_SYNC: every block of sweep k reads sweep k-1 values (Jacobi).
+ *          MS_ASYNC: blocks advance independently and read whatever
+ *          neighbour values are in memory, a block running at most
+ *          opts->staleness sweeps ahead of a neighbour; the stop is decided
+ *          from published block residuals and then verified in FP64.
+ *   opts   NULL for defaults.  stats: NULL or filled on return.
+ * Precision MS_MIXED runs the inner CG in FP32 (storage and accumulation)
+ * while residual, convergence test and x stay FP64 (iterative refinement).
+ * Blocking: returns once the work on opts->stream is finished.
+ * Errors: MS_ERR_ARG, MS_ERR_NOT_CONVERGED (x = last iterate, stats valid),
+ * MS_ERR_NONFINITE / MS_ERR_DIVERGED (x unspecified), MS_ERR_HIP.
+ * If ||b_eff|| = 0 the result is x = 0 with MS_OK. */
+ms_status ms_solve(ms_handle *h, const double *b, double *x, double tol,
+                   int32_t inner_iters, ms_mode mode, const ms_opts *opts,
+                   ms_stats *stats);
+
+/* True FP64 relative residual ||b_eff - A x||_2 / ||b_eff||_2 (Section 2.1
+ * stopping quantity; Section 3 root-sum-square of block residuals).  b, x:
+ * device FP64.  *rel_out (host) receives the value (0 if ||b_eff|| = 0);
+ * abs_out (host, nullable) receives ||b_eff - A x||_2.  stream: hipStream_t
+ * or NULL.  Blocking. */
+ms_status ms_residual(ms_handle *h, const double *b, const double *x,
+                      double *rel_out, double *abs_out, void *stream);
+
+/* y = A u with zero values outside the interior (the Section 2.1 stencil,
+ * boundary data not applied).  u, y device FP64, must not alias.  Enqueued on
+ * stream (hipStream_t or NULL); not blocking. */
+ms_status ms_apply(ms_handle *h, const double *u, double *y, void *stream);
+
+/* Conventional global solver (Section 4's baseline, here unpreconditioned CG
+ * on the whole grid) with the same kernels and data layout.  Stops at the
+ * first iteration whose recurrence residual is <= tol * ||b_eff|| (tol <= 0:
+ * run exactly max_iters iterations) and reports the true residual in stats.
+ * Same argument rules as ms_solve. */
+ms_status ms_cg(ms_handle *h, const double *b, double *x, double tol,
+                int32_t max_iters, const ms_opts *opts, ms_stats *stats);
+
+/* Free the handle and its device memory (NULL is ignored). */
+void ms_destroy(ms_handle *h);
+
+/* Static text for a status code. */
+const char *ms_status_string(ms_status s);
+
+/* Text of the last error on this handle (or of the last failed ms_create
+ * when h is NULL).  Valid until the next call on the handle. */
+const char *ms_last_error(const ms_handle *h);
+
+/* Library version string. */
+const char *ms_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MS_H */

@@ -1,0 +1,682 @@
+/*
+ * Plain FP64 CPU oracle for two-stage multisplitting (block Jacobi outer
+ * sweep, conjugate-gradient inner solves) on the 3D 7-point Laplace/Poisson
+ * system, after Brown, Bull and Bethune, "A highly scalable approach to
+ * solving linear systems using two-stage multisplitting".
+ *
+ * THIS IS TEST INFRASTRUCTURE.  It exists only to check the GPU library.
+ * Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load it.  It shares no code, header, table or helper with
+ * the GPU library, and it is written to be read against the paper, not to
+ * be fast: every loop is the plain definition.  OpenMP is used only where
+ * each output element is computed independently, and every sum is taken in
+ * a fixed serial order, so results do not depend on the thread count.
+ *
+ * Conventions (the same ones the GPU library documents, restated here):
+ *   - interior grid nx*ny*nz, C order, index (i*ny + j)*nz + k, z fastest;
+ *   - (A u)(i,j,k) = 6 u(i,j,k) - sum of the 6 axis neighbours, the
+ *     7-point Laplacian of Section 2.1 (diagonal 6, off-diagonal -1);
+ *   - neighbours outside the interior are Dirichlet nodes; their values g
+ *     are moved to the right-hand side (b_eff = b + sum of boundary g);
+ *   - six boundary faces in the order -x,+x,-y,+y,-z,+z; the x faces are
+ *     [ny][nz], the y faces [nx][nz], the z faces [nx][ny]; NULL means 0;
+ *   - blocks are a tensor product of per-axis cut lists
+ *     cx[0]=0 < cx[1] < ... < cx[gx]=nx (likewise y, z); block (bi,bj,bk)
+ *     has linear number (bi*gy + bj)*gz + bk.
+ *
+ * Readings of the paper where it is silent (each is also listed in the
+ * design notes):
+ *   - inner solver: unpreconditioned CG (every diagonal block is SPD);
+ *   - inner start: residual-correction form, d = 0 on r_i, which equals CG
+ *     on A_ii X_i = B_i - sum_j A_ij X_j started from the current X_i;
+ *   - inner stop: at most m iterations, or earlier when
+ *     ||r_i|| <= inner_tol * ||r_i at entry|| (inner_tol > 0 only), or on
+ *     breakdown (p.Ap not > 0);
+ *   - residual: the true residual ||b_eff - A x|| / ||b_eff||, tested with
+ *     "<=" at the top of every sweep;
+ *   - tol <= 0 means: run exactly max_sweeps sweeps.
+ *
+ * ORACLE_MUTANT (compile-time, test use only) plants one known mistake so
+ * that the test suite can show each pin catches something.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef ORACLE_MUTANT
+#define ORACLE_MUTANT 0
+#endif
+
+/* status codes returned by the solvers */
+#define OR_OK 0
+#define OR_NOT_CONVERGED 4
+#define OR_NONFINITE 5
+#define OR_DIVERGED 6
+#define OR_ARG 1
+
+#define IDX(i, j, k) (((long)(i) * ny + (j)) * nz + (k))
+
+/* ------------------------------------------------------------------ */
+/* Operator and right-hand side (Section 2.1: 7-point Laplace stencil) */
+/* ------------------------------------------------------------------ */
+
+/* y = A u with u = 0 outside the interior. */
+void or_apply(long nx, long ny, long nz, const double *u, double *y)
+{
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < nx; i++)
+        for (long j = 0; j < ny; j++)
+            for (long k = 0; k < nz; k++) {
+                double s = 6.0 * u[IDX(i, j, k)];
+                if (i > 0) s -= u[IDX(i - 1, j, k)];
+                if (i < nx - 1) s -= u[IDX(i + 1, j, k)];
+                if (j > 0) s -= u[IDX(i, j - 1, k)];
+                if (j < ny - 1) s -= u[IDX(i, j + 1, k)];
+                if (k > 0) s -= u[IDX(i, j, k - 1)];
+#if ORACLE_MUTANT != 1
+                if (k < nz - 1) s -= u[IDX(i, j, k + 1)];
+#endif
+                y[IDX(i, j, k)] = s;
+            }
+}
+
+/* b_eff = b + g at every boundary neighbour (Dirichlet lifting). */
+void or_lift_bc(long nx, long ny, long nz, const double *b,
+                const double *fxm, const double *fxp, const double *fym,
+                const double *fyp, const double *fzm, const double *fzp,
+                double *beff)
+{
+#if ORACLE_MUTANT == 8
+    /* planted mistake: -x and -y faces exchanged (only meaningful on cubes) */
+    const double *t = fxm; fxm = fym; fym = t;
+#endif
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < nx; i++)
+        for (long j = 0; j < ny; j++)
+            for (long k = 0; k < nz; k++) {
+                double s = b ? b[IDX(i, j, k)] : 0.0;
+                if (i == 0 && fxm) s += fxm[j * nz + k];
+                if (i == nx - 1 && fxp) s += fxp[j * nz + k];
+                if (j == 0 && fym) s += fym[i * nz + k];
+                if (j == ny - 1 && fyp) s += fyp[i * nz + k];
+                if (k == 0 && fzm) s += fzm[i * ny + j];
+#if ORACLE_MUTANT == 2
+                if (k == nz - 1 && fzp) s -= fzp[i * ny + j];
+#else
+                if (k == nz - 1 && fzp) s += fzp[i * ny + j];
+#endif
+                beff[IDX(i, j, k)] = s;
+            }
+}
+
+/* r = b_eff - A x; returns ||r||_2 summed in index order. r may be NULL. */
+double or_residual(long nx, long ny, long nz, const double *beff,
+                   const double *x, double *r)
+{
+    long n = nx * ny * nz;
+    double *rr = r ? r : (double *)malloc(sizeof(double) * (size_t)n);
+    or_apply(nx, ny, nz, x, rr);
+#pragma omp parallel for schedule(static)
+    for (long t = 0; t < n; t++) rr[t] = beff[t] - rr[t];
+    double s = 0.0;
+    for (long t = 0; t < n; t++) s += rr[t] * rr[t];
+    if (!r) free(rr);
+    return sqrt(s);
+}
+
+double or_norm2(long n, const double *v)
+{
+    double s = 0.0;
+    for (long t = 0; t < n; t++) s += v[t] * v[t];
+    return sqrt(s);
+}
+
+/* ------------------------------------------------------------------ */
+/* Inner stage: CG on one diagonal block A_ii (Section 3, the inner    */
+/* Krylov solve of each block; Section 3.2, maximum inner iterations)  */
+/* ------------------------------------------------------------------ */
+
+/* q = A_ii p on a bx*by*bz block: the 7-point stencil with every
+ * neighbour outside the block taken as zero. */
+static void block_apply(int bx, int by, int bz, const double *p, double *q)
+{
+    for (int i = 0; i < bx; i++)
+        for (int j = 0; j < by; j++)
+            for (int k = 0; k < bz; k++) {
+                long c = ((long)i * by + j) * bz + k;
+                double s = 6.0 * p[c];
+#if ORACLE_MUTANT == 6
+                /* planted mistake: periodic wrap instead of zero at the block faces */
+                s -= p[(((long)((i + bx - 1) % bx)) * by + j) * bz + k];
+#else
+                if (i > 0) s -= p[c - (long)by * bz];
+#endif
+                if (i < bx - 1) s -= p[c + (long)by * bz];
+                if (j > 0) s -= p[c - bz];
+                if (j < by - 1) s -= p[c + bz];
+                if (k > 0) s -= p[c - 1];
+                if (k < bz - 1) s -= p[c + 1];
+                q[c] = s;
+            }
+}
+
+static double dot(long n, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (long t = 0; t < n; t++) s += a[t] * b[t];
+    return s;
+}
+
+/* CG on A_ii d = r from d = 0, at most m iterations.
+ * In: r = block residual.  Out: d = correction, r = final inner residual.
+ * p, q: scratch of the block's size.  Returns the iterations taken. */
+static int block_cg(int bx, int by, int bz, double *r, double *d, double *p,
+                    double *q, int m, double inner_tol)
+{
+    long n = (long)bx * by * bz;
+    for (long t = 0; t < n; t++) { d[t] = 0.0; p[t] = r[t]; }
+    double rho = dot(n, r, r);
+    double rho0 = rho;
+    if (rho == 0.0) return 0;
+    int it = 0;
+    while (it < m) {
+        block_apply(bx, by, bz, p, q);
+        double sigma = dot(n, p, q);
+        if (!(sigma > 0.0)) break;             /* breakdown guard */
+#if ORACLE_MUTANT == 10
+        double alpha = sigma / rho;
+#else
+        double alpha = rho / sigma;
+#endif
+        for (long t = 0; t < n; t++) {
+            d[t] += alpha * p[t];
+#if ORACLE_MUTANT == 4
+            r[t] += alpha * q[t];
+#else
+            r[t] -= alpha * q[t];
+#endif
+        }
+        it++;
+        double rho_new = dot(n, r, r);
+        if (inner_tol > 0.0 && sqrt(rho_new) <= inner_tol * sqrt(rho0)) break;
+#if ORACLE_MUTANT == 3
+        double beta = rho / rho_new;
+#else
+        double beta = rho_new / rho;
+#endif
+        for (long t = 0; t < n; t++) p[t] = r[t] + beta * p[t];
+        rho = rho_new;
+    }
+    return it;
+}
+
+/* Same inner stage carried out entirely in single precision (storage and
+ * accumulation), used only to attribute the error of mixed precision. */
+static void block_apply_f(int bx, int by, int bz, const float *p, float *q)
+{
+    for (int i = 0; i < bx; i++)
+        for (int j = 0; j < by; j++)
+            for (int k = 0; k < bz; k++) {
+                long c = ((long)i * by + j) * bz + k;
+                float s = 6.0f * p[c];
+                if (i > 0) s -= p[c - (long)by * bz];
+                if (i < bx - 1) s -= p[c + (long)by * bz];
+                if (j > 0) s -= p[c - bz];
+                if (j < by - 1) s -= p[c + bz];
+                if (k > 0) s -= p[c - 1];
+                if (k < bz - 1) s -= p[c + 1];
+                q[c] = s;
+            }
+}
+
+static float dot_f(long n, const float *a, const float *b)
+{
+    float s = 0.0f;
+    for (long t = 0; t < n; t++) s += a[t] * b[t];
+    return s;
+}
+
+static int block_cg_f(int bx, int by, int bz, float *r, float *d, float *p,
+                      float *q, int m, double inner_tol)
+{
+    long n = (long)bx * by * bz;
+    for (long t = 0; t < n; t++) { d[t] = 0.0f; p[t] = r[t]; }
+    float rho = dot_f(n, r, r);
+    float rho0 = rho;
+    if (rho == 0.0f) return 0;
+    int it = 0;
+    while (it < m) {
+        block_apply_f(bx, by, bz, p, q);
+        float sigma = dot_f(n, p, q);
+        if (!(sigma > 0.0f)) break;
+        float alpha = rho / sigma;
+        for (long t = 0; t < n; t++) { d[t] += alpha * p[t]; r[t] -= alpha * q[t]; }
+        it++;
+        float rho_new = dot_f(n, r, r);
+        if (inner_tol > 0.0 && sqrtf(rho_new) <= (float)inner_tol * sqrtf(rho0)) break;
+        float beta = rho_new / rho;
+        for (long t = 0; t < n; t++) p[t] = r[t] + beta * p[t];
+        rho = rho_new;
+    }
+    return it;
+}
+
+/* ------------------------------------------------------------------ */
+/* Block bookkeeping                                                   */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    long nx, ny, nz;
+    int gx, gy, gz;
+    const int *cx, *cy, *cz;
+} part_t;
+
+static int check_cuts(const int *c, int g, long n)
+{
+    if (g < 1 || c[0] != 0 || c[g] != n) return 0;
+    for (int t = 0; t < g; t++)
+        if (c[t + 1] <= c[t]) return 0;
+    return 1;
+}
+
+static void block_range(const part_t *P, int b, int *i0, int *j0, int *k0,
+                        int *bx, int *by, int *bz)
+{
+    int bk = b % P->gz, bj = (b / P->gz) % P->gy, bi = b / (P->gz * P->gy);
+    *i0 = P->cx[bi]; *j0 = P->cy[bj]; *k0 = P->cz[bk];
+    *bx = P->cx[bi + 1] - P->cx[bi];
+    *by = P->cy[bj + 1] - P->cy[bj];
+    *bz = P->cz[bk + 1] - P->cz[bk];
+}
+
+/* copy a block of a global array into a packed buffer, and back */
+static void gather(const part_t *P, int b, const double *g, double *loc)
+{
+    long nx = P->nx, ny = P->ny, nz = P->nz; (void)nx;
+    int i0, j0, k0, bx, by, bz;
+    block_range(P, b, &i0, &j0, &k0, &bx, &by, &bz);
+    for (int i = 0; i < bx; i++)
+        for (int j = 0; j < by; j++)
+            for (int k = 0; k < bz; k++)
+                loc[((long)i * by + j) * bz + k] = g[IDX(i0 + i, j0 + j, k0 + k)];
+}
+
+static void scatter(const part_t *P, int b, const double *loc, double *g)
+{
+    long nx = P->nx, ny = P->ny, nz = P->nz; (void)nx;
+    int i0, j0, k0, bx, by, bz;
+    block_range(P, b, &i0, &j0, &k0, &bx, &by, &bz);
+    for (int i = 0; i < bx; i++)
+        for (int j = 0; j < by; j++)
+            for (int k = 0; k < bz; k++)
+                g[IDX(i0 + i, j0 + j, k0 + k)] = loc[((long)i * by + j) * bz + k];
+}
+
+static long max_block_volume(const part_t *P)
+{
+    long mx = 0;
+    for (int a = 0; a < P->gx; a++)
+        for (int c = 0; c < P->gy; c++)
+            for (int e = 0; e < P->gz; e++) {
+                long v = (long)(P->cx[a + 1] - P->cx[a]) * (P->cy[c + 1] - P->cy[c]) *
+                         (P->cz[e + 1] - P->cz[e]);
+                if (v > mx) mx = v;
+            }
+    return mx;
+}
+
+/* Residual of the current iterate, as the sum over blocks of the squared
+ * block residual norms (Section 3: the global residual is the square root
+ * of the sum of squares of the block-local residues).  Fills r. */
+static double blocked_residual_norm(const part_t *P, const double *beff,
+                                    const double *x, double *r)
+{
+    long nx = P->nx, ny = P->ny, nz = P->nz;
+    int nb = P->gx * P->gy * P->gz;
+#if ORACLE_MUTANT == 7
+    /* planted mistake: residual taken with the block-diagonal operator only
+     * (neighbour blocks' values never read) */
+    {
+        long vmax = max_block_volume(P);
+        double *loc = (double *)malloc(sizeof(double) * (size_t)vmax);
+        double *out = (double *)malloc(sizeof(double) * (size_t)vmax);
+        for (int b = 0; b < nb; b++) {
+            int i0, j0, k0, bx, by, bz;
+            block_range(P, b, &i0, &j0, &k0, &bx, &by, &bz);
+            gather(P, b, x, loc);
+            block_apply(bx, by, bz, loc, out);
+            scatter(P, b, out, r);
+        }
+        free(loc); free(out);
+#pragma omp parallel for schedule(static)
+        for (long t = 0; t < nx * ny * nz; t++) r[t] = beff[t] - r[t];
+    }
+#else
+    or_apply(nx, ny, nz, x, r);
+#pragma omp parallel for schedule(static)
+    for (long t = 0; t < nx * ny * nz; t++) r[t] = beff[t] - r[t];
+#endif
+    double total = 0.0;
+    for (int b = 0; b < nb; b++) {
+        int i0, j0, k0, bx, by, bz;
+        block_range(P, b, &i0, &j0, &k0, &bx, &by, &bz);
+        double s = 0.0;
+        for (int i = 0; i < bx; i++)
+            for (int j = 0; j < by; j++)
+                for (int k = 0; k < bz; k++) {
+                    double v = r[IDX(i0 + i, j0 + j, k0 + k)];
+                    s += v * v;
+                }
+        total += s;
+    }
+    return sqrt(total);
+}
+
+/* ------------------------------------------------------------------ */
+/* Outer stage: synchronous block Jacobi (Section 3 block formula and   */
+/* Listing 1: test the global residual, inner solve each block, halo    */
+/* exchange, repeat)                                                    */
+/* ------------------------------------------------------------------ */
+
+/*
+ * x (in/out): initial guess on entry, final iterate on exit.
+ * history (nullable, length max_sweeps+1): relative residual at the top of
+ *   each sweep, history[s] for s = 0..sweeps.
+ * precision: 0 = FP64 inner CG; 1 = FP32 inner CG (attribution only).
+ * Returns a status; *sweeps_out = number of updates applied.
+ */
+int or_block_jacobi(long nx, long ny, long nz, int gx, int gy, int gz,
+                    const int *cx, const int *cy, const int *cz,
+                    const double *beff, double *x, double tol, int m,
+                    double inner_tol, int max_sweeps, int precision,
+                    double *history, int *sweeps_out, long *inner_out)
+{
+    part_t P = {nx, ny, nz, gx, gy, gz, cx, cy, cz};
+    if (sweeps_out) *sweeps_out = 0;
+    if (inner_out) *inner_out = 0;
+    if (nx < 1 || ny < 1 || nz < 1 || m < 1 || max_sweeps < 0) return OR_ARG;
+    if (!check_cuts(cx, gx, nx) || !check_cuts(cy, gy, ny) || !check_cuts(cz, gz, nz))
+        return OR_ARG;
+    long n = nx * ny * nz;
+    int nb = gx * gy * gz;
+    double nbeff = or_norm2(n, beff);
+    if (!isfinite(nbeff)) return OR_NONFINITE;
+    if (nbeff == 0.0) {
+        memset(x, 0, sizeof(double) * (size_t)n);
+        if (history) history[0] = 0.0;
+        return OR_OK;
+    }
+    double *r = (double *)malloc(sizeof(double) * (size_t)n);
+    double *dg = (double *)malloc(sizeof(double) * (size_t)n);
+    long vmax = max_block_volume(&P);
+    long inner_total = 0;
+    int status = OR_OK;
+    double res0 = -1.0;
+    int s = 0;
+    for (;;) {
+        double res = blocked_residual_norm(&P, beff, x, r) / nbeff;
+        if (history) history[s] = res;
+        if (!isfinite(res)) { status = OR_NONFINITE; break; }
+        if (res0 < 0.0) res0 = res;
+        if (tol > 0.0 && res <= tol) break;
+        if (res > 1e6 * res0 && res0 > 0.0) { status = OR_DIVERGED; break; }
+        if (s == max_sweeps) { status = tol > 0.0 ? OR_NOT_CONVERGED : OR_OK; break; }
+        /* inner solves: each block reads only this sweep's residual */
+#pragma omp parallel
+        {
+            double *lr = (double *)malloc(sizeof(double) * (size_t)vmax);
+            double *ld = (double *)malloc(sizeof(double) * (size_t)vmax);
+            double *lp = (double *)malloc(sizeof(double) * (size_t)vmax);
+            double *lq = (double *)malloc(sizeof(double) * (size_t)vmax);
+            float *fr = NULL, *fd = NULL, *fp = NULL, *fq = NULL;
+            if (precision == 1) {
+                fr = (float *)malloc(sizeof(float) * (size_t)vmax);
+                fd = (float *)malloc(sizeof(float) * (size_t)vmax);
+                fp = (float *)malloc(sizeof(float) * (size_t)vmax);
+                fq = (float *)malloc(sizeof(float) * (size_t)vmax);
+            }
+#pragma omp for schedule(dynamic, 1) reduction(+ : inner_total)
+            for (int b = 0; b < nb; b++) {
+                int i0, j0, k0, bx, by, bz;
+                block_range(&P, b, &i0, &j0, &k0, &bx, &by, &bz);
+                long v = (long)bx * by * bz;
+                gather(&P, b, r, lr);
+                int it;
+                if (precision == 1) {
+                    for (long t = 0; t < v; t++) fr[t] = (float)lr[t];
+                    it = block_cg_f(bx, by, bz, fr, fd, fp, fq, m, inner_tol);
+                    for (long t = 0; t < v; t++) ld[t] = (double)fd[t];
+                } else {
+                    it = block_cg(bx, by, bz, lr, ld, lp, lq, m, inner_tol);
+                }
+                inner_total += it;
+                scatter(&P, b, ld, dg);
+            }
+            free(lr); free(ld); free(lp); free(lq);
+            free(fr); free(fd); free(fp); free(fq);
+        }
+        /* Jacobi update, after every block has read the old iterate */
+#pragma omp parallel for schedule(static)
+        for (long t = 0; t < n; t++) {
+#if ORACLE_MUTANT == 5
+            x[t] = dg[t];
+#else
+            x[t] += dg[t];
+#endif
+        }
+        s++;
+    }
+    free(r); free(dg);
+    if (sweeps_out) *sweeps_out = s;
+    if (inner_out) *inner_out = inner_total;
+    return status;
+}
+
+/*
+ * One synchronous sweep restricted to a list of blocks: for each listed
+ * block b, x_new_b = x_b + d_b with d_b from m inner CG iterations on the
+ * residual of x.  Writes the new values of listed blocks into xout (a full
+ * array; other entries untouched).  Used to check a GPU sweep one block at a
+ * time at sizes where a whole-grid oracle run would take too long.
+ */
+int or_block_sweep_some(long nx, long ny, long nz, int gx, int gy, int gz,
+                        const int *cx, const int *cy, const int *cz,
+                        const double *beff, const double *x, int nlist,
+                        const int *blocks, int m, double inner_tol,
+                        double *xout)
+{
+    part_t P = {nx, ny, nz, gx, gy, gz, cx, cy, cz};
+    if (!check_cuts(cx, gx, nx) || !check_cuts(cy, gy, ny) || !check_cuts(cz, gz, nz))
+        return OR_ARG;
+    long vmax = max_block_volume(&P);
+    int nb = gx * gy * gz;
+    for (int t = 0; t < nlist; t++)
+        if (blocks[t] < 0 || blocks[t] >= nb) return OR_ARG;
+#pragma omp parallel
+    {
+        double *lr = (double *)malloc(sizeof(double) * (size_t)vmax);
+        double *ld = (double *)malloc(sizeof(double) * (size_t)vmax);
+        double *lp = (double *)malloc(sizeof(double) * (size_t)vmax);
+        double *lq = (double *)malloc(sizeof(double) * (size_t)vmax);
+#pragma omp for schedule(dynamic, 1)
+        for (int t = 0; t < nlist; t++) {
+            int b = blocks[t];
+            int i0, j0, k0, bx, by, bz;
+            block_range(&P, b, &i0, &j0, &k0, &bx, &by, &bz);
+            /* block residual b_eff - A x, read cell by cell with the global
+             * operator (neighbour-block values are the halo) */
+            for (int i = 0; i < bx; i++)
+                for (int j = 0; j < by; j++)
+                    for (int k = 0; k < bz; k++) {
+                        long I = i0 + i, J = j0 + j, K = k0 + k;
+                        double s = 6.0 * x[IDX(I, J, K)];
+                        if (I > 0) s -= x[IDX(I - 1, J, K)];
+                        if (I < nx - 1) s -= x[IDX(I + 1, J, K)];
+                        if (J > 0) s -= x[IDX(I, J - 1, K)];
+                        if (J < ny - 1) s -= x[IDX(I, J + 1, K)];
+                        if (K > 0) s -= x[IDX(I, J, K - 1)];
+                        if (K < nz - 1) s -= x[IDX(I, J, K + 1)];
+                        lr[((long)i * by + j) * bz + k] = beff[IDX(I, J, K)] - s;
+                    }
+            block_cg(bx, by, bz, lr, ld, lp, lq, m, inner_tol);
+            for (int i = 0; i < bx; i++)
+                for (int j = 0; j < by; j++)
+                    for (int k = 0; k < bz; k++) {
+                        long c = ((long)i * by + j) * bz + k;
+                        xout[IDX(i0 + i, j0 + j, k0 + k)] = x[IDX(i0 + i, j0 + j, k0 + k)] + ld[c];
+                    }
+        }
+        free(lr); free(ld); free(lp); free(lq);
+    }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Asynchronous outer iterations, bounded-delay model (Section 2.3: the */
+/* latest received values are used; Section 2.1: whatever halo values   */
+/* a process has).  Deterministic given the delay table.                */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Every block advances one sweep at a time, but in sweep s the value of
+ * neighbour block j seen by block i is x_j from sweep s - delay, with
+ * delay = delays[(s * nb + i) * 6 + f] (f = the face -x,+x,-y,+y,-z,+z
+ * across which j lies), clipped to [0, min(S, s)].  Delays are supplied
+ * by the caller (seeded), so the run is reproducible.  The stopping test
+ * uses the true residual of the current iterate.  With all delays 0 this
+ * is the synchronous method exactly.
+ */
+int or_block_jacobi_async(long nx, long ny, long nz, int gx, int gy, int gz,
+                          const int *cx, const int *cy, const int *cz,
+                          const double *beff, double *x, double tol, int m,
+                          int max_sweeps, int S, const int *delays,
+                          double *history, int *sweeps_out)
+{
+    part_t P = {nx, ny, nz, gx, gy, gz, cx, cy, cz};
+    if (sweeps_out) *sweeps_out = 0;
+    if (nx < 1 || ny < 1 || nz < 1 || m < 1 || S < 0 || max_sweeps < 0) return OR_ARG;
+    if (!check_cuts(cx, gx, nx) || !check_cuts(cy, gy, ny) || !check_cuts(cz, gz, nz))
+        return OR_ARG;
+    long n = nx * ny * nz;
+    int nb = gx * gy * gz;
+    double nbeff = or_norm2(n, beff);
+    if (nbeff == 0.0) {
+        memset(x, 0, sizeof(double) * (size_t)n);
+        if (history) history[0] = 0.0;
+        return OR_OK;
+    }
+    /* ring of past iterates: hist[v % (S+1)] = x after v sweeps */
+    int ring = S + 1;
+    double **hist = (double **)malloc(sizeof(double *) * (size_t)ring);
+    for (int t = 0; t < ring; t++) hist[t] = (double *)malloc(sizeof(double) * (size_t)n);
+    memcpy(hist[0], x, sizeof(double) * (size_t)n);
+    double *r = (double *)malloc(sizeof(double) * (size_t)n);
+    double *xn = (double *)malloc(sizeof(double) * (size_t)n);
+    long vmax = max_block_volume(&P);
+    int status = OR_OK;
+    int s = 0;
+    for (;;) {
+        const double *xc = hist[s % ring];
+        double res = or_residual(nx, ny, nz, beff, xc, r) / nbeff;
+        if (history) history[s] = res;
+        if (!isfinite(res)) { status = OR_NONFINITE; break; }
+        if (tol > 0.0 && res <= tol) break;
+        if (s == max_sweeps) { status = tol > 0.0 ? OR_NOT_CONVERGED : OR_OK; break; }
+#pragma omp parallel
+        {
+            double *lr = (double *)malloc(sizeof(double) * (size_t)vmax);
+            double *ld = (double *)malloc(sizeof(double) * (size_t)vmax);
+            double *lp = (double *)malloc(sizeof(double) * (size_t)vmax);
+            double *lq = (double *)malloc(sizeof(double) * (size_t)vmax);
+#pragma omp for schedule(dynamic, 1)
+            for (int b = 0; b < nb; b++) {
+                int i0, j0, k0, bx, by, bz;
+                block_range(&P, b, &i0, &j0, &k0, &bx, &by, &bz);
+                const double *src[6];
+                for (int f = 0; f < 6; f++) {
+                    int dl = delays ? delays[((long)s * nb + b) * 6 + f] : 0;
+                    if (dl < 0) dl = 0;
+                    if (dl > S) dl = S;
+                    if (dl > s) dl = s;
+                    src[f] = hist[(s - dl) % ring];
+                }
+                for (int i = 0; i < bx; i++)
+                    for (int j = 0; j < by; j++)
+                        for (int k = 0; k < bz; k++) {
+                            long I = i0 + i, J = j0 + j, K = k0 + k;
+                            double v = 6.0 * xc[IDX(I, J, K)];
+                            /* in-block neighbours from the current iterate,
+                             * off-block neighbours from the delayed one */
+                            if (I > 0) v -= (i > 0 ? xc : src[0])[IDX(I - 1, J, K)];
+                            if (I < nx - 1) v -= (i < bx - 1 ? xc : src[1])[IDX(I + 1, J, K)];
+                            if (J > 0) v -= (j > 0 ? xc : src[2])[IDX(I, J - 1, K)];
+                            if (J < ny - 1) v -= (j < by - 1 ? xc : src[3])[IDX(I, J + 1, K)];
+                            if (K > 0) v -= (k > 0 ? xc : src[4])[IDX(I, J, K - 1)];
+                            if (K < nz - 1) v -= (k < bz - 1 ? xc : src[5])[IDX(I, J, K + 1)];
+                            lr[((long)i * by + j) * bz + k] = beff[IDX(I, J, K)] - v;
+                        }
+                block_cg(bx, by, bz, lr, ld, lp, lq, m, 0.0);
+                for (int i = 0; i < bx; i++)
+                    for (int j = 0; j < by; j++)
+                        for (int k = 0; k < bz; k++) {
+                            long c = ((long)i * by + j) * bz + k;
+                            long G = IDX(i0 + i, j0 + j, k0 + k);
+                            xn[G] = xc[G] + ld[c];
+                        }
+            }
+            free(lr); free(ld); free(lp); free(lq);
+        }
+        s++;
+        memcpy(hist[s % ring], xn, sizeof(double) * (size_t)n);
+    }
+    memcpy(x, hist[s % ring], sizeof(double) * (size_t)n);
+    for (int t = 0; t < ring; t++) free(hist[t]);
+    free(hist); free(r); free(xn);
+    if (sweeps_out) *sweeps_out = s;
+    return status;
+}
+
+/* ------------------------------------------------------------------ */
+/* Conventional solver: CG on the whole system (the global Krylov      */
+/* baseline the block method is compared against, Section 4)           */
+/* ------------------------------------------------------------------ */
+
+int or_cg(long nx, long ny, long nz, const double *beff, double *x, double tol,
+          int max_iters, double *history, int *iters_out)
+{
+    long n = nx * ny * nz;
+    if (iters_out) *iters_out = 0;
+    double nbeff = or_norm2(n, beff);
+    if (nbeff == 0.0) {
+        memset(x, 0, sizeof(double) * (size_t)n);
+        if (history) history[0] = 0.0;
+        return OR_OK;
+    }
+    double *r = (double *)malloc(sizeof(double) * (size_t)n);
+    double *p = (double *)malloc(sizeof(double) * (size_t)n);
+    double *q = (double *)malloc(sizeof(double) * (size_t)n);
+    or_residual(nx, ny, nz, beff, x, r);
+    memcpy(p, r, sizeof(double) * (size_t)n);
+    double rho = dot(n, r, r);
+    int it = 0, status = OR_OK;
+    for (;;) {
+        double res = sqrt(rho) / nbeff;   /* recurrence residual */
+        if (history) history[it] = res;
+        if (!isfinite(res)) { status = OR_NONFINITE; break; }
+        if (tol > 0.0 && res <= tol) break;
+        if (it == max_iters) { status = tol > 0.0 ? OR_NOT_CONVERGED : OR_OK; break; }
+        or_apply(nx, ny, nz, p, q);
+        double sigma = dot(n, p, q);
+        if (!(sigma > 0.0)) break;
+        double alpha = rho / sigma;
+        for (long t = 0; t < n; t++) { x[t] += alpha * p[t]; r[t] -= alpha * q[t]; }
+        double rho_new = dot(n, r, r);
+        double beta = rho_new / rho;
+        for (long t = 0; t < n; t++) p[t] = r[t] + beta * p[t];
+        rho = rho_new;
+        it++;
+    }
+    free(r); free(p); free(q);
+    if (iters_out) *iters_out = it;
+    return status;
+}

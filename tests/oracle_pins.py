@@ -1,0 +1,314 @@
+"""Pins for the CPU oracle: facts fixed by the paper or by mathematics, each
+computed WITHOUT the oracle's own code path (dense matrices built from
+Kronecker sums, closed-form eigenpairs, the point-Jacobi update of Section
+2.1, the block formula of Section 3 with dense inverses, exact solutions).
+
+Each pin takes an oracle instance and raises AssertionError on failure, so
+the same list can be run against planted-mistake builds of the oracle to show
+that every planted mistake is caught by at least one pin.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from paper_2009_12638_amd import inputs
+
+
+# ----------------------------------------------------------------------
+# independent constructions
+# ----------------------------------------------------------------------
+
+def second_difference(n: int) -> np.ndarray:
+    """1D Dirichlet second-difference matrix tridiag(-1, 2, -1), n x n."""
+    T = 2.0 * np.eye(n)
+    T -= np.eye(n, k=1)
+    T -= np.eye(n, k=-1)
+    return T
+
+
+def dense_laplacian(nx: int, ny: int, nz: int) -> np.ndarray:
+    """7-point operator as the Kronecker sum of 1D second differences; with
+    z fastest in C order, the z factor is the last Kronecker factor."""
+    Ix, Iy, Iz = np.eye(nx), np.eye(ny), np.eye(nz)
+    return (np.kron(np.kron(second_difference(nx), Iy), Iz)
+            + np.kron(np.kron(Ix, second_difference(ny)), Iz)
+            + np.kron(np.kron(Ix, Iy), second_difference(nz)))
+
+
+def block_index_sets(shape, cuts):
+    """Flat index arrays of every block, in the library's block order."""
+    nx, ny, nz = shape
+    idx = np.arange(nx * ny * nz).reshape(shape)
+    sets = []
+    cx, cy, cz = cuts
+    for a in range(len(cx) - 1):
+        for b in range(len(cy) - 1):
+            for c in range(len(cz) - 1):
+                sets.append(idx[cx[a]:cx[a + 1], cy[b]:cy[b + 1], cz[c]:cz[c + 1]].ravel())
+    return sets
+
+
+def point_jacobi_sweep(x: np.ndarray, beff: np.ndarray) -> np.ndarray:
+    """Section 2.1 update x_i <- (b_i - sum_{j != i} a_ij x_j) / a_ii for the
+    7-point stencil: one sixth of (b + the six neighbours), zero outside."""
+    xp = np.pad(x, 1)
+    nb = (xp[2:, 1:-1, 1:-1] + xp[:-2, 1:-1, 1:-1] + xp[1:-1, 2:, 1:-1]
+          + xp[1:-1, :-2, 1:-1] + xp[1:-1, 1:-1, 2:] + xp[1:-1, 1:-1, :-2])
+    return (beff + nb) / 6.0
+
+
+def rel(a, b) -> float:
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+# ----------------------------------------------------------------------
+# pins
+# ----------------------------------------------------------------------
+
+def pin_operator_dense(o):
+    """Matrix-free apply equals the assembled Kronecker-sum matrix."""
+    shape = (5, 4, 6)
+    u = np.random.default_rng(1).standard_normal(shape)
+    A = dense_laplacian(*shape)
+    want = (A @ u.ravel()).reshape(shape)
+    got = o.apply(u)
+    assert np.max(np.abs(got - want)) <= 1e-13, np.max(np.abs(got - want))
+    # symmetry x.Ay == y.Ax on the oracle's own apply
+    v = np.random.default_rng(2).standard_normal(shape)
+    assert abs(np.vdot(u, o.apply(v)) - np.vdot(v, o.apply(u))) < 1e-11
+
+
+def pin_operator_eigen(o):
+    """Closed-form eigenpairs: sin modes with eigenvalue
+    sum over axes of 2 - 2 cos(a pi / (n + 1))."""
+    shape = (7, 5, 9)
+    for (a, b, c) in [(1, 1, 1), (3, 2, 5), (7, 5, 9)]:
+        ix = np.sin(a * np.pi * (np.arange(shape[0]) + 1) / (shape[0] + 1))
+        iy = np.sin(b * np.pi * (np.arange(shape[1]) + 1) / (shape[1] + 1))
+        iz = np.sin(c * np.pi * (np.arange(shape[2]) + 1) / (shape[2] + 1))
+        v = np.einsum("i,j,k->ijk", ix, iy, iz)
+        lam = sum(2 - 2 * np.cos(t * np.pi / (n + 1)) for t, n in zip((a, b, c), shape))
+        assert np.max(np.abs(o.apply(v) - lam * v)) < 1e-12
+
+
+def pin_harmonic_lift(o):
+    """u = x^2 - y^2 + xyz is reproduced exactly by the 7-point stencil when
+    h_x = h_y, so A u_interior must equal b_eff from the boundary values."""
+    shape = (7, 7, 9)
+    u = inputs.harmonic_interior(*shape)
+    beff = o.lift_bc(np.zeros(shape), inputs.harmonic_faces(*shape))
+    err = np.max(np.abs(o.apply(u) - beff))
+    assert err < 1e-13, err
+    # and the residual of the exact solution is at rounding level
+    assert o.residual(beff, u) / np.linalg.norm(beff) < 1e-14
+
+
+def pin_residual_identity(o):
+    """Residual norm equals ||b_eff - A x|| from the dense matrix."""
+    shape = (4, 5, 3)
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(shape)
+    faces = inputs.random_faces(*shape, seed=4)
+    beff = o.lift_bc(b, faces)
+    # independent lifting: each boundary node value enters its neighbour once
+    want_beff = b.copy()
+    want_beff[0, :, :] += faces[0]
+    want_beff[-1, :, :] += faces[1]
+    want_beff[:, 0, :] += faces[2]
+    want_beff[:, -1, :] += faces[3]
+    want_beff[:, :, 0] += faces[4]
+    want_beff[:, :, -1] += faces[5]
+    assert np.max(np.abs(beff - want_beff)) < 1e-15
+    x = rng.standard_normal(shape)
+    want = np.linalg.norm(want_beff.ravel() - dense_laplacian(*shape) @ x.ravel())
+    got = o.residual(beff, x)
+    assert abs(got - want) <= 1e-12 * want
+
+
+def pin_dense_fixed_point(o):
+    """Block Jacobi + CG converges to the dense LU solution (uneven blocks)."""
+    shape = (6, 6, 6)
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal(shape)
+    faces = inputs.random_faces(*shape, seed=6)
+    beff = o.lift_bc(b, faces)
+    xstar = np.linalg.solve(dense_laplacian(*shape), beff.ravel()).reshape(shape)
+    cuts = [np.array([0, 2, 6]), np.array([0, 3, 6]), np.array([0, 4, 6])]
+    st, x, sw, _, hist = o.block_jacobi(beff, np.zeros(shape), cuts, tol=1e-13, m=3,
+                                        max_sweeps=3000)
+    assert st == 0, st
+    assert hist[-1] <= 1e-13
+    assert rel(x, xstar) < 1e-11, rel(x, xstar)
+
+
+def pin_point_jacobi(o):
+    """1x1x1 blocks with one inner CG step are the point-Jacobi iteration of
+    Section 2.1: one CG step on the 1x1 system 6 d = r gives d = r / 6."""
+    shape = (6, 5, 4)
+    rng = np.random.default_rng(7)
+    beff = rng.standard_normal(shape)
+    cuts = [np.arange(n + 1) for n in shape]
+    K = 9
+    st, x, sw, inner, _ = o.block_jacobi(beff, np.zeros(shape), cuts, tol=0.0, m=1,
+                                         max_sweeps=K)
+    assert st == 0 and sw == K
+    ref = np.zeros(shape)
+    for _ in range(K):
+        ref = point_jacobi_sweep(ref, beff)
+    assert rel(x, ref) < 1e-14, rel(x, ref)
+
+
+def pin_exact_block_jacobi(o):
+    """2x2x2 blocks: A_ii has 4 distinct eigenvalues (3,5,7,9), so 4 CG
+    steps solve each block exactly and the sweep is Section 3's
+    X_i = A_ii^{-1}(B_i - sum_j A_ij X_j) with dense inverses."""
+    shape = (4, 6, 4)
+    rng = np.random.default_rng(8)
+    beff = rng.standard_normal(shape)
+    cuts = [np.arange(0, n + 1, 2) for n in shape]
+    A = dense_laplacian(*shape)
+    sets = block_index_sets(shape, cuts)
+    K = 6
+    st, x, sw, _, _ = o.block_jacobi(beff, np.zeros(shape), cuts, tol=0.0, m=4, max_sweeps=K)
+    assert st == 0 and sw == K
+    xr = np.zeros(A.shape[0])
+    bf = beff.ravel()
+    for _ in range(K):
+        xn = xr.copy()
+        for S in sets:
+            rhs = bf[S] - A[S] @ xr + A[np.ix_(S, S)] @ xr[S]
+            xn[S] = np.linalg.solve(A[np.ix_(S, S)], rhs)
+        xr = xn
+    assert rel(x.ravel(), xr) < 1e-12, rel(x.ravel(), xr)
+
+
+def pin_contraction_rate(o):
+    """With exact block solves the residual contracts per sweep by the
+    spectral radius of the block Jacobi iteration matrix I - M^{-1} A
+    (Section 2.3: converges iff that radius is below 1)."""
+    shape = (8, 8, 8)
+    cuts = [np.array([0, 4, 8])] * 3
+    A = dense_laplacian(*shape)
+    M = np.zeros_like(A)
+    for S in block_index_sets(shape, cuts):
+        M[np.ix_(S, S)] = A[np.ix_(S, S)]
+    rho = np.max(np.abs(np.linalg.eigvals(np.eye(A.shape[0]) - np.linalg.solve(M, A))))
+    beff = np.random.default_rng(9).standard_normal(shape)
+    st, x, sw, _, hist = o.block_jacobi(beff, np.zeros(shape), cuts, tol=0.0, m=40,
+                                        max_sweeps=60)
+    ratio = (hist[60] / hist[40]) ** (1.0 / 20)
+    assert abs(ratio - rho) < 2e-3, (ratio, rho)
+    assert rho < 1.0
+
+
+def pin_cg_dense(o):
+    """Global CG reaches the dense solution."""
+    shape = (6, 5, 7)
+    rng = np.random.default_rng(10)
+    beff = rng.standard_normal(shape)
+    xstar = np.linalg.solve(dense_laplacian(*shape), beff.ravel()).reshape(shape)
+    st, x, it, hist = o.cg(beff, np.zeros(shape), tol=1e-14, max_iters=1000)
+    assert st == 0
+    assert rel(x, xstar) < 1e-12, rel(x, xstar)
+    # finite termination: at most n distinct eigenvalues, far fewer than n here
+    assert it <= 210
+
+
+def pin_analytic_solution(o):
+    """32^3 harmonic Laplace problem solved to 1e-12 reproduces u to 1e-10."""
+    w = inputs.workload("laplace32")
+    beff = o.lift_bc(w["b"], w["faces"])
+    st, x, sw, _, hist = o.block_jacobi(beff, np.zeros(w["shape"]), w["cuts"], tol=1e-12,
+                                        m=w["m"], max_sweeps=2000)
+    assert st == 0
+    u = inputs.harmonic_interior(*w["shape"])
+    assert rel(x, u) <= 1e-10, rel(x, u)
+
+
+def pin_async_zero_delay(o):
+    """The bounded-delay model with every delay 0 is the synchronous method,
+    and with delays up to S it still reaches the dense solution."""
+    shape = (8, 8, 8)
+    cuts = [np.array([0, 4, 8])] * 3
+    rng = np.random.default_rng(11)
+    beff = rng.standard_normal(shape)
+    K = 12
+    _, xs, _, _, _ = o.block_jacobi(beff, np.zeros(shape), cuts, tol=0.0, m=5, max_sweeps=K)
+    st, xa, sw, _ = o.block_jacobi_async(beff, np.zeros(shape), cuts, tol=0.0, m=5,
+                                         max_sweeps=K, S=3, delays=np.zeros((K, 8, 6)))
+    assert np.array_equal(xa, xs)
+    xstar = np.linalg.solve(dense_laplacian(*shape), beff.ravel()).reshape(shape)
+    D = inputs.async_delays(400, 8, 2, seed=12)
+    st, xa, sw, hist = o.block_jacobi_async(beff, np.zeros(shape), cuts, tol=1e-12, m=5,
+                                            max_sweeps=400, S=2, delays=D)
+    assert st == 0, st
+    assert rel(xa, xstar) < 1e-10
+
+
+def pin_mixed_reference(o):
+    """FP32 inner solves with FP64 residual/update refine to the FP64 answer."""
+    shape = (16, 16, 16)
+    cuts = [np.array([0, 8, 16])] * 3
+    beff = inputs.poisson_randn(shape, 13)
+    st64, x64, s64, _, _ = o.block_jacobi(beff, np.zeros(shape), cuts, tol=1e-8, m=10)
+    st32, x32, s32, _, h32 = o.block_jacobi(beff, np.zeros(shape), cuts, tol=1e-8, m=10,
+                                            precision=1)
+    assert st64 == 0 and st32 == 0
+    assert h32[-1] <= 1e-8
+    assert rel(x32, x64) < 1e-6, rel(x32, x64)
+
+
+def pin_sweep_semantics(o):
+    """tol <= 0 runs exactly max_sweeps; x = 0 when b_eff = 0; a tol above the
+    starting residual returns at once with zero sweeps."""
+    shape = (4, 4, 4)
+    cuts = [np.array([0, 2, 4])] * 3
+    beff = np.random.default_rng(14).standard_normal(shape)
+    st, x, sw, inner, hist = o.block_jacobi(beff, np.zeros(shape), cuts, tol=0.0, m=2,
+                                            max_sweeps=5)
+    assert st == 0 and sw == 5 and len(hist) == 6
+    assert inner == 5 * 8 * 2
+    st, x, sw, _, _ = o.block_jacobi(np.zeros(shape), np.ones(shape), cuts, tol=1e-8, m=2)
+    assert st == 0 and sw == 0 and not x.any()
+    st, x, sw, _, _ = o.block_jacobi(beff, np.zeros(shape), cuts, tol=2.0, m=2)
+    assert st == 0 and sw == 0
+    st, x, sw, _, _ = o.block_jacobi(beff, np.zeros(shape), cuts, tol=1e-30, m=2,
+                                     max_sweeps=3)
+    assert st == 4 and sw == 3
+
+
+def pin_block_sweep_some(o):
+    """Per-block sweep on listed blocks equals the same blocks of a full sweep."""
+    shape = (8, 6, 10)
+    cuts = [np.array([0, 3, 8]), np.array([0, 6]), np.array([0, 4, 10])]
+    rng = np.random.default_rng(15)
+    beff = rng.standard_normal(shape)
+    x0 = rng.standard_normal(shape)
+    _, x1, _, _, _ = o.block_jacobi(beff, x0, cuts, tol=0.0, m=4, max_sweeps=1)
+    part = o.block_sweep_some(beff, x0, cuts, [1, 2], m=4)
+    sets = block_index_sets(shape, cuts)
+    for b in (1, 2):
+        assert np.array_equal(part.ravel()[sets[b]], x1.ravel()[sets[b]])
+    for b in (0, 3):
+        assert np.array_equal(part.ravel()[sets[b]], x0.ravel()[sets[b]])
+
+
+ALL_PINS = [
+    pin_operator_dense,
+    pin_operator_eigen,
+    pin_harmonic_lift,
+    pin_residual_identity,
+    pin_dense_fixed_point,
+    pin_point_jacobi,
+    pin_exact_block_jacobi,
+    pin_contraction_rate,
+    pin_cg_dense,
+    pin_analytic_solution,
+    pin_async_zero_delay,
+    pin_mixed_reference,
+    pin_sweep_semantics,
+    pin_block_sweep_some,
+]
+
+# fast subset used against planted-mistake builds
+FAST_PINS = [p for p in ALL_PINS if p is not pin_analytic_solution]

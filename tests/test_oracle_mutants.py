@@ -1,0 +1,40 @@
+"""Each planted mistake in the oracle (compiled with ORACLE_MUTANT=n) must be
+caught by at least one pin: a dropped stencil term, a wrong sign in the
+boundary lifting, inverted CG beta and alpha, a wrong sign in the residual
+update, a replace-instead-of-add outer update, a periodic instead of zero
+block boundary, a residual that skips neighbour blocks (no halo), and swapped
+boundary faces."""
+import os
+import tempfile
+
+import pytest
+
+import oracle
+import oracle_pins as P
+
+MUTANTS = {
+    1: "stencil drops the +z neighbour",
+    2: "+z boundary value subtracted",
+    3: "CG beta inverted",
+    4: "CG residual update sign",
+    5: "outer update replaces x",
+    6: "block stencil wraps periodically",
+    7: "outer residual without neighbour blocks",
+    8: "-x and -y faces exchanged",
+    10: "CG alpha inverted",
+}
+
+
+@pytest.mark.filterwarnings("ignore::RuntimeWarning")
+@pytest.mark.parametrize("mutant", sorted(MUTANTS), ids=lambda m: f"m{m}")
+def test_mutant_is_caught(mutant):
+    with tempfile.TemporaryDirectory() as d:
+        path = oracle.build(mutant, out=os.path.join(d, f"liboracle_mut{mutant}.so"))
+        o = oracle.Oracle(path)
+        caught = []
+        for pin in P.FAST_PINS:
+            try:
+                pin(o)
+            except Exception:
+                caught.append(pin.__name__)
+        assert caught, f"mutant {mutant} ({MUTANTS[mutant]}) passed every pin"
