@@ -23,9 +23,12 @@
  *     from the boundary faces held by the handle and is moved to the
  *     right-hand side: b_eff = b + sum over boundary neighbours of g.
  *   - All vector arguments are FP64 DEVICE pointers (for instance the
- *     data_ptr() of a contiguous torch tensor on the GPU), 8-byte aligned,
+ *     data_ptr() of a contiguous torch tensor on the GPU), 16-byte aligned,
  *     length nx*ny*nz, owned by the caller.  Nothing is retained after a
- *     call returns.
+ *     call returns.  A pointer that is not device memory, or whose
+ *     allocation ends before nx*ny*nz doubles, is rejected (MS_ERR_ARG);
+ *     a piece of a larger allocation (a caching allocator's block) cannot
+ *     be told apart from a whole buffer, so its size is the caller's duty.
  *   - Relative residual = ||b_eff - A x||_2 / ||b_eff||_2 in FP64.
  *   - Every call returns an ms_status; nothing aborts or prints.  After a
  *     failure ms_last_error(handle) describes it.
@@ -62,9 +65,10 @@ typedef struct {
 /* Block partition (Section 3: the unknowns split into blocks X_i): a tensor
  * product of per-axis cuts.  gx,gy,gz = blocks per axis.  cuts_x is a HOST
  * array of gx+1 increasing offsets 0 = c[0] < ... < c[gx] = nx (likewise y,
- * z); NULL means a uniform split, which requires nx % gx == 0.  Every block
- * edge must be a multiple of 2 and at most 1024 points; block (bi,bj,bk) has
- * number (bi*gy + bj)*gz + bk. */
+ * z); NULL means a uniform split, which requires nx % gx == 0.  Block
+ * edges may be any size >= 1 (kernels use 16-byte accesses when nz and every
+ * z cut are multiples of 4, or 2); block (bi,bj,bk) has number
+ * (bi*gy + bj)*gz + bk. */
 typedef struct {
     int32_t gx, gy, gz;
     const int32_t *cuts_x, *cuts_y, *cuts_z;

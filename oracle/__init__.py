@@ -84,7 +84,12 @@ class Oracle:
         L.or_block_jacobi_async.restype = C.c_int
         L.or_cg.argtypes = [C.c_long] * 3 + [_dp, _dp, C.c_double, C.c_int, _dp, _ip]
         L.or_cg.restype = C.c_int
+        L.or_num_threads.argtypes = []
+        L.or_num_threads.restype = C.c_int
         self.L = L
+
+    def num_threads(self) -> int:
+        return int(self.L.or_num_threads())
 
     # ---- helpers -----------------------------------------------------
     @staticmethod

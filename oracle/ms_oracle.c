@@ -42,6 +42,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #ifndef ORACLE_MUTANT
 #define ORACLE_MUTANT 0
@@ -55,6 +58,16 @@
 #define OR_ARG 1
 
 #define IDX(i, j, k) (((long)(i) * ny + (j)) * nz + (k))
+
+/* threads an OpenMP region of the oracle uses (1 without OpenMP) */
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------ */
 /* Operator and right-hand side (Section 2.1: 7-point Laplace stencil) */

@@ -1,0 +1,713 @@
+// Host side of libms: handle, argument checks, device buffers and the sweep
+// scheduler for the synchronous two-stage multisplitting solve.
+//
+// Sweep schedule (synchronous mode).  Blocks are processed in groups of
+// consecutive blocks whose inner CG vectors (r, d and two p buffers) fit in
+// the on-package cache; every group reuses the same inner buffers.  For one
+// group: residual (halo reads from x_old), then m x {stencil, update}; the
+// last update writes x_new = x_old + d into the second outer buffer, so all
+// groups of a sweep read only x_old (Section 3: X_i^(k) uses only sweep k-1
+// values).  After all groups a one-workgroup kernel adds the residual
+// partials of x_old in a fixed order and decides convergence on the device.
+// Because the test is on x_old, a converged solve returns x_old and the
+// sweep just computed is discarded (the two outer buffers make that free).
+// The host reads the device flag once per batch of sweeps; kernels enqueued
+// after convergence exit at once.
+#include "ms.h"
+#include "ms_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using ms::BlockInfo;
+using ms::Ctrl;
+using ms::Faces;
+using ms::Geom;
+
+namespace {
+
+constexpr int kTxMin = 4;             // smallest x chunk a tiling may use
+constexpr int kHistoryCap = 1 << 20;  // device residual history entries
+constexpr int kMaxEvents = 4096;      // profile: event pairs per batch
+
+std::string g_create_error;
+
+struct Group {
+    int b0, b1;     // blocks [b0, b1)
+    int t0, t1;     // tiles [t0, t1)
+    long long off;  // packed offset of block b0
+};
+
+}  // namespace
+
+struct ms_handle {
+    long long nx = 0, ny = 0, nz = 0, N = 0;
+    int gx = 0, gy = 0, gz = 0, nblocks = 0;
+    std::vector<int> cx, cy, cz;
+    int vzmax = 1;              // widest vector every z cut and nz allow
+    // current tiling
+    int cur_vz = 0, cur_tx = 0, ntiles = 0;
+    std::vector<BlockInfo> blocks_h;
+    int tiles_cap = 0;
+    // device memory
+    BlockInfo *blocks_d = nullptr;
+    int *tile_block_d = nullptr;
+    double *x1 = nullptr;
+    void *r = nullptr, *d = nullptr, *p0 = nullptr, *p1 = nullptr;
+    double *part64 = nullptr;
+    void *partT = nullptr, *psig = nullptr, *prhoA = nullptr, *prhoB = nullptr;
+    int *active = nullptr;
+    Ctrl *ctrl = nullptr;
+    double *history_d = nullptr;
+    double *faces_d[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    double *scal_d = nullptr;
+    // profiling
+    std::vector<hipEvent_t> ev;
+    std::vector<int> ev_class;
+    int ev_used = 0;
+    bool profiling = false;
+    std::string err;
+};
+
+namespace {
+
+ms_status fail(ms_handle *h, ms_status s, const std::string &msg) {
+    if (h) h->err = msg;
+    else g_create_error = msg;
+    if (getenv("MS_LOG")) fprintf(stderr, "[libms] %s: %s\n", ms_status_string(s), msg.c_str());
+    return s;
+}
+
+ms_status hip_fail(ms_handle *h, hipError_t e, const char *what) {
+    return fail(h, e == hipErrorOutOfMemory ? MS_ERR_NOMEM : MS_ERR_HIP,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(h, call)                                   \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return hip_fail(h, e_, #call); \
+    } while (0)
+
+bool valid_cuts(const std::vector<int> &c, long long n) {
+    if (c.size() < 2 || c.front() != 0 || c.back() != n) return false;
+    for (size_t t = 0; t + 1 < c.size(); t++)
+        if (c[t + 1] <= c[t]) return false;
+    return true;
+}
+
+// A device allocation that covers [p, p + bytes).
+bool dev_range_ok(const void *p, size_t bytes) {
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    if (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged) return false;
+    void *base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, const_cast<void *>(p)) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return (const char *)p + bytes <= (const char *)base + size;
+}
+
+// Build the tile table for vector width vz and x chunk tx.
+ms_status set_tiling(ms_handle *h, int vz, int tx, hipStream_t st) {
+    if (h->cur_vz == vz && h->cur_tx == tx) return MS_OK;
+    std::vector<int> tb;
+    h->blocks_h.resize(h->nblocks);
+    long long off = 0;
+    int tile = 0;
+    for (int bi = 0; bi < h->gx; bi++)
+        for (int bj = 0; bj < h->gy; bj++)
+            for (int bk = 0; bk < h->gz; bk++) {
+                const int b = (bi * h->gy + bj) * h->gz + bk;
+                BlockInfo &B = h->blocks_h[b];
+                B.i0 = h->cx[bi]; B.j0 = h->cy[bj]; B.k0 = h->cz[bk];
+                B.bx = h->cx[bi + 1] - B.i0;
+                B.by = h->cy[bj + 1] - B.j0;
+                B.bz = h->cz[bk + 1] - B.k0;
+                B.off = off;
+                const long long P = (long long)B.by * B.bz;
+                B.nplane = (int)((P + (long long)ms::kThreads * vz - 1) / ((long long)ms::kThreads * vz));
+                const int nxc = (B.bx + tx - 1) / tx;
+                B.ntiles = B.nplane * nxc;
+                B.tile0 = tile;
+                B.pad_ = 0;
+                for (int t = 0; t < B.ntiles; t++) tb.push_back(b);
+                tile += B.ntiles;
+                off += (long long)B.bx * P;
+            }
+    if (tile > h->tiles_cap) return fail(h, MS_ERR_ARG, "tiling exceeds its table");
+    HIPCHK(h, hipMemcpyAsync(h->blocks_d, h->blocks_h.data(), sizeof(BlockInfo) * h->nblocks,
+                             hipMemcpyHostToDevice, st));
+    HIPCHK(h, hipMemcpyAsync(h->tile_block_d, tb.data(), sizeof(int) * tb.size(),
+                             hipMemcpyHostToDevice, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    h->ntiles = tile;
+    h->cur_vz = vz;
+    h->cur_tx = tx;
+    return MS_OK;
+}
+
+Geom geom(const ms_handle *h) {
+    Geom g;
+    g.nx = h->nx; g.ny = h->ny; g.nz = h->nz;
+    g.blocks = h->blocks_d;
+    g.tile_block = h->tile_block_d;
+    g.tx = h->cur_tx;
+    g.nblocks = h->nblocks;
+    return g;
+}
+
+Faces faces(const ms_handle *h) {
+    Faces f;
+    for (int t = 0; t < 6; t++) f.f[t] = h->faces_d[t];
+    return f;
+}
+
+ms_status copy_bc(ms_handle *h, const ms_bc *bc) {
+    const long long sz[6] = {h->ny * h->nz, h->ny * h->nz, h->nx * h->nz,
+                             h->nx * h->nz, h->nx * h->ny, h->nx * h->ny};
+    for (int t = 0; t < 6; t++) {
+        const double *src = bc ? bc->face[t] : nullptr;
+        if (src && !dev_range_ok(src, sizeof(double) * sz[t]))
+            return fail(h, MS_ERR_ARG, "boundary face " + std::to_string(t) +
+                                           " is not a device buffer of the face's size");
+    }
+    for (int t = 0; t < 6; t++) {
+        const double *src = bc ? bc->face[t] : nullptr;
+        if (!src) {
+            if (h->faces_d[t]) { (void)hipFree(h->faces_d[t]); h->faces_d[t] = nullptr; }
+            continue;
+        }
+        if (!h->faces_d[t]) HIPCHK(h, hipMalloc(&h->faces_d[t], sizeof(double) * sz[t]));
+        HIPCHK(h, hipMemcpy(h->faces_d[t], src, sizeof(double) * sz[t], hipMemcpyDeviceToDevice));
+    }
+    return MS_OK;
+}
+
+void free_all(ms_handle *h) {
+    void *ps[] = {h->blocks_d, h->tile_block_d, h->x1, h->r, h->d, h->p0, h->p1, h->part64,
+                  h->partT, h->psig, h->prhoA, h->prhoB, h->active, h->ctrl, h->history_d,
+                  h->scal_d};
+    for (void *p : ps)
+        if (p) (void)hipFree(p);
+    for (int t = 0; t < 6; t++)
+        if (h->faces_d[t]) (void)hipFree(h->faces_d[t]);
+    for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+}
+
+// ---- profiling -------------------------------------------------------
+
+struct Prof {
+    ms_handle *h;
+    hipStream_t st;
+    int cls;
+    int slot;
+    Prof(ms_handle *h_, hipStream_t s, int c) : h(h_), st(s), cls(c), slot(-1) {
+        if (!h->profiling || h->ev_used + 2 > (int)h->ev.size()) return;
+        slot = h->ev_used;
+        h->ev_used += 2;
+        h->ev_class[slot] = cls;
+        (void)hipEventRecord(h->ev[slot], st);
+    }
+    ~Prof() {
+        if (slot >= 0) (void)hipEventRecord(h->ev[slot + 1], st);
+    }
+};
+
+void prof_collect(ms_handle *h, ms_stats *stats) {
+    if (!h->profiling) return;
+    for (int s = 0; s + 1 < h->ev_used; s += 2) {
+        float ms_ = 0.f;
+        if (hipEventElapsedTime(&ms_, h->ev[s], h->ev[s + 1]) == hipSuccess && stats) {
+            stats->kernel_ms[h->ev_class[s]] += ms_;
+            stats->kernel_launches[h->ev_class[s]] += 1;
+        }
+    }
+    h->ev_used = 0;
+}
+
+ms_status prof_begin(ms_handle *h, bool on) {
+    h->profiling = on;
+    h->ev_used = 0;
+    if (on && h->ev.empty()) {
+        h->ev.resize(2 * kMaxEvents);
+        h->ev_class.assign(2 * kMaxEvents, 0);
+        for (auto &e : h->ev) HIPCHK(h, hipEventCreate(&e));
+    }
+    return MS_OK;
+}
+
+// ---- solve pieces -------------------------------------------------------
+
+template <typename T>
+struct Bufs {
+    T *r, *d, *p[2];
+    T *pT, *psig, *prA, *prB;
+};
+
+template <typename T>
+Bufs<T> bufs(ms_handle *h) {
+    Bufs<T> B;
+    B.r = (T *)h->r;
+    B.d = (T *)h->d;
+    B.p[0] = (T *)h->p0;
+    B.p[1] = (T *)h->p1;
+    B.pT = sizeof(T) == sizeof(double) ? (T *)h->part64 : (T *)h->partT;
+    B.psig = (T *)h->psig;
+    B.prA = (T *)h->prhoA;
+    B.prB = (T *)h->prhoB;
+    return B;
+}
+
+std::vector<Group> make_groups(const ms_handle *h, long long cap_cells) {
+    std::vector<Group> gs;
+    int b = 0;
+    while (b < h->nblocks) {
+        Group g;
+        g.b0 = b;
+        g.off = h->blocks_h[b].off;
+        long long cells = 0;
+        do {
+            const BlockInfo &B = h->blocks_h[b];
+            cells += (long long)B.bx * B.by * B.bz;
+            b++;
+        } while (b < h->nblocks &&
+                 cells + (long long)h->blocks_h[b].bx * h->blocks_h[b].by * h->blocks_h[b].bz <=
+                     cap_cells);
+        g.b1 = b;
+        g.t0 = h->blocks_h[g.b0].tile0;
+        g.t1 = h->blocks_h[g.b1 - 1].tile0 + h->blocks_h[g.b1 - 1].ntiles;
+        gs.push_back(g);
+    }
+    return gs;
+}
+
+// Enqueue one sweep from xa into xb (or, final_only, just the residual check
+// of xa).
+template <typename T>
+ms_status enqueue_sweep(ms_handle *h, const std::vector<Group> &groups, const double *b,
+                        const double *xa, double *xb, double tol, int m, double inner_tol,
+                        bool final_only, hipStream_t st) {
+    const Geom g = geom(h);
+    const int vz = h->cur_vz;
+    Bufs<T> B = bufs<T>(h);
+    const Faces F = faces(h);
+    for (const Group &G : groups) {
+        {
+            Prof p(h, st, MS_K_RESID);
+            HIPCHK(h, ms::launch_resid<T>(g, vz, G.t0, G.t1, G.off, b, xa, F,
+                                          final_only ? nullptr : B.r, h->part64, B.pT, h->ctrl,
+                                          st));
+        }
+        if (final_only) continue;
+        T *prho[3] = {B.pT, B.prA, B.prB};
+        for (int j = 0; j < m; j++) {
+            T *cur = j == 0 ? prho[0] : (j % 2 ? prho[1] : prho[2]);
+            T *prev = j == 0 ? prho[0] : (j == 1 ? prho[0] : (j % 2 ? prho[2] : prho[1]));
+            T *next = (j + 1) % 2 ? prho[1] : prho[2];
+            T *pold = B.p[(j + 1) % 2];
+            T *pnew = B.p[j % 2];
+            const bool last = j == m - 1;
+            {
+                Prof p(h, st, MS_K_STENCIL);
+                HIPCHK(h, ms::launch_stencil<T>(g, vz, G.t0, G.t1, G.off, B.r, pold, pnew,
+                                                B.psig, cur, prev, prho[0], h->active, j,
+                                                inner_tol, h->ctrl, st));
+            }
+            {
+                Prof p(h, st, last ? MS_K_FINAL : MS_K_UPDATE);
+                HIPCHK(h, ms::launch_update<T>(g, vz, G.t0, G.t1, G.off, B.r, pnew, B.d,
+                                               B.psig, cur, next, h->active, j, last ? 1 : 0,
+                                               xa, xb, h->ctrl, st));
+            }
+        }
+    }
+    {
+        Prof p(h, st, MS_K_CHECK);
+        HIPCHK(h, ms::launch_check(h->part64, h->ntiles, tol, final_only ? 1 : 0, h->history_d,
+                                   kHistoryCap, h->ctrl, st));
+    }
+    return MS_OK;
+}
+
+__global__ void k_ctrl_init(Ctrl *c) {
+    if (threadIdx.x == 0) {
+        c->done = 0; c->status = 0; c->sweep = 0; c->final_sweep = 0;
+        c->nbeff = 0.0; c->res0 = 0.0; c->last_res = 0.0; c->inner_iters = 0ull; c->inner_snap = 0ull;
+        c->stop = 0; c->max_stale = 0; c->work_items = 0ull;
+    }
+}
+
+__global__ void k_fill_zero(double *x, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        x[i] = 0.0;
+}
+
+ms_status zero_vec(ms_handle *h, double *x, long long n, hipStream_t st) {
+    long long grid = std::min<long long>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)std::max<long long>(grid, 1)), dim3(256), 0,
+                       st, x, n);
+    HIPCHK(h, hipGetLastError());
+    return MS_OK;
+}
+
+// ||b_eff|| into ctrl->nbeff and *out (host); resets the control block.
+template <typename T>
+ms_status beff_norm(ms_handle *h, const double *b, hipStream_t st, double *out) {
+    hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, st, h->ctrl);
+    HIPCHK(h, hipGetLastError());
+    const Geom g = geom(h);
+    Bufs<T> B = bufs<T>(h);
+    HIPCHK(h, ms::launch_resid<T>(g, h->cur_vz, 0, h->ntiles, 0, b, nullptr, faces(h), nullptr,
+                                  h->part64, B.pT, nullptr, st));
+    HIPCHK(h, ms::launch_norm(h->part64, h->ntiles, h->ctrl, st));
+    Ctrl c;
+    HIPCHK(h, hipMemcpyAsync(&c, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    *out = c.nbeff;
+    return MS_OK;
+}
+
+int auto_tx(const ms_handle *h, int bx_min) {
+    (void)h;
+    return std::max(kTxMin, std::min(16, bx_min));
+}
+
+template <typename T>
+ms_status solve_sync(ms_handle *h, const double *b, double *x, double tol, int m,
+                     const ms_opts &o, ms_stats *stats, hipStream_t st) {
+    const int vz = std::min(h->vzmax, (int)(16 / sizeof(T)));
+    int bx_min = 1 << 30;
+    for (int t = 0; t + 1 < (int)h->cx.size(); t++) bx_min = std::min(bx_min, h->cx[t + 1] - h->cx[t]);
+    const int tx = o.x_chunk > 0 ? std::max(kTxMin, o.x_chunk) : auto_tx(h, bx_min);
+    ms_status s = set_tiling(h, vz, tx, st);
+    if (s != MS_OK) return s;
+    double nbeff = 0.0;
+    s = beff_norm<T>(h, b, st, &nbeff);
+    if (s != MS_OK) return s;
+    if (!std::isfinite(nbeff)) return fail(h, MS_ERR_NONFINITE, "b_eff is not finite");
+    if (nbeff == 0.0) {
+        s = zero_vec(h, x, h->N, st);
+        if (s != MS_OK) return s;
+        HIPCHK(h, hipStreamSynchronize(st));
+        if (stats) { stats->sweeps = 0; stats->rel_residual = 0.0; }
+        if (stats && stats->history && stats->history_cap > 0) {
+            stats->history[0] = 0.0;
+            stats->history_len = 1;
+        }
+        return MS_OK;
+    }
+    // groups: inner vectors r, d, p0, p1 of one group sized for the cache
+    long long cap_cells;
+    if (o.group_blocks < 0) cap_cells = h->N;
+    else if (o.group_blocks > 0) {
+        long long mx = 0;
+        for (const BlockInfo &B : h->blocks_h) mx = std::max(mx, (long long)B.bx * B.by * B.bz);
+        cap_cells = mx * o.group_blocks;
+    } else {
+        cap_cells = (160ll << 20) / (4 * (long long)sizeof(T));
+    }
+    const std::vector<Group> groups = make_groups(h, cap_cells);
+    const long long cells_per_sweep = h->N * (long long)m;
+    int batch = o.check_every > 0 ? o.check_every
+                                  : (int)std::max(2ll, std::min(256ll, (1ll << 31) / std::max(1ll, cells_per_sweep)));
+    s = prof_begin(h, o.profile != 0);
+    if (s != MS_OK) return s;
+    double *X[2] = {x, h->x1};
+    Ctrl c;
+    memset(&c, 0, sizeof(c));
+    int next = 0;   // next sweep to enqueue
+    for (;;) {
+        const int nb = std::min(batch, o.max_sweeps - next);
+        for (int q = 0; q < nb; q++, next++) {
+            s = enqueue_sweep<T>(h, groups, b, X[next % 2], X[(next + 1) % 2], tol, m, o.inner_tol,
+                                 false, st);
+            if (s != MS_OK) return s;
+        }
+        if (next == o.max_sweeps) {
+            s = enqueue_sweep<T>(h, groups, b, X[next % 2], nullptr, tol, m, o.inner_tol, true, st);
+            if (s != MS_OK) return s;
+        }
+        HIPCHK(h, hipMemcpyAsync(&c, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+        HIPCHK(h, hipStreamSynchronize(st));
+        prof_collect(h, stats);
+        if (c.done) break;
+        if (next >= o.max_sweeps) return fail(h, MS_ERR_HIP, "device did not finish the solve");
+    }
+    if (c.final_sweep % 2 == 1)
+        HIPCHK(h, hipMemcpyAsync(x, h->x1, sizeof(double) * h->N, hipMemcpyDeviceToDevice, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    if (stats) {
+        stats->sweeps = c.final_sweep;
+        stats->inner_iters = (int64_t)c.inner_snap;
+        stats->rel_residual = c.last_res;
+        if (stats->history && stats->history_cap > 0) {
+            const int n = std::min(std::min(stats->history_cap, kHistoryCap), c.final_sweep + 1);
+            HIPCHK(h, hipMemcpy(stats->history, h->history_d, sizeof(double) * n,
+                                hipMemcpyDeviceToHost));
+            stats->history_len = n;
+        }
+    }
+    switch (c.status) {
+        case 0: return MS_OK;
+        case 4: return fail(h, MS_ERR_NOT_CONVERGED, "max_sweeps reached above tol");
+        case 5: return fail(h, MS_ERR_NONFINITE, "residual became non-finite");
+        case 6: return fail(h, MS_ERR_DIVERGED, "residual grew by 1e6");
+        default: return fail(h, MS_ERR_HIP, "unknown device status");
+    }
+}
+
+}  // namespace
+
+// ======================================================================
+// C ABI
+// ======================================================================
+
+extern "C" {
+
+void ms_default_opts(ms_opts *o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->max_sweeps = 100000;
+    o->inner_tol = 0.0;
+    o->staleness = 2;
+    o->precision = MS_FP64;
+    o->stream = nullptr;
+    o->check_every = 0;
+    o->group_blocks = 0;
+    o->x_chunk = 0;
+    o->profile = 0;
+    o->use_graph = 1;
+}
+
+const char *ms_status_string(ms_status s) {
+    switch (s) {
+        case MS_OK: return "MS_OK";
+        case MS_ERR_ARG: return "MS_ERR_ARG";
+        case MS_ERR_HIP: return "MS_ERR_HIP";
+        case MS_ERR_NOMEM: return "MS_ERR_NOMEM";
+        case MS_ERR_NOT_CONVERGED: return "MS_ERR_NOT_CONVERGED";
+        case MS_ERR_NONFINITE: return "MS_ERR_NONFINITE";
+        case MS_ERR_DIVERGED: return "MS_ERR_DIVERGED";
+        case MS_ERR_UNSUPPORTED: return "MS_ERR_UNSUPPORTED";
+    }
+    return "MS_ERR_UNKNOWN";
+}
+
+const char *ms_last_error(const ms_handle *h) {
+    return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+const char *ms_version(void) { return "libms 0.1.0 (gfx950)"; }
+
+ms_status ms_create(const ms_grid *grid, const ms_blocks *blocks, const ms_bc *bc,
+                    ms_handle **out) {
+    if (!out) return fail(nullptr, MS_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!grid || !blocks) return fail(nullptr, MS_ERR_ARG, "grid or blocks is NULL");
+    if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1)
+        return fail(nullptr, MS_ERR_ARG, "grid sizes must be >= 1");
+    if (grid->nx > (1 << 20) || grid->ny > (1 << 20) || grid->nz > (1 << 20) ||
+        (double)grid->nx * grid->ny * grid->nz > 4.0e10)
+        return fail(nullptr, MS_ERR_ARG, "grid too large");
+    if (blocks->gx < 1 || blocks->gy < 1 || blocks->gz < 1)
+        return fail(nullptr, MS_ERR_ARG, "block counts must be >= 1");
+    ms_handle tmp;
+    tmp.nx = grid->nx; tmp.ny = grid->ny; tmp.nz = grid->nz;
+    tmp.N = tmp.nx * tmp.ny * tmp.nz;
+    tmp.gx = blocks->gx; tmp.gy = blocks->gy; tmp.gz = blocks->gz;
+    const int32_t *cuts[3] = {blocks->cuts_x, blocks->cuts_y, blocks->cuts_z};
+    const long long ns[3] = {tmp.nx, tmp.ny, tmp.nz};
+    const int gs[3] = {tmp.gx, tmp.gy, tmp.gz};
+    std::vector<int> *dst[3] = {&tmp.cx, &tmp.cy, &tmp.cz};
+    for (int a = 0; a < 3; a++) {
+        if (gs[a] > ns[a]) return fail(nullptr, MS_ERR_ARG, "more blocks than points on an axis");
+        dst[a]->resize(gs[a] + 1);
+        if (cuts[a]) {
+            for (int t = 0; t <= gs[a]; t++) (*dst[a])[t] = cuts[a][t];
+        } else {
+            if (ns[a] % gs[a]) return fail(nullptr, MS_ERR_ARG, "uniform split needs n % g == 0");
+            for (int t = 0; t <= gs[a]; t++) (*dst[a])[t] = (int)(ns[a] / gs[a] * t);
+        }
+        if (!valid_cuts(*dst[a], ns[a]))
+            return fail(nullptr, MS_ERR_ARG, "cuts must increase strictly from 0 to n");
+    }
+    if ((long long)tmp.gx * tmp.gy * tmp.gz > (1 << 22))
+        return fail(nullptr, MS_ERR_ARG, "too many blocks");
+    tmp.nblocks = tmp.gx * tmp.gy * tmp.gz;
+    // vector width: every z cut and nz divisible
+    tmp.vzmax = 1;
+    for (int w : {4, 2}) {
+        bool ok = tmp.nz % w == 0;
+        for (int c : tmp.cz) ok = ok && (c % w == 0);
+        if (ok) { tmp.vzmax = w; break; }
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(nullptr, MS_ERR_HIP, std::string("no HIP device: ") + hipGetErrorString(e));
+    ms_handle *h = new ms_handle(std::move(tmp));
+    // tile table capacity: narrowest vector, smallest x chunk
+    long long cap = 0;
+    for (int bi = 0; bi < h->gx; bi++)
+        for (int bj = 0; bj < h->gy; bj++)
+            for (int bk = 0; bk < h->gz; bk++) {
+                const long long P = (long long)(h->cy[bj + 1] - h->cy[bj]) * (h->cz[bk + 1] - h->cz[bk]);
+                const long long np = (P + ms::kThreads - 1) / ms::kThreads;
+                const long long nxc = (h->cx[bi + 1] - h->cx[bi] + kTxMin - 1) / kTxMin;
+                cap += np * nxc;
+            }
+    if (cap > (1ll << 30)) { delete h; return fail(nullptr, MS_ERR_ARG, "too many tiles"); }
+    h->tiles_cap = (int)cap;
+    const size_t vb = sizeof(double) * (size_t)h->N;
+    const size_t tb = sizeof(double) * (size_t)h->tiles_cap;
+    struct A { void **p; size_t n; } allocs[] = {
+        {(void **)&h->blocks_d, sizeof(BlockInfo) * (size_t)h->nblocks},
+        {(void **)&h->tile_block_d, sizeof(int) * (size_t)h->tiles_cap},
+        {(void **)&h->x1, vb}, {&h->r, vb}, {&h->d, vb}, {&h->p0, vb}, {&h->p1, vb},
+        {(void **)&h->part64, tb}, {&h->partT, tb}, {&h->psig, tb}, {&h->prhoA, tb},
+        {&h->prhoB, tb},
+        {(void **)&h->active, sizeof(int) * (size_t)h->nblocks},
+        {(void **)&h->ctrl, sizeof(Ctrl)},
+        {(void **)&h->history_d, sizeof(double) * (size_t)kHistoryCap},
+        {(void **)&h->scal_d, 64},
+    };
+    for (auto &a : allocs) {
+        e = hipMalloc(a.p, a.n);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            free_all(h);
+            delete h;
+            return fail(nullptr, e == hipErrorOutOfMemory ? MS_ERR_NOMEM : MS_ERR_HIP,
+                        std::string("device allocation failed: ") + hipGetErrorString(e));
+        }
+    }
+    ms_status s = copy_bc(h, bc);
+    if (s == MS_OK) s = set_tiling(h, h->vzmax >= 2 ? 2 : 1, 16, nullptr);
+    if (s != MS_OK) {
+        g_create_error = h->err;
+        free_all(h);
+        delete h;
+        return s;
+    }
+    *out = h;
+    return MS_OK;
+}
+
+ms_status ms_set_bc(ms_handle *h, const ms_bc *bc) {
+    if (!h) return fail(nullptr, MS_ERR_ARG, "handle is NULL");
+    return copy_bc(h, bc);
+}
+
+void ms_destroy(ms_handle *h) {
+    if (!h) return;
+    (void)hipDeviceSynchronize();
+    free_all(h);
+    delete h;
+}
+
+static ms_status check_vec(ms_handle *h, const void *p, const char *name) {
+    if (!p) return fail(h, MS_ERR_ARG, std::string(name) + " is NULL");
+    if ((uintptr_t)p % 16) return fail(h, MS_ERR_ARG, std::string(name) + " must be 16-byte aligned");
+    if (!dev_range_ok(p, sizeof(double) * (size_t)h->N))
+        return fail(h, MS_ERR_ARG, std::string(name) + " is not a device buffer of nx*ny*nz doubles");
+    return MS_OK;
+}
+
+ms_status ms_solve(ms_handle *h, const double *b, double *x, double tol, int32_t inner_iters,
+                   ms_mode mode, const ms_opts *opts, ms_stats *stats) {
+    const auto t_start = std::chrono::steady_clock::now();
+    if (!h) return fail(nullptr, MS_ERR_ARG, "handle is NULL");
+    ms_opts o;
+    ms_default_opts(&o);
+    if (opts) o = *opts;
+    ms_status s = check_vec(h, b, "b");
+    if (s != MS_OK) return s;
+    s = check_vec(h, x, "x");
+    if (s != MS_OK) return s;
+    const char *bb = (const char *)b, *xx = (const char *)x;
+    const size_t bytes = sizeof(double) * (size_t)h->N;
+    if (bb < xx + bytes && xx < bb + bytes) return fail(h, MS_ERR_ARG, "b and x overlap");
+    if (inner_iters < 1) return fail(h, MS_ERR_ARG, "inner_iters must be >= 1");
+    if (o.max_sweeps < 0) return fail(h, MS_ERR_ARG, "max_sweeps must be >= 0");
+    if (o.staleness < 0) return fail(h, MS_ERR_ARG, "staleness must be >= 0");
+    if (std::isnan(tol) || !(o.inner_tol >= 0.0) || !std::isfinite(o.inner_tol))
+        return fail(h, MS_ERR_ARG, "tol or inner_tol invalid");
+    if (o.precision != MS_FP64 && o.precision != MS_MIXED)
+        return fail(h, MS_ERR_ARG, "unknown precision");
+    if (mode != MS_SYNC && mode != MS_ASYNC) return fail(h, MS_ERR_ARG, "unknown mode");
+    if (stats) {
+        double *hist = stats->history;
+        const int cap = stats->history_cap;
+        memset(stats, 0, sizeof(*stats));
+        stats->history = hist;
+        stats->history_cap = cap;
+    }
+    hipStream_t st = (hipStream_t)o.stream;
+    if (mode == MS_ASYNC) return fail(h, MS_ERR_UNSUPPORTED, "asynchronous mode not built yet");
+    s = o.precision == MS_FP64 ? solve_sync<double>(h, b, x, tol, inner_iters, o, stats, st)
+                               : solve_sync<float>(h, b, x, tol, inner_iters, o, stats, st);
+    if (stats)
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    return s;
+}
+
+ms_status ms_residual(ms_handle *h, const double *b, const double *x, double *rel_out,
+                      double *abs_out, void *stream) {
+    if (!h) return fail(nullptr, MS_ERR_ARG, "handle is NULL");
+    if (!rel_out) return fail(h, MS_ERR_ARG, "rel_out is NULL");
+    ms_status s = check_vec(h, b, "b");
+    if (s != MS_OK) return s;
+    s = check_vec(h, x, "x");
+    if (s != MS_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    s = set_tiling(h, std::min(h->vzmax, 2), h->cur_tx ? h->cur_tx : 16, st);
+    if (s != MS_OK) return s;
+    double nbeff = 0.0;
+    s = beff_norm<double>(h, b, st, &nbeff);
+    if (s != MS_OK) return s;
+    const Geom g = geom(h);
+    HIPCHK(h, ms::launch_resid<double>(g, h->cur_vz, 0, h->ntiles, 0, b, x, faces(h), nullptr,
+                                       h->part64, h->part64, nullptr, st));
+    HIPCHK(h, ms::launch_sum(h->part64, h->ntiles, h->scal_d, st));
+    double ss = 0.0;
+    HIPCHK(h, hipMemcpyAsync(&ss, h->scal_d, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    const double a = std::sqrt(ss);
+    if (abs_out) *abs_out = a;
+    *rel_out = nbeff > 0.0 ? a / nbeff : 0.0;
+    return MS_OK;
+}
+
+ms_status ms_apply(ms_handle *h, const double *u, double *y, void *stream) {
+    if (!h) return fail(nullptr, MS_ERR_ARG, "handle is NULL");
+    ms_status s = check_vec(h, u, "u");
+    if (s != MS_OK) return s;
+    s = check_vec(h, y, "y");
+    if (s != MS_OK) return s;
+    const char *uu = (const char *)u, *yy = (const char *)y;
+    const size_t bytes = sizeof(double) * (size_t)h->N;
+    if (uu < yy + bytes && yy < uu + bytes) return fail(h, MS_ERR_ARG, "u and y overlap");
+    HIPCHK(h, ms::launch_apply(h->nx, h->ny, h->nz, u, y, (hipStream_t)stream));
+    return MS_OK;
+}
+
+ms_status ms_cg(ms_handle *h, const double *b, double *x, double tol, int32_t max_iters,
+                const ms_opts *opts, ms_stats *stats) {
+    (void)b; (void)x; (void)tol; (void)max_iters; (void)opts; (void)stats;
+    if (!h) return fail(nullptr, MS_ERR_ARG, "handle is NULL");
+    return fail(h, MS_ERR_UNSUPPORTED, "global CG not built yet");
+}
+
+}  // extern "C"

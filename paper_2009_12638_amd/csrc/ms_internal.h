@@ -1,0 +1,99 @@
+// Internal declarations shared by the kernels and the host side of libms.
+// Not part of the public ABI (include/ms.h is).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ms {
+
+constexpr int kThreads = 256;  // threads per workgroup in the tiled kernels
+
+// One block of the partition (Section 3: the unknowns X_i of one block).
+struct BlockInfo {
+    int i0, j0, k0;   // origin in the global interior grid
+    int bx, by, bz;   // extents
+    long long off;    // offset of this block inside the packed inner vectors
+    int tile0;        // first tile (workgroup) number of this block
+    int ntiles;       // tiles of this block = nplane * nxchunk
+    int nplane;       // tiles across one y-z plane
+    int pad_;
+};
+
+// Device-side control block: convergence state of one solve.
+struct Ctrl {
+    int done;          // 1 once the solve has finished (all kernels then exit)
+    int status;        // ms_status of the finished solve
+    int sweep;         // index of the next residual check
+    int final_sweep;   // iterate returned = x^(final_sweep)
+    double nbeff;      // ||b_eff||_2
+    double res0;       // first relative residual (divergence test)
+    double last_res;   // latest relative residual
+    unsigned long long inner_iters;  // CG iterations summed over blocks
+    unsigned long long inner_snap;   // inner_iters as of the previous check
+    // async bookkeeping
+    int stop;          // async: set once the residual estimate is below tol
+    int max_stale;     // async: largest version gap observed
+    unsigned long long work_items;   // async: block sweeps completed
+    double pad_[3];
+};
+
+// Geometry passed by value to every kernel.
+struct Geom {
+    long long nx, ny, nz;
+    const BlockInfo *blocks;
+    const int *tile_block;   // tile -> block
+    int tx;                  // x planes per tile
+    int nblocks;
+};
+
+struct Faces {
+    const double *f[6];      // -x,+x,-y,+y,-z,+z (nullable)
+};
+
+// ---- launchers (ms_kernels.hip) ----------------------------------------
+// All launchers enqueue on `st` and return the launch error.
+
+// Outer residual r = b_eff - A x (x == nullptr means x = 0) over tiles
+// [t0, t1); stores r packed (relative to group offset goff) when r != null;
+// writes per-tile partial sums of r^2 in FP64 (p64) and in the inner type
+// (pT, may equal p64 for FP64).
+template <typename T>
+hipError_t launch_resid(const Geom &g, int vz, int t0, int t1, long long goff,
+                        const double *b, const double *x, Faces faces, T *r,
+                        double *p64, T *pT, const Ctrl *ctrl, hipStream_t st);
+
+// Inner CG phase 1: p_new = r + beta p_old (beta = 0 at iter 0), per-tile
+// partials of sigma = p_new . A_ii p_new.
+template <typename T>
+hipError_t launch_stencil(const Geom &g, int vz, int t0, int t1, long long goff,
+                          const T *r, const T *p_old, T *p_new, T *psig,
+                          const T *prho_cur, const T *prho_prev, const T *prho0,
+                          int *active, int iter, double inner_tol,
+                          Ctrl *ctrl, hipStream_t st);
+
+// Inner CG phase 2: alpha = rho/sigma; d += alpha p; r -= alpha A_ii p;
+// partials of r.r.  When last != 0: xb = xa + d + alpha p instead (r and d
+// not written).
+template <typename T>
+hipError_t launch_update(const Geom &g, int vz, int t0, int t1, long long goff,
+                         T *r, const T *p, T *d, const T *psig,
+                         const T *prho_cur, T *prho_next, int *active, int iter,
+                         int last, const double *xa, double *xb, Ctrl *ctrl,
+                         hipStream_t st);
+
+// Residual check after a sweep's residual kernels: fixed-order sum of the
+// FP64 partials of tiles [0, ntiles), convergence/divergence decision.
+hipError_t launch_check(const double *p64, int ntiles, double tol, int final_check,
+                        double *history, int history_cap, Ctrl *ctrl, hipStream_t st);
+
+// ||b_eff||: fixed-order sum of partials into ctrl->nbeff.
+hipError_t launch_norm(const double *p64, int ntiles, Ctrl *ctrl, hipStream_t st);
+
+// y = A u on the global grid (zero outside the interior).
+hipError_t launch_apply(long long nx, long long ny, long long nz, const double *u,
+                        double *y, hipStream_t st);
+
+// Fixed-order sum of n doubles into *out (device).
+hipError_t launch_sum(const double *v, int n, double *out, hipStream_t st);
+
+}  // namespace ms

@@ -1,0 +1,78 @@
+"""Parity at full size, in the launch configuration the benchmark times.
+
+A synchronous sweep updates each block from the previous iterate only
+(Section 3: X_i^(k) from sweep k-1 values), so one GPU sweep can be checked
+block by block: from the GPU's own iterate x^(2) the oracle recomputes the
+new values of a few sampled blocks (a corner, edges, interior ones) and they
+are compared with the GPU's x^(3) on those blocks.
+"""
+import numpy as np
+import pytest
+
+from paper_2009_12638_amd import inputs, ms
+from gpu_util import dev, host, rel, say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+# Tolerance on the block correction d = x^(3) - x^(2): FP64 differs only by
+# summation order (observed ~1e-14); FP32 inner CG differs from the FP64
+# oracle by FP32 rounding amplified by at most the block condition number
+# (about 1.7e3 for a 64^3 block, so ~1e-4), hence 1e-3.
+D_TOL = {"fp64": 1e-10, "mixed": 1e-3}
+
+_cache = {}
+
+
+def workload(name):
+    if name not in _cache:
+        _cache.clear()
+        _cache[name] = inputs.workload(name)
+    return _cache[name]
+
+
+def sampled_blocks(g):
+    """corner, opposite corner, an edge block and two interior blocks"""
+    def num(i, j, k):
+        return (i * g + j) * g + k
+    picks = {num(0, 0, 0), num(g - 1, g - 1, g - 1), num(0, g // 2, g - 1),
+             num(g // 2, g // 2, g // 2), num(g - 2, 1, g // 2 - 1)}
+    return sorted(picks)
+
+
+@pytest.mark.parametrize("name,precision", [("poisson256", "fp64"), ("bumps512", "fp64"),
+                                            ("bumps512", "mixed")])
+def test_sampled_block_sweep(orc, name, precision):
+    torch = torch_cuda()
+    w = workload(name)
+    shape, cuts = w["shape"], w["cuts"]
+    g = len(cuts[0]) - 1
+    h = ms.ms_create(shape, cuts=[list(map(int, c)) for c in cuts], faces=None)
+    b = dev(w["b"])
+    x = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    say("fullsize", name, precision, "2 sweeps")
+    ms.ms_solve(h, b, x, 0.0, w["m"], "sync", max_sweeps=2, precision=precision)
+    x2 = host(x)
+    say("fullsize", name, precision, "1 more sweep")
+    ms.ms_solve(h, b, x, 0.0, w["m"], "sync", max_sweeps=1, precision=precision)
+    x3 = host(x)
+    del x, b
+    ms.ms_destroy(h)
+    torch.cuda.empty_cache()
+    beff = orc.lift_bc(w["b"], [None] * 6)
+    blocks = sampled_blocks(g)
+    xo = orc.block_sweep_some(beff, x2, cuts, blocks, m=w["m"])
+    cx, cy, cz = cuts
+    worst = 0.0
+    for blk in blocks:
+        bi, bj, bk = blk // (g * g), (blk // g) % g, blk % g
+        sl = (slice(cx[bi], cx[bi + 1]), slice(cy[bj], cy[bj + 1]), slice(cz[bk], cz[bk + 1]))
+        d_gpu = x3[sl] - x2[sl]
+        d_or = xo[sl] - x2[sl]
+        e = rel(d_gpu, d_or)
+        worst = max(worst, e)
+        assert e <= D_TOL[precision], (blk, e)
+    # every other block moved too (nothing skipped), and nothing is non-finite
+    assert np.isfinite(x3).all()
+    moved = np.abs(x3 - x2).reshape(g, shape[0] // g, g, shape[1] // g, g, shape[2] // g)
+    assert (moved.max(axis=(1, 3, 5)) > 0).all()
+    print(f"{name} {precision}: worst block correction error {worst:.2e}")
