@@ -2,8 +2,9 @@
 // scheduler for the synchronous two-stage multisplitting solve.
 //
 // Sweep schedule (synchronous mode).  Blocks are processed in groups of
-// consecutive blocks whose inner CG vectors (r, d and two p buffers) fit in
-// the on-package cache; every group reuses the same inner buffers.  For one
+// consecutive blocks (by default one group holding every block; smaller
+// groups keep their inner vectors cache resident but give smaller launches);
+// every group reuses the same inner buffers.  For one
 // group: residual (halo reads from x_old), then m x {stencil, update}; the
 // last update writes x_new = x_old + d into the second outer buffer, so all
 // groups of a sweep read only x_old (Section 3: X_i^(k) uses only sweep k-1
@@ -29,6 +30,7 @@ using ms::BlockInfo;
 using ms::Ctrl;
 using ms::Faces;
 using ms::Geom;
+using ms::AsyncState;
 
 namespace {
 
@@ -52,7 +54,7 @@ struct ms_handle {
     std::vector<int> cx, cy, cz;
     int vzmax = 1;              // widest vector every z cut and nz allow
     // current tiling
-    int cur_vz = 0, cur_tx = 0, ntiles = 0;
+    int cur_vz = 0, cur_tx = 0, cur_rows = 0, ntiles = 0;
     std::vector<BlockInfo> blocks_h;
     int tiles_cap = 0;
     // device memory
@@ -67,6 +69,14 @@ struct ms_handle {
     double *history_d = nullptr;
     double *faces_d[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     double *scal_d = nullptr;
+    // global CG: the whole grid as a single block
+    BlockInfo *cg_block_d = nullptr;
+    int *cg_tiles_d = nullptr;
+    int cg_cap = 0, cg_ntiles = 0, cg_vz = 0, cg_tx = 0, cg_rows = 0;
+    // asynchronous sweeps
+    int *version_d = nullptr, *claim_d = nullptr, *nbr_d = nullptr, *finished_d = nullptr;
+    double *board_d = nullptr;
+    int num_cu = 0;
     // profiling
     std::vector<hipEvent_t> ev;
     std::vector<int> ev_class;
@@ -119,9 +129,9 @@ bool dev_range_ok(const void *p, size_t bytes) {
     return (const char *)p + bytes <= (const char *)base + size;
 }
 
-// Build the tile table for vector width vz and x chunk tx.
-ms_status set_tiling(ms_handle *h, int vz, int tx, hipStream_t st) {
-    if (h->cur_vz == vz && h->cur_tx == tx) return MS_OK;
+// Build the tile table for vector width vz, x chunk tx and rows per thread.
+ms_status set_tiling(ms_handle *h, int vz, int tx, int rows, hipStream_t st) {
+    if (h->cur_vz == vz && h->cur_tx == tx && h->cur_rows == rows) return MS_OK;
     std::vector<int> tb;
     h->blocks_h.resize(h->nblocks);
     long long off = 0;
@@ -137,7 +147,8 @@ ms_status set_tiling(ms_handle *h, int vz, int tx, hipStream_t st) {
                 B.bz = h->cz[bk + 1] - B.k0;
                 B.off = off;
                 const long long P = (long long)B.by * B.bz;
-                B.nplane = (int)((P + (long long)ms::kThreads * vz - 1) / ((long long)ms::kThreads * vz));
+                const long long slots = (long long)((B.by + rows - 1) / rows) * (B.bz / vz);
+                B.nplane = (int)((slots + ms::kThreads - 1) / ms::kThreads);
                 const int nxc = (B.bx + tx - 1) / tx;
                 B.ntiles = B.nplane * nxc;
                 B.tile0 = tile;
@@ -155,6 +166,7 @@ ms_status set_tiling(ms_handle *h, int vz, int tx, hipStream_t st) {
     h->ntiles = tile;
     h->cur_vz = vz;
     h->cur_tx = tx;
+    h->cur_rows = rows;
     return MS_OK;
 }
 
@@ -164,6 +176,7 @@ Geom geom(const ms_handle *h) {
     g.blocks = h->blocks_d;
     g.tile_block = h->tile_block_d;
     g.tx = h->cur_tx;
+    g.rows = h->cur_rows;
     g.nblocks = h->nblocks;
     return g;
 }
@@ -198,7 +211,8 @@ ms_status copy_bc(ms_handle *h, const ms_bc *bc) {
 void free_all(ms_handle *h) {
     void *ps[] = {h->blocks_d, h->tile_block_d, h->x1, h->r, h->d, h->p0, h->p1, h->part64,
                   h->partT, h->psig, h->prhoA, h->prhoB, h->active, h->ctrl, h->history_d,
-                  h->scal_d};
+                  h->scal_d, h->cg_block_d, h->cg_tiles_d, h->version_d, h->claim_d,
+                  h->nbr_d, h->finished_d, h->board_d};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     for (int t = 0; t < 6; t++)
@@ -380,19 +394,42 @@ ms_status beff_norm(ms_handle *h, const double *b, hipStream_t st, double *out) 
     return MS_OK;
 }
 
-int auto_tx(const ms_handle *h, int bx_min) {
-    (void)h;
-    return std::max(kTxMin, std::min(16, bx_min));
+// Tile choice when the caller leaves it open: the largest rows-per-thread
+// and x chunk that still give at least kMinTiles workgroups per launch
+// (measured on 512^3 with 64^3 blocks: fewer, fatter tiles win as long as
+// every compute unit gets several workgroups).
+constexpr long long kMinTiles = 1024;
+
+long long count_tiles(const ms_handle *h, int vz, int tx, int rows) {
+    long long n = 0;
+    for (int bi = 0; bi < h->gx; bi++)
+        for (int bj = 0; bj < h->gy; bj++)
+            for (int bk = 0; bk < h->gz; bk++) {
+                const int bx = h->cx[bi + 1] - h->cx[bi], by = h->cy[bj + 1] - h->cy[bj],
+                          bz = h->cz[bk + 1] - h->cz[bk];
+                const long long slots = (long long)((by + rows - 1) / rows) * (bz / vz);
+                n += ((slots + ms::kThreads - 1) / ms::kThreads) * ((bx + tx - 1) / tx);
+            }
+    return n;
+}
+
+void auto_tiling(const ms_handle *h, int vz, int *tx, int *rows) {
+    for (int r : {4, 2, 1})
+        for (int t : {32, 16, 8, 4})
+            if (count_tiles(h, vz, t, r) >= kMinTiles) { *tx = t; *rows = r; return; }
+    *tx = kTxMin;
+    *rows = 1;
 }
 
 template <typename T>
 ms_status solve_sync(ms_handle *h, const double *b, double *x, double tol, int m,
                      const ms_opts &o, ms_stats *stats, hipStream_t st) {
     const int vz = std::min(h->vzmax, (int)(16 / sizeof(T)));
-    int bx_min = 1 << 30;
-    for (int t = 0; t + 1 < (int)h->cx.size(); t++) bx_min = std::min(bx_min, h->cx[t + 1] - h->cx[t]);
-    const int tx = o.x_chunk > 0 ? std::max(kTxMin, o.x_chunk) : auto_tx(h, bx_min);
-    ms_status s = set_tiling(h, vz, tx, st);
+    int tx = 0, rows = 0;
+    auto_tiling(h, vz, &tx, &rows);
+    if (o.x_chunk > 0) tx = std::max(kTxMin, o.x_chunk);
+    if (o.rows == 1 || o.rows == 2 || o.rows == 4) rows = o.rows;
+    ms_status s = set_tiling(h, vz, tx, rows, st);
     if (s != MS_OK) return s;
     double nbeff = 0.0;
     s = beff_norm<T>(h, b, st, &nbeff);
@@ -410,14 +447,14 @@ ms_status solve_sync(ms_handle *h, const double *b, double *x, double tol, int m
         return MS_OK;
     }
     // groups: inner vectors r, d, p0, p1 of one group sized for the cache
-    long long cap_cells;
-    if (o.group_blocks < 0) cap_cells = h->N;
-    else if (o.group_blocks > 0) {
+    // groups: blocks per launch (all of them unless the caller asks for
+    // cache-sized groups; small launches lose more to kernel ramp-up and
+    // drain than the cache gives back)
+    long long cap_cells = h->N;
+    if (o.group_blocks > 0) {
         long long mx = 0;
         for (const BlockInfo &B : h->blocks_h) mx = std::max(mx, (long long)B.bx * B.by * B.bz);
         cap_cells = mx * o.group_blocks;
-    } else {
-        cap_cells = (160ll << 20) / (4 * (long long)sizeof(T));
     }
     const std::vector<Group> groups = make_groups(h, cap_cells);
     const long long cells_per_sweep = h->N * (long long)m;
@@ -469,6 +506,271 @@ ms_status solve_sync(ms_handle *h, const double *b, double *x, double tol, int m
     }
 }
 
+// ---- residual of an iterate, FP64, without touching the control block ----
+
+ms_status residual_norms(ms_handle *h, const double *b, const double *x, hipStream_t st,
+                         double *nbeff, double *absres) {
+    const Geom g = geom(h);
+    HIPCHK(h, ms::launch_resid<double>(g, h->cur_vz, 0, h->ntiles, 0, b, nullptr, faces(h),
+                                       nullptr, h->part64, h->part64, nullptr, st));
+    HIPCHK(h, ms::launch_sum(h->part64, h->ntiles, h->scal_d, st));
+    HIPCHK(h, ms::launch_resid<double>(g, h->cur_vz, 0, h->ntiles, 0, b, x, faces(h), nullptr,
+                                       h->part64, h->part64, nullptr, st));
+    HIPCHK(h, ms::launch_sum(h->part64, h->ntiles, h->scal_d + 1, st));
+    double ss[2] = {0.0, 0.0};
+    HIPCHK(h, hipMemcpyAsync(ss, h->scal_d, sizeof(ss), hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    *nbeff = std::sqrt(ss[0]);
+    *absres = std::sqrt(ss[1]);
+    return MS_OK;
+}
+
+// ---- asynchronous solve ----------------------------------------------------
+
+__global__ void k_async_reset(int *version, int *claim, double *board, int nb, int *finished,
+                              int already, Ctrl *c, int full) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += gridDim.x * blockDim.x) {
+        if (full) { version[i] = 0; claim[i] = 0; }
+        board[i] = INFINITY;   // a block counts as unconverged until it publishes
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *finished = already;   // blocks already at the sweep limit of this launch
+        c->stop = 0;
+        if (full) { c->work_items = 0ull; c->inner_iters = 0ull; c->max_stale = 0; }
+    }
+}
+
+template <typename T>
+ms_status solve_async(ms_handle *h, const double *b, double *x, double tol, int m,
+                      const ms_opts &o, ms_stats *stats, hipStream_t st) {
+    if (o.staleness < 1)
+        return fail(h, MS_ERR_ARG, "asynchronous mode needs staleness >= 1");
+    const int vz = std::min(h->vzmax, (int)(16 / sizeof(T)));
+    int tx = 0, rows = 0;
+    auto_tiling(h, vz, &tx, &rows);
+    if (o.x_chunk > 0) tx = std::max(kTxMin, o.x_chunk);
+    if (o.rows == 1 || o.rows == 2 || o.rows == 4) rows = o.rows;
+    ms_status s = set_tiling(h, vz, tx, rows, st);
+    if (s != MS_OK) return s;
+    double nbeff = 0.0, absres = 0.0;
+    s = beff_norm<T>(h, b, st, &nbeff);    // also resets the control block
+    if (s != MS_OK) return s;
+    if (!std::isfinite(nbeff)) return fail(h, MS_ERR_NONFINITE, "b_eff is not finite");
+    if (nbeff == 0.0) {
+        s = zero_vec(h, x, h->N, st);
+        if (s != MS_OK) return s;
+        HIPCHK(h, hipStreamSynchronize(st));
+        return MS_OK;
+    }
+    int per_cu = 0;
+    HIPCHK(h, ms::async_occupancy<T>(vz, rows, &per_cu));
+    if (per_cu < 1) return fail(h, MS_ERR_HIP, "asynchronous kernel cannot be resident");
+    const int grid = (int)std::min<long long>(h->nblocks, (long long)per_cu * h->num_cu);
+    const int nbk = h->nblocks;
+    hipLaunchKernelGGL(k_async_reset, dim3((nbk + 255) / 256), dim3(256), 0, st, h->version_d,
+                       h->claim_d, h->board_d, nbk, h->finished_d, 0, h->ctrl, 1);
+    HIPCHK(h, hipGetLastError());
+    const double tol2 = tol > 0.0 ? (tol * nbeff) * (tol * nbeff) : 0.0;
+    const long long per_sweep = std::max(1ll, h->N * (long long)m);
+    const int chunk = o.check_every > 0
+                          ? o.check_every
+                          : (int)std::max(8ll, std::min(1000ll, (8ll << 30) / per_sweep));
+    AsyncState as;
+    as.version = h->version_d;
+    as.claim = h->claim_d;
+    as.board = h->board_d;
+    as.nbr = h->nbr_d;
+    as.finished = h->finished_d;
+    Bufs<T> B = bufs<T>(h);
+    std::vector<int> ver(nbk, 0);
+    int maxv = 0, minv = 0, relaunches = 0;
+    int hist_n = 0;
+    ms_status result = MS_OK;
+    s = prof_begin(h, o.profile != 0);
+    if (s != MS_OK) return s;
+    // the test comes first, as in the synchronous loop
+    s = residual_norms(h, b, x, st, &nbeff, &absres);
+    if (s != MS_OK) return s;
+    double rel = absres / nbeff;
+    const double rel0 = rel;
+    if (stats && stats->history && hist_n < stats->history_cap) stats->history[hist_n++] = rel;
+    bool first = true;
+    for (;;) {
+        if (!std::isfinite(rel)) { result = fail(h, MS_ERR_NONFINITE, "residual became non-finite"); break; }
+        if (tol > 0.0 && rel <= tol) break;
+        if (rel0 > 0.0 && rel > 1e6 * rel0) { result = fail(h, MS_ERR_DIVERGED, "residual grew by 1e6"); break; }
+        if (minv >= o.max_sweeps) {
+            if (tol > 0.0) result = fail(h, MS_ERR_NOT_CONVERGED, "max_sweeps reached above tol");
+            break;
+        }
+        // this launch runs until the estimate drops below tol or every block
+        // has reached `limit` sweeps (limit > minv, so some block can move)
+        const int limit = (int)std::min<long long>(o.max_sweeps, (long long)maxv + chunk);
+        int already = 0;
+        for (int v : ver) already += v >= limit;
+        if (!first) {
+            Ctrl c;
+            HIPCHK(h, hipMemcpy(&c, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+            if (c.stop) relaunches++;   // the estimate said converged, the check did not
+        }
+        hipLaunchKernelGGL(k_async_reset, dim3((nbk + 255) / 256), dim3(256), 0, st, h->version_d,
+                           h->claim_d, h->board_d, nbk, h->finished_d, already, h->ctrl, 0);
+        HIPCHK(h, hipGetLastError());
+        first = false;
+        {
+            Prof p(h, st, MS_K_OTHER);
+            HIPCHK(h, ms::launch_async<T>(geom(h), vz, grid, b, x, faces(h), B.r, B.p[0], B.p[1],
+                                          B.d, as, m, o.staleness, limit, tol2, o.inner_tol,
+                                          h->ctrl, st));
+        }
+        HIPCHK(h, hipMemcpyAsync(ver.data(), h->version_d, sizeof(int) * nbk,
+                                 hipMemcpyDeviceToHost, st));
+        HIPCHK(h, hipStreamSynchronize(st));
+        prof_collect(h, stats);
+        minv = *std::min_element(ver.begin(), ver.end());
+        maxv = *std::max_element(ver.begin(), ver.end());
+        // verify on the true FP64 residual (the estimate may be sweeps old)
+        s = residual_norms(h, b, x, st, &nbeff, &absres);
+        if (s != MS_OK) return s;
+        rel = absres / nbeff;
+        if (stats && stats->history && hist_n < stats->history_cap) stats->history[hist_n++] = rel;
+    }
+    Ctrl c;
+    HIPCHK(h, hipMemcpy(&c, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    if (stats) {
+        stats->sweeps = (int)((c.work_items + nbk / 2) / nbk);
+        stats->inner_iters = (int64_t)c.inner_iters;
+        stats->rel_residual = rel;
+        stats->max_staleness_seen = c.max_stale;
+        stats->relaunches = relaunches;
+        stats->history_len = hist_n;
+    }
+    return result;
+}
+
+// ---- global CG baseline ------------------------------------------------------
+
+ms_status set_cg_tiling(ms_handle *h, int vz, hipStream_t st) {
+    int tx = kTxMin, rows = 1;
+    bool found = false;
+    const long long slots_base = h->ny;  // rows
+    for (int r : {4, 2, 1}) {
+        for (int t : {32, 16, 8, 4}) {
+            const long long slots = ((slots_base + r - 1) / r) * (h->nz / vz);
+            const long long n = ((slots + ms::kThreads - 1) / ms::kThreads) * ((h->nx + t - 1) / t);
+            if (n >= kMinTiles) { tx = t; rows = r; found = true; break; }
+        }
+        if (found) break;
+    }
+    if (h->cg_vz == vz && h->cg_tx == tx && h->cg_rows == rows) return MS_OK;
+    BlockInfo B;
+    B.i0 = B.j0 = B.k0 = 0;
+    B.bx = (int)h->nx; B.by = (int)h->ny; B.bz = (int)h->nz;
+    B.off = 0;
+    B.tile0 = 0;
+    const long long slots = ((h->ny + rows - 1) / rows) * (h->nz / vz);
+    B.nplane = (int)((slots + ms::kThreads - 1) / ms::kThreads);
+    B.ntiles = B.nplane * (int)((h->nx + tx - 1) / tx);
+    B.pad_ = 0;
+    if (B.ntiles > h->cg_cap) return fail(h, MS_ERR_ARG, "global CG tiling exceeds its table");
+    std::vector<int> tb(B.ntiles, 0);
+    HIPCHK(h, hipMemcpyAsync(h->cg_block_d, &B, sizeof(B), hipMemcpyHostToDevice, st));
+    HIPCHK(h, hipMemcpyAsync(h->cg_tiles_d, tb.data(), sizeof(int) * tb.size(),
+                             hipMemcpyHostToDevice, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    h->cg_vz = vz; h->cg_tx = tx; h->cg_rows = rows; h->cg_ntiles = B.ntiles;
+    return MS_OK;
+}
+
+ms_status solve_cg(ms_handle *h, const double *b, double *x, double tol, int max_iters,
+                   const ms_opts &o, ms_stats *stats, hipStream_t st) {
+    if (h->nx > (1 << 30) || h->ny > (1 << 30) || h->nz > (1 << 30))
+        return fail(h, MS_ERR_ARG, "grid too large for the single-block tiling");
+    const int vz = h->nz % 2 == 0 ? 2 : 1;
+    ms_status s = set_cg_tiling(h, vz, st);
+    if (s != MS_OK) return s;
+    // block tiling for the b_eff norm (any valid tiling will do)
+    if (h->cur_vz == 0) {
+        s = set_tiling(h, std::min(h->vzmax, 2), 16, 1, st);
+        if (s != MS_OK) return s;
+    }
+    double nbeff = 0.0;
+    s = beff_norm<double>(h, b, st, &nbeff);
+    if (s != MS_OK) return s;
+    if (!std::isfinite(nbeff)) return fail(h, MS_ERR_NONFINITE, "b_eff is not finite");
+    if (nbeff == 0.0) {
+        s = zero_vec(h, x, h->N, st);
+        if (s != MS_OK) return s;
+        HIPCHK(h, hipStreamSynchronize(st));
+        return MS_OK;
+    }
+    Geom g1;
+    g1.nx = h->nx; g1.ny = h->ny; g1.nz = h->nz;
+    g1.blocks = h->cg_block_d;
+    g1.tile_block = h->cg_tiles_d;
+    g1.tx = h->cg_tx;
+    g1.rows = h->cg_rows;
+    g1.nblocks = 1;
+    const int nt = h->cg_ntiles;
+    double *r = (double *)h->r, *P[2] = {(double *)h->p0, (double *)h->p1};
+    double *psig = (double *)h->psig, *prho = (double *)h->prhoA, *scal = h->scal_d;
+    s = prof_begin(h, o.profile != 0);
+    if (s != MS_OK) return s;
+    {
+        Prof p(h, st, MS_K_RESID);
+        HIPCHK(h, ms::launch_resid<double>(g1, vz, 0, nt, 0, b, x, faces(h), r, h->part64,
+                                           h->part64, h->ctrl, st));
+    }
+    HIPCHK(h, ms::launch_gcg_reduce(h->part64, nt, 0, tol, max_iters, h->history_d, kHistoryCap,
+                                    scal, h->ctrl, st));
+    const int batch = o.check_every > 0 ? o.check_every : 64;
+    Ctrl c;
+    int j = 0;
+    for (;;) {
+        const int nb = std::min(batch, max_iters - j);
+        for (int q = 0; q < nb; q++, j++) {
+            {
+                Prof p(h, st, MS_K_STENCIL);
+                HIPCHK(h, ms::launch_gcg_stencil(g1, vz, nt, r, P[(j + 1) % 2], P[j % 2], psig,
+                                                 scal, j, h->ctrl, st));
+            }
+            HIPCHK(h, ms::launch_gcg_reduce(psig, nt, 1, tol, max_iters, h->history_d, kHistoryCap,
+                                            scal, h->ctrl, st));
+            {
+                Prof p(h, st, MS_K_UPDATE);
+                HIPCHK(h, ms::launch_gcg_update(g1, vz, nt, r, P[j % 2], x, prho, scal, h->ctrl, st));
+            }
+            HIPCHK(h, ms::launch_gcg_reduce(prho, nt, 2, tol, max_iters, h->history_d, kHistoryCap,
+                                            scal, h->ctrl, st));
+        }
+        HIPCHK(h, hipMemcpyAsync(&c, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+        HIPCHK(h, hipStreamSynchronize(st));
+        prof_collect(h, stats);
+        if (c.done) break;
+        if (j >= max_iters) return fail(h, MS_ERR_HIP, "device did not finish the CG solve");
+    }
+    double absres = 0.0;
+    s = residual_norms(h, b, x, st, &nbeff, &absres);
+    if (s != MS_OK) return s;
+    if (stats) {
+        stats->sweeps = c.final_sweep;
+        stats->inner_iters = c.final_sweep;
+        stats->rel_residual = absres / nbeff;
+        if (stats->history && stats->history_cap > 0) {
+            const int n = std::min(std::min(stats->history_cap, kHistoryCap), c.final_sweep + 1);
+            HIPCHK(h, hipMemcpy(stats->history, h->history_d, sizeof(double) * n,
+                                hipMemcpyDeviceToHost));
+            stats->history_len = n;
+        }
+    }
+    switch (c.status) {
+        case 0: return MS_OK;
+        case 4: return fail(h, MS_ERR_NOT_CONVERGED, "max_iters reached above tol");
+        case 5: return fail(h, MS_ERR_NONFINITE, "residual became non-finite");
+        default: return fail(h, MS_ERR_HIP, "unknown device status");
+    }
+}
+
 }  // namespace
 
 // ======================================================================
@@ -490,6 +792,7 @@ void ms_default_opts(ms_opts *o) {
     o->x_chunk = 0;
     o->profile = 0;
     o->use_graph = 1;
+    o->rows = 0;
 }
 
 const char *ms_status_string(ms_status s) {
@@ -568,8 +871,15 @@ ms_status ms_create(const ms_grid *grid, const ms_blocks *blocks, const ms_bc *b
                 const long long nxc = (h->cx[bi + 1] - h->cx[bi] + kTxMin - 1) / kTxMin;
                 cap += np * nxc;
             }
-    if (cap > (1ll << 30)) { delete h; return fail(nullptr, MS_ERR_ARG, "too many tiles"); }
-    h->tiles_cap = (int)cap;
+    // the global-CG tiling (one block = the grid) needs at most as many tiles
+    const long long cg_cap = ((h->ny * h->nz + ms::kThreads - 1) / ms::kThreads) *
+                             ((h->nx + kTxMin - 1) / kTxMin);
+    if (cap > (1ll << 30) || cg_cap > (1ll << 30)) {
+        delete h;
+        return fail(nullptr, MS_ERR_ARG, "too many tiles");
+    }
+    h->cg_cap = (int)cg_cap;
+    h->tiles_cap = (int)std::max(cap, cg_cap);
     const size_t vb = sizeof(double) * (size_t)h->N;
     const size_t tb = sizeof(double) * (size_t)h->tiles_cap;
     struct A { void **p; size_t n; } allocs[] = {
@@ -582,6 +892,13 @@ ms_status ms_create(const ms_grid *grid, const ms_blocks *blocks, const ms_bc *b
         {(void **)&h->ctrl, sizeof(Ctrl)},
         {(void **)&h->history_d, sizeof(double) * (size_t)kHistoryCap},
         {(void **)&h->scal_d, 64},
+        {(void **)&h->cg_block_d, sizeof(BlockInfo)},
+        {(void **)&h->cg_tiles_d, sizeof(int) * (size_t)h->cg_cap},
+        {(void **)&h->version_d, sizeof(int) * (size_t)h->nblocks},
+        {(void **)&h->claim_d, sizeof(int) * (size_t)h->nblocks},
+        {(void **)&h->nbr_d, sizeof(int) * 6 * (size_t)h->nblocks},
+        {(void **)&h->finished_d, 64},
+        {(void **)&h->board_d, sizeof(double) * (size_t)h->nblocks},
     };
     for (auto &a : allocs) {
         e = hipMalloc(a.p, a.n);
@@ -594,7 +911,25 @@ ms_status ms_create(const ms_grid *grid, const ms_blocks *blocks, const ms_bc *b
         }
     }
     ms_status s = copy_bc(h, bc);
-    if (s == MS_OK) s = set_tiling(h, h->vzmax >= 2 ? 2 : 1, 16, nullptr);
+    if (s == MS_OK) s = set_tiling(h, h->vzmax >= 2 ? 2 : 1, 16, 1, nullptr);
+    if (s == MS_OK) {
+        // neighbour table of the block grid, faces -x,+x,-y,+y,-z,+z
+        std::vector<int> nbr(6 * (size_t)h->nblocks, -1);
+        for (int bi = 0; bi < h->gx; bi++)
+            for (int bj = 0; bj < h->gy; bj++)
+                for (int bk = 0; bk < h->gz; bk++) {
+                    const int b = (bi * h->gy + bj) * h->gz + bk;
+                    if (bi > 0) nbr[6 * b + 0] = b - h->gy * h->gz;
+                    if (bi < h->gx - 1) nbr[6 * b + 1] = b + h->gy * h->gz;
+                    if (bj > 0) nbr[6 * b + 2] = b - h->gz;
+                    if (bj < h->gy - 1) nbr[6 * b + 3] = b + h->gz;
+                    if (bk > 0) nbr[6 * b + 4] = b - 1;
+                    if (bk < h->gz - 1) nbr[6 * b + 5] = b + 1;
+                }
+        e = hipMemcpy(h->nbr_d, nbr.data(), sizeof(int) * nbr.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&h->num_cu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) s = hip_fail(h, e, "ms_create setup");
+    }
     if (s != MS_OK) {
         g_create_error = h->err;
         free_all(h);
@@ -655,9 +990,12 @@ ms_status ms_solve(ms_handle *h, const double *b, double *x, double tol, int32_t
         stats->history_cap = cap;
     }
     hipStream_t st = (hipStream_t)o.stream;
-    if (mode == MS_ASYNC) return fail(h, MS_ERR_UNSUPPORTED, "asynchronous mode not built yet");
-    s = o.precision == MS_FP64 ? solve_sync<double>(h, b, x, tol, inner_iters, o, stats, st)
-                               : solve_sync<float>(h, b, x, tol, inner_iters, o, stats, st);
+    if (mode == MS_ASYNC)
+        s = o.precision == MS_FP64 ? solve_async<double>(h, b, x, tol, inner_iters, o, stats, st)
+                                   : solve_async<float>(h, b, x, tol, inner_iters, o, stats, st);
+    else
+        s = o.precision == MS_FP64 ? solve_sync<double>(h, b, x, tol, inner_iters, o, stats, st)
+                                   : solve_sync<float>(h, b, x, tol, inner_iters, o, stats, st);
     if (stats)
         stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     return s;
@@ -672,19 +1010,9 @@ ms_status ms_residual(ms_handle *h, const double *b, const double *x, double *re
     s = check_vec(h, x, "x");
     if (s != MS_OK) return s;
     hipStream_t st = (hipStream_t)stream;
-    s = set_tiling(h, std::min(h->vzmax, 2), h->cur_tx ? h->cur_tx : 16, st);
+    double nbeff = 0.0, a = 0.0;
+    s = residual_norms(h, b, x, st, &nbeff, &a);
     if (s != MS_OK) return s;
-    double nbeff = 0.0;
-    s = beff_norm<double>(h, b, st, &nbeff);
-    if (s != MS_OK) return s;
-    const Geom g = geom(h);
-    HIPCHK(h, ms::launch_resid<double>(g, h->cur_vz, 0, h->ntiles, 0, b, x, faces(h), nullptr,
-                                       h->part64, h->part64, nullptr, st));
-    HIPCHK(h, ms::launch_sum(h->part64, h->ntiles, h->scal_d, st));
-    double ss = 0.0;
-    HIPCHK(h, hipMemcpyAsync(&ss, h->scal_d, sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(h, hipStreamSynchronize(st));
-    const double a = std::sqrt(ss);
     if (abs_out) *abs_out = a;
     *rel_out = nbeff > 0.0 ? a / nbeff : 0.0;
     return MS_OK;
@@ -705,9 +1033,31 @@ ms_status ms_apply(ms_handle *h, const double *u, double *y, void *stream) {
 
 ms_status ms_cg(ms_handle *h, const double *b, double *x, double tol, int32_t max_iters,
                 const ms_opts *opts, ms_stats *stats) {
-    (void)b; (void)x; (void)tol; (void)max_iters; (void)opts; (void)stats;
+    const auto t_start = std::chrono::steady_clock::now();
     if (!h) return fail(nullptr, MS_ERR_ARG, "handle is NULL");
-    return fail(h, MS_ERR_UNSUPPORTED, "global CG not built yet");
+    ms_opts o;
+    ms_default_opts(&o);
+    if (opts) o = *opts;
+    ms_status s = check_vec(h, b, "b");
+    if (s != MS_OK) return s;
+    s = check_vec(h, x, "x");
+    if (s != MS_OK) return s;
+    const char *bb = (const char *)b, *xx = (const char *)x;
+    const size_t bytes = sizeof(double) * (size_t)h->N;
+    if (bb < xx + bytes && xx < bb + bytes) return fail(h, MS_ERR_ARG, "b and x overlap");
+    if (max_iters < 0) return fail(h, MS_ERR_ARG, "max_iters must be >= 0");
+    if (std::isnan(tol)) return fail(h, MS_ERR_ARG, "tol is NaN");
+    if (stats) {
+        double *hist = stats->history;
+        const int cap = stats->history_cap;
+        memset(stats, 0, sizeof(*stats));
+        stats->history = hist;
+        stats->history_cap = cap;
+    }
+    s = solve_cg(h, b, x, tol, max_iters, o, stats, (hipStream_t)o.stream);
+    if (stats)
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    return s;
 }
 
 }  // extern "C"

@@ -6,7 +6,8 @@
 
 namespace ms {
 
-constexpr int kThreads = 256;  // threads per workgroup in the tiled kernels
+constexpr int kThreads = 256;       // threads per workgroup in the tiled kernels
+constexpr int kAsyncThreads = 512;  // threads per persistent asynchronous worker
 
 // One block of the partition (Section 3: the unknowns X_i of one block).
 struct BlockInfo {
@@ -43,11 +44,21 @@ struct Geom {
     const BlockInfo *blocks;
     const int *tile_block;   // tile -> block
     int tx;                  // x planes per tile
+    int rows;                // rows (y) per thread: 1, 2 or 4
     int nblocks;
 };
 
 struct Faces {
     const double *f[6];      // -x,+x,-y,+y,-z,+z (nullable)
+};
+
+// Shared state of an asynchronous solve (one entry per block).
+struct AsyncState {
+    int *version;        // sweeps the block has completed
+    int *claim;          // 1 while a worker holds the block
+    double *board;       // latest published ||r_i||^2 of the block
+    const int *nbr;      // 6 neighbour blocks per block (-1 = none)
+    int *finished;       // blocks that reached the sweep limit this launch
 };
 
 // ---- launchers (ms_kernels.hip) ----------------------------------------
@@ -80,6 +91,25 @@ hipError_t launch_update(const Geom &g, int vz, int t0, int t1, long long goff,
                          const T *prho_cur, T *prho_next, int *active, int iter,
                          int last, const double *xa, double *xb, Ctrl *ctrl,
                          hipStream_t st);
+
+// Persistent asynchronous sweep kernel (grid = workers).
+template <typename T>
+hipError_t launch_async(const Geom &g, int vz, int grid, const double *b, double *x, Faces faces,
+                        T *r, T *p0, T *p1, T *d, AsyncState as, int m, int S, int max_sweeps,
+                        double tol2, double inner_tol, Ctrl *ctrl, hipStream_t st);
+template <typename T>
+hipError_t async_occupancy(int vz, int rows, int *per_cu);
+
+// Global CG on the single-block geometry g (device scalars scal[3]).
+hipError_t launch_gcg_stencil(const Geom &g, int vz, int ntiles, const double *r,
+                              const double *pold, double *pnew, double *psig, const double *scal,
+                              int iter, const Ctrl *ctrl, hipStream_t st);
+hipError_t launch_gcg_update(const Geom &g, int vz, int ntiles, double *r, const double *p,
+                             double *x, double *prho, const double *scal, const Ctrl *ctrl,
+                             hipStream_t st);
+hipError_t launch_gcg_reduce(const double *part, int ntiles, int which, double tol, int max_iters,
+                             double *history, int history_cap, double *scal, Ctrl *ctrl,
+                             hipStream_t st);
 
 // Residual check after a sweep's residual kernels: fixed-order sum of the
 // FP64 partials of tiles [0, ntiles), convergence/divergence decision.
