@@ -1,4 +1,4 @@
-"""Benchmark: synchronous two-stage multisplitting sweeps on one MI355X.
+"""Benchmark: two-stage multisplitting sweeps on one MI355X.
 
 Workload (default "bumps512"): 512^3 Poisson problem, source = 8 seeded
 Gaussian bumps plus N(0, 1e-3) noise, zero Dirichlet boundaries, 8x8x8
@@ -8,13 +8,16 @@ block, outer update), timed with tol <= 0 so exactly --steps sweeps run.
 Inputs are resident in GPU memory before timing starts.
 
 Prints one JSON line.  `value` is the whole-sweep memory throughput of the
-headline precision (mixed: FP32 inner CG, FP64 outer) in GB/s, using the
-compulsory bytes per unknown of the kernels that make up a sweep (see
-sweep_bytes); the FP64 sweep is reported beside it, with per-kernel event
-timings, the dominant kernel's fraction of the 8 TB/s HBM peak, and the CPU
-oracle timed on this host over a bounded sample of the same workload.
+headline run (synchronous sweeps, mixed precision: FP32 inner CG, FP64
+residual/test/update) in GB/s, from the compulsory bytes per unknown of the
+kernels that make up a sweep (kernel_bytes).  The same line carries the FP64
+and asynchronous sweeps, the global CG baseline, per-kernel event timings,
+the dominant kernel's fraction of the 8 TB/s HBM peak, and the CPU oracle
+timed on this host over a bounded sample of the same workload.  With
+--full-solve each mode is also run to the 1e-8 relative residual and timed
+(time-to-tolerance), and the CPU oracle re-checks the final residual.
 
-    python bench.py [--steps K] [--warmup W] [--precision mixed|fp64|both]
+    python bench.py [--steps K] [--warmup W] [--modes sync-mixed,sync-fp64,...]
                     [--full-solve] [--no-cpu]
 """
 from __future__ import annotations
@@ -30,12 +33,17 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time-to-1e-8 residual & stencil/CG HBM GB/s, 512^3 Laplace; mixed vs plain FP64"
 HBM_PEAK_GBPS = 8000.0
+ALL_MODES = ["sync-mixed", "sync-fp64", "async-mixed", "async-fp64", "cg-fp64"]
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
 
 def kernel_bytes(m: int, T: int):
-    """Compulsory bytes per unknown of each kernel launch in one sweep, in
-    launch order, for inner type size T (8 = FP64, 4 = FP32): every operand
-    vector counted once (halo re-reads are cache hits and not counted).
+    """Compulsory bytes per unknown of each kernel launch in one synchronous
+    sweep, in launch order, for inner type size T (8 = FP64, 4 = FP32):
+    every operand vector counted once (halo re-reads are cache hits).
 
     resid   : read x, b (FP64), write r (T)
     stencil : read r (+ p_old after iteration 0), write p_new
@@ -62,101 +70,123 @@ def model_sweep_bytes(m: int, mixed: bool) -> int:
     return 40 * m + 40 if mixed else 80 * m + 48
 
 
-def run_gpu(args, torch, ms, inputs, w, precision: str):
-    shape, cuts = w["shape"], w["cuts"]
-    N = shape[0] * shape[1] * shape[2]
-    m = args.m
-    T = 4 if precision == "mixed" else 8
-    b = torch.from_numpy(w["b"]).to("cuda")
-    h = ms.ms_create(shape, cuts=[list(map(int, c)) for c in cuts], faces=None)
-    x = torch.zeros(shape, dtype=torch.float64, device="cuda")
-    print(f"[bench] {precision}: warmup {args.warmup} sweeps", file=sys.stderr, flush=True)
-    if args.warmup > 0:
-        ms.ms_solve(h, b, x, 0.0, m, "sync", max_sweeps=args.warmup, precision=precision)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st = ms.ms_solve(h, b, x, 0.0, m, "sync", max_sweeps=args.steps, precision=precision)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    sec = t1 - t0
-    print(f"[bench] {precision}: {args.steps} sweeps in {sec:.3f} s", file=sys.stderr, flush=True)
-    # per-kernel event timing in a separate, shorter run (events perturb a little)
-    prof = ms.ms_solve(h, b, x, 0.0, m, "sync", max_sweeps=max(2, min(args.steps, 5)),
-                       precision=precision, profile=True)
-    kb = kernel_bytes(m, T)
-    per_class_bytes = {}
-    for name, by in kb:
-        per_class_bytes.setdefault(name, []).append(by)
-    kernels = {}
-    for name, lst in per_class_bytes.items():
+CG_BYTES = {"stencil": 24, "update": 40}   # FP64 global CG, per unknown per iteration
+
+
+def per_kernel(prof, N, byte_lists, extra=None):
+    out = {}
+    for name, lst in byte_lists.items():
         launches = prof.kernel_launches.get(name, 0)
         ms_tot = prof.kernel_ms.get(name, 0.0)
         if launches == 0 or ms_tot <= 0:
             continue
-        # bytes of all launches of this class in the profiled run: each sweep
-        # runs the class's per-cell byte list over every unknown
-        sweeps_prof = prof.sweeps
-        bytes_tot = sum(lst) * N * sweeps_prof
-        if name == "resid":
-            bytes_tot += 16 * N      # residual-only check of the final iterate
-        kernels[name] = {
-            "launches": launches,
-            "avg_us": 1e3 * ms_tot / launches,
-            "total_ms": ms_tot,
-            "GBps": bytes_tot / (ms_tot * 1e-3) / 1e9,
-            "bytes_per_unknown": lst,
-        }
-    res = {
-        "precision": precision,
-        "sweeps": st.sweeps,
-        "seconds": sec,
-        "ms_per_sweep": 1e3 * sec / args.steps,
-        "GBps": sweep_bytes(m, T) * N * args.steps / sec / 1e9,
-        "bytes_per_unknown_sweep": sweep_bytes(m, T),
-        "model_GBps": model_sweep_bytes(m, precision == "mixed") * N * args.steps / sec / 1e9,
-        "unknown_iters_per_s": N * m * args.steps / sec,
-        "kernels": kernels,
-    }
+        bytes_tot = sum(lst) * N * prof.sweeps + (extra or {}).get(name, 0)
+        out[name] = {"launches": launches, "avg_us": round(1e3 * ms_tot / launches, 2),
+                     "total_ms": round(ms_tot, 3),
+                     "GBps": round(bytes_tot / (ms_tot * 1e-3) / 1e9, 1),
+                     "bytes_per_unknown": lst}
+    return out
+
+
+def run_mode(args, torch, ms, w, mode: str, oracle_check):
+    kind, prec = mode.split("-")
+    shape, cuts = w["shape"], w["cuts"]
+    N = shape[0] * shape[1] * shape[2]
+    m = args.m
+    T = 4 if prec == "mixed" else 8
+    precision = "mixed" if prec == "mixed" else "fp64"
+    b = torch.from_numpy(w["b"]).to("cuda")
+    h = ms.ms_create(shape, cuts=[list(map(int, c)) for c in cuts], faces=None)
+    x = torch.zeros(shape, dtype=torch.float64, device="cuda")
+
+    def step(k, **kw):
+        if kind == "cg":
+            return ms.ms_cg(h, b, x, 0.0, k, **kw)
+        return ms.ms_solve(h, b, x, 0.0, m, kind, max_sweeps=k, precision=precision, **kw)
+
+    log(f"{mode}: warmup {args.warmup}")
+    if args.warmup > 0:
+        step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = step(args.steps)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    log(f"{mode}: {args.steps} steps in {sec:.3f} s")
+    res = {"mode": mode, "steps": args.steps, "seconds": round(sec, 4),
+           "ms_per_step": round(1e3 * sec / args.steps, 4)}
+    if kind == "cg":
+        bpu = sum(CG_BYTES.values())
+        res["GBps"] = round(bpu * N * args.steps / sec / 1e9, 1)
+        res["bytes_per_unknown_step"] = bpu
+    else:
+        res["GBps"] = round(sweep_bytes(m, T) * N * args.steps / sec / 1e9, 1)
+        res["bytes_per_unknown_step"] = sweep_bytes(m, T)
+        res["model_GBps"] = round(model_sweep_bytes(m, T == 4) * N * args.steps / sec / 1e9, 1)
+        res["unknown_iters_per_s"] = N * m * args.steps / sec
+    if kind == "async":
+        res["max_staleness_seen"] = st.max_staleness_seen
+    if kind == "sync" or kind == "cg":
+        prof = step(max(2, min(args.steps, 5)), profile=True)
+        if kind == "sync":
+            lists = {}
+            for name, by in kernel_bytes(m, T):
+                lists.setdefault(name, []).append(by)
+            res["kernels"] = per_kernel(prof, N, lists, extra={"resid": 16 * N})
+        else:
+            res["kernels"] = per_kernel(prof, N, {k: [v] for k, v in CG_BYTES.items()})
     if args.full_solve:
         x.zero_()
-        print(f"[bench] {precision}: full solve to {w['tol']}", file=sys.stderr, flush=True)
+        log(f"{mode}: solve to {w['tol']}")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        fs = ms.ms_solve(h, b, x, w["tol"], m, "sync", precision=precision)
+        if kind == "cg":
+            fs = ms.ms_cg(h, b, x, w["tol"], 100000)
+            total = fs.sweeps
+        else:
+            # in chunks so progress is printed; a sweep resumed from x is the
+            # same sweep (the whole outer state is x)
+            total = 0
+            while True:
+                fs = ms.ms_solve(h, b, x, w["tol"], m, kind, precision=precision,
+                                 max_sweeps=args.chunk, raise_on_error=False)
+                total += fs.sweeps
+                if fs.status == ms.MS_OK:
+                    break
+                if fs.status != ms.MS_ERR_NOT_CONVERGED or total > 200000:
+                    raise RuntimeError(f"{mode}: solve failed with status {fs.status}")
+                log(f"{mode}: {total} sweeps, residual {fs.rel_residual:.3e}, "
+                    f"{time.perf_counter() - t0:.1f} s")
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
+        res["time_to_tol_s"] = round(time.perf_counter() - t0, 3)
+        res["sweeps_to_tol"] = total
         rel, _ = ms.ms_residual(h, b, x)
-        res["time_to_tol_s"] = t1 - t0
-        res["sweeps_to_tol"] = fs.sweeps
-        res["final_rel_residual"] = rel
+        res["final_rel_residual_gpu"] = rel
+        if oracle_check is not None:
+            res["final_rel_residual_oracle"] = oracle_check(x.cpu().numpy())
+        log(f"{mode}: {total} sweeps, {res['time_to_tol_s']} s, residual {rel:.3e}")
     ms.ms_destroy(h)
     del x, b
     torch.cuda.empty_cache()
     return res
 
 
-def cpu_baseline(w, m: int, sweeps: int):
+def cpu_baseline(o, beff, w, m: int, sweeps: int):
     import numpy as np
-
-    import oracle
-    o = oracle.load()
     shape, cuts = w["shape"], w["cuts"]
     N = shape[0] * shape[1] * shape[2]
-    beff = o.lift_bc(w["b"], [None] * 6)
-    x0 = np.zeros(shape)
-    print(f"[bench] cpu oracle: {sweeps} FP64 sweeps on {o.num_threads()} threads",
-          file=sys.stderr, flush=True)
+    log(f"cpu oracle: {sweeps} FP64 sweeps on {o.num_threads()} threads")
     t0 = time.perf_counter()
-    st, x, sw, inner, hist = o.block_jacobi(beff, x0, cuts, tol=0.0, m=m, max_sweeps=sweeps)
+    o.block_jacobi(beff, np.zeros(shape), cuts, tol=0.0, m=m, max_sweeps=sweeps)
     sec = time.perf_counter() - t0
     return {
-        "value": sweep_bytes(m, 8) * N * sweeps / sec / 1e9,
+        "value": round(sweep_bytes(m, 8) * N * sweeps / sec / 1e9, 2),
         "unit": "GB/s",
         "cores": o.num_threads(),
         "kind": "oracle",
-        "sample": f"{sweeps} FP64 sweeps of the full {shape[0]}^3 workload (m={m}), "
-                  f"{sec:.2f} s, {1e3 * sec / sweeps:.0f} ms per sweep",
-        "ms_per_sweep": 1e3 * sec / sweeps,
+        "sample": f"{sweeps} FP64 synchronous sweeps of the full {shape[0]}^3 workload "
+                  f"(m={m}): {sec:.2f} s, {1e3 * sec / sweeps:.0f} ms per sweep",
+        "ms_per_sweep": round(1e3 * sec / sweeps, 1),
     }
 
 
@@ -167,15 +197,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="bumps512")
     ap.add_argument("--m", type=int, default=10)
-    ap.add_argument("--precision", default="both", choices=["both", "mixed", "fp64"])
+    ap.add_argument("--modes", default="sync-mixed,sync-fp64,async-mixed,cg-fp64")
     ap.add_argument("--full-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=4)
+    ap.add_argument("--chunk", type=int, default=400, help="sweeps per call in --full-solve")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for hardware counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               f"(asked for --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
+    modes = [m for m in args.modes.split(",") if m]
+    for m in modes:
+        if m not in ALL_MODES:
+            sys.exit(f"unknown mode {m}; choose from {ALL_MODES}")
 
     import torch
     from paper_2009_12638_amd import inputs, ms
@@ -184,42 +221,58 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     ms.lib()
-    print(f"[bench] building inputs for {args.workload}", file=sys.stderr, flush=True)
+    if args.copy_probe:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: 2 copies of 1 GiB")
+        del src, dst
+    log(f"building inputs for {args.workload}")
     w = inputs.workload(args.workload)
-    precs = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
-    results = {p: run_gpu(args, torch, ms, inputs, w, p) for p in precs}
-    head = results[precs[0]]
-    # roofline of the dominant kernel (largest total time) of the headline run
-    dom_name, dom = max(head["kernels"].items(), key=lambda kv: kv[1]["total_ms"])
-    roof = {
-        "bound": "hbm",
-        "kernel": f"k_{dom_name} ({head['precision']})",
-        "achieved": round(dom["GBps"], 1),
-        "peak": HBM_PEAK_GBPS,
-        "unit": "GB/s",
-        "frac": round(dom["GBps"] / HBM_PEAK_GBPS, 4),
-        "traffic": None,
-    }
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(w, args.m, args.cpu_sweeps)
+    o = beff = None
+    if not args.no_cpu or args.full_solve:
+        import numpy as np
+        import oracle
+        o = oracle.load()
+        beff = o.lift_bc(w["b"], [None] * 6)
+        nbeff = float(np.linalg.norm(beff))
+
+        def oracle_check(xh):
+            return o.residual(beff, xh) / nbeff
+    else:
+        oracle_check = None
+    results = {mo: run_mode(args, torch, ms, w, mo, oracle_check if args.full_solve else None)
+               for mo in modes}
+    head = results[modes[0]]
+    roof = None
+    if "kernels" in head and head["kernels"]:
+        dom_name, dom = max(head["kernels"].items(), key=lambda kv: kv[1]["total_ms"])
+        roof = {"bound": "hbm", "kernel": f"k_{dom_name} ({head['mode']})",
+                "achieved": dom["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(dom["GBps"] / HBM_PEAK_GBPS, 4), "traffic": None}
+    cpu = None if args.no_cpu else cpu_baseline(o, beff, w, args.m, args.cpu_sweeps)
     shape = w["shape"]
+    kind, prec = modes[0].split("-")
     line = {
         "metric": METRIC,
-        "value": round(head["GBps"], 1),
+        "value": head["GBps"],
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(head["ms_per_sweep"], 4),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if head["precision"] == "mixed" else "f64",
+        "dtype": "f32+f64" if prec == "mixed" else "f64",
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: {shape[0]}x{shape[1]}x{shape[2]} Poisson, "
-                        f"{len(w['cuts'][0]) - 1}^3 blocks, m={args.m}, sync sweeps",
+                        f"{len(w['cuts'][0]) - 1}^3 blocks of "
+                        f"{shape[0] // (len(w['cuts'][0]) - 1)}^3, m={args.m}, "
+                        f"{kind} sweeps, {prec}",
             "step": "one outer sweep",
             "unknowns": shape[0] * shape[1] * shape[2],
         },

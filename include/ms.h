@@ -100,6 +100,8 @@ typedef struct {
     int32_t use_graph;    /* sync: 1 = replay sweeps from a captured HIP graph
                              (default 1) */
     int32_t rows;         /* y rows each thread owns: 1, 2 or 4 (0 = automatic) */
+    int32_t workers;      /* async: persistent workgroups, each sweeping one block
+                             at a time (0 = automatic) */
 } ms_opts;
 
 /* Kernel classes reported by the profile counters of ms_stats. */

@@ -565,7 +565,8 @@ ms_status solve_async(ms_handle *h, const double *b, double *x, double tol, int 
     int per_cu = 0;
     HIPCHK(h, ms::async_occupancy<T>(vz, rows, &per_cu));
     if (per_cu < 1) return fail(h, MS_ERR_HIP, "asynchronous kernel cannot be resident");
-    const int grid = (int)std::min<long long>(h->nblocks, (long long)per_cu * h->num_cu);
+    int grid = (int)std::min<long long>(h->nblocks, (long long)per_cu * h->num_cu);
+    if (o.workers > 0) grid = std::min(grid, o.workers);
     const int nbk = h->nblocks;
     hipLaunchKernelGGL(k_async_reset, dim3((nbk + 255) / 256), dim3(256), 0, st, h->version_d,
                        h->claim_d, h->board_d, nbk, h->finished_d, 0, h->ctrl, 1);
@@ -793,6 +794,7 @@ void ms_default_opts(ms_opts *o) {
     o->profile = 0;
     o->use_graph = 1;
     o->rows = 0;
+    o->workers = 0;
 }
 
 const char *ms_status_string(ms_status s) {

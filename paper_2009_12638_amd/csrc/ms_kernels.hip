@@ -138,6 +138,18 @@ __device__ __forceinline__ T from_left(T v) { return __shfl_up(v, 1, 64); }
 template <typename T>
 __device__ __forceinline__ T from_right(T v) { return __shfl_down(v, 1, 64); }
 
+// Workgroups of a launch are dispatched to the XCDs in turn (workgroup w to
+// XCD w % 8).  Hand each XCD one contiguous range of tiles instead, so the
+// tiles of a block and of its z and y neighbours share that XCD's L2 and
+// the halo rows and planes they exchange are L2 hits.  A bijection on
+// [0, n) for any n; correctness does not depend on the dispatch order.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile(int w, int n) {
+    const int q = n / kXcds, rem = n % kXcds;
+    const int c = w % kXcds, k = w / kXcds;
+    return c * q + min(c, rem) + k;
+}
+
 // ----------------------------------------------------------------------
 // tile bodies
 // ----------------------------------------------------------------------
@@ -160,6 +172,8 @@ __device__ __forceinline__ void tile_resid(const Geom &g, const Tile &t, long lo
     const bool zp_sh = t.zc < t.tpr - 1 && t.lane < 63;
     const bool ym_ld = t.nrows > 0 && J0 > 0;              // row above the group
     const bool yp_ld = t.nrows > 0 && J0 + t.nrows < ny;   // row below the group
+    const bool ym_sh = t.j0 > 0 && t.lane >= t.tpr;         // ... held by a lane of this wave
+    const bool yp_sh = t.j0 + t.nrows < t.B.by && t.lane + t.tpr < 64;
     double xm[R][VZ], xc[R][VZ], xp[R][VZ];
 #pragma unroll
     for (int rr = 0; rr < R; rr++)
@@ -180,12 +194,34 @@ __device__ __forceinline__ void tile_resid(const Geom &g, const Tile &t, long lo
         double ym[VZ], yp[VZ];
 #pragma unroll
         for (int v = 0; v < VZ; v++) { ym[v] = 0.0; yp[v] = 0.0; }
+        // rows next to the group: from the neighbouring group tpr lanes away
+        // when it is in this wavefront and in this block, else from memory
+        double ysu[VZ], ysd[VZ];
+#pragma unroll
+        for (int v = 0; v < VZ; v++) {
+            ysu[v] = __shfl_up(xc[R - 1][v], t.tpr, 64);
+            ysd[v] = __shfl_down(xc[0][v], t.tpr, 64);
+        }
         if (x) {
 #pragma unroll
             for (int rr = 0; rr < R; rr++)
                 if (rr < t.nrows && I + 1 < nx) vload<double, VZ>(x + gidx(I + 1, rr), xp[rr]);
-            if (ym_ld) vload<double, VZ>(x + gidx(I, -1), ym);
-            if (yp_ld) vload<double, VZ>(x + gidx(I, t.nrows), yp);
+            if (ym_ld) {
+                if (ym_sh) {
+#pragma unroll
+                    for (int v = 0; v < VZ; v++) ym[v] = ysu[v];
+                } else {
+                    vload<double, VZ>(x + gidx(I, -1), ym);
+                }
+            }
+            if (yp_ld) {
+                if (yp_sh) {
+#pragma unroll
+                    for (int v = 0; v < VZ; v++) yp[v] = ysd[v];
+                } else {
+                    vload<double, VZ>(x + gidx(I, t.nrows), yp);
+                }
+            }
         }
 #pragma unroll
         for (int rr = 0; rr < R; rr++) {
@@ -261,6 +297,7 @@ __device__ __forceinline__ T tile_stencil(const Tile &t, long long goff,
     const bool zm_sh = zm_in && t.lane > 0, zp_sh = zp_in && t.lane < 63;
     const bool ym_ld = t.nrows > 0 && t.j0 > 0;
     const bool yp_ld = t.nrows > 0 && t.j0 + t.nrows < by;
+    const bool ym_sh = t.lane >= t.tpr, yp_sh = t.lane + t.tpr < 64;
     auto pv = [&](long long o, T(&out)[VZ]) {
         vload<T, VZ>(r + o, out);
         if (use_old) {
@@ -293,11 +330,31 @@ __device__ __forceinline__ T tile_stencil(const Tile &t, long long goff,
         T ym[VZ], yp[VZ];
 #pragma unroll
         for (int v = 0; v < VZ; v++) { ym[v] = T(0); yp[v] = T(0); }
+        T ysu[VZ], ysd[VZ];
+#pragma unroll
+        for (int v = 0; v < VZ; v++) {
+            ysu[v] = __shfl_up(pc[R - 1][v], t.tpr, 64);
+            ysd[v] = __shfl_down(pc[0][v], t.tpr, 64);
+        }
 #pragma unroll
         for (int rr = 0; rr < R; rr++)
             if (rr < t.nrows && i + 1 < bx) pv(o + P + (long long)rr * bz, pp[rr]);
-        if (ym_ld) pv(o - bz, ym);
-        if (yp_ld) pv(o + (long long)t.nrows * bz, yp);
+        if (ym_ld) {
+            if (ym_sh) {
+#pragma unroll
+                for (int v = 0; v < VZ; v++) ym[v] = ysu[v];
+            } else {
+                pv(o - bz, ym);
+            }
+        }
+        if (yp_ld) {
+            if (yp_sh) {
+#pragma unroll
+                for (int v = 0; v < VZ; v++) yp[v] = ysd[v];
+            } else {
+                pv(o + (long long)t.nrows * bz, yp);
+            }
+        }
 #pragma unroll
         for (int rr = 0; rr < R; rr++) {
             const T sl = from_left(pc[rr][VZ - 1]);
@@ -339,6 +396,7 @@ __device__ __forceinline__ T tile_update(const Tile &t, long long goff, T *__res
     const bool zm_sh = zm_in && t.lane > 0, zp_sh = zp_in && t.lane < 63;
     const bool ym_ld = t.nrows > 0 && t.j0 > 0;
     const bool yp_ld = t.nrows > 0 && t.j0 + t.nrows < by;
+    const bool ym_sh = t.lane >= t.tpr, yp_sh = t.lane + t.tpr < 64;
     T pm[R][VZ], pc[R][VZ], pp[R][VZ];
 #pragma unroll
     for (int rr = 0; rr < R; rr++)
@@ -357,11 +415,31 @@ __device__ __forceinline__ T tile_update(const Tile &t, long long goff, T *__res
         T ym[VZ], yp[VZ];
 #pragma unroll
         for (int v = 0; v < VZ; v++) { ym[v] = T(0); yp[v] = T(0); }
+        T ysu[VZ], ysd[VZ];
+#pragma unroll
+        for (int v = 0; v < VZ; v++) {
+            ysu[v] = __shfl_up(pc[R - 1][v], t.tpr, 64);
+            ysd[v] = __shfl_down(pc[0][v], t.tpr, 64);
+        }
 #pragma unroll
         for (int rr = 0; rr < R; rr++)
             if (rr < t.nrows && i + 1 < bx) vload<T, VZ>(p + o + P + (long long)rr * bz, pp[rr]);
-        if (ym_ld) vload<T, VZ>(p + o - bz, ym);
-        if (yp_ld) vload<T, VZ>(p + o + (long long)t.nrows * bz, yp);
+        if (ym_ld) {
+            if (ym_sh) {
+#pragma unroll
+                for (int v = 0; v < VZ; v++) ym[v] = ysu[v];
+            } else {
+                vload<T, VZ>(p + o - bz, ym);
+            }
+        }
+        if (yp_ld) {
+            if (yp_sh) {
+#pragma unroll
+                for (int v = 0; v < VZ; v++) yp[v] = ysd[v];
+            } else {
+                vload<T, VZ>(p + o + (long long)t.nrows * bz, yp);
+            }
+        }
 #pragma unroll
         for (int rr = 0; rr < R; rr++) {
             const T sl = from_left(pc[rr][VZ - 1]);
@@ -448,7 +526,7 @@ __global__ __launch_bounds__(kThreads) void k_resid(Geom g, int t0, long long go
                                                     T *__restrict__ r, double *__restrict__ p64,
                                                     T *__restrict__ pT, const Ctrl *ctrl) {
     if (ctrl && ctrl->done) return;
-    const int tile = t0 + blockIdx.x;
+    const int tile = t0 + xcd_tile(blockIdx.x, gridDim.x);
     const Tile t = decode_tile<VZ, R>(g, tile, threadIdx.x);
     double acc64 = 0.0;
     T accT = T(0);
@@ -473,7 +551,7 @@ __global__ __launch_bounds__(kThreads) void k_stencil(Geom g, int t0, long long 
                                                       int *active, int iter, double inner_tol,
                                                       Ctrl *ctrl) {
     if (ctrl->done) return;
-    const int tile = t0 + blockIdx.x;
+    const int tile = t0 + xcd_tile(blockIdx.x, gridDim.x);
     const Tile t = decode_tile<VZ, R>(g, tile, threadIdx.x);
     const T rho = tiles_sum(prho_cur, t.B.tile0, t.B.ntiles);
     bool act;
@@ -509,7 +587,7 @@ __global__ __launch_bounds__(kThreads) void k_update(Geom g, int t0, long long g
                                                      int iter, const double *__restrict__ xa,
                                                      double *__restrict__ xb, Ctrl *ctrl) {
     if (ctrl->done) return;
-    const int tile = t0 + blockIdx.x;
+    const int tile = t0 + xcd_tile(blockIdx.x, gridDim.x);
     const Tile t = decode_tile<VZ, R>(g, tile, threadIdx.x);
     bool act = active[t.b] != 0;
     T alpha = T(0);
@@ -565,7 +643,7 @@ __global__ __launch_bounds__(kThreads) void k_gcg_stencil(Geom g, const double *
                                                           const double *scal, int iter,
                                                           const Ctrl *ctrl) {
     if (ctrl->done) return;
-    const int tile = blockIdx.x;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const Tile t = decode_tile<VZ, R>(g, tile, threadIdx.x);
     const double beta = iter > 0 ? scal[2] : 0.0;
     const double acc = tile_stencil<double, VZ, R>(t, 0, r, pold, pnew, beta, iter > 0);
@@ -580,7 +658,7 @@ __global__ __launch_bounds__(kThreads) void k_gcg_update(Geom g, double *__restr
                                                          double *__restrict__ prho,
                                                          const double *scal, const Ctrl *ctrl) {
     if (ctrl->done) return;
-    const int tile = blockIdx.x;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const Tile t = decode_tile<VZ, R>(g, tile, threadIdx.x);
     const double acc = tile_update<double, double, VZ, R>(t, 0, r, p, x, scal[1], true);
     const double s = wg_allsum<double, kThreads>(acc);

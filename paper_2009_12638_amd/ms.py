@@ -48,7 +48,8 @@ class ms_opts(C.Structure):
                 ("staleness", C.c_int32), ("precision", C.c_int32),
                 ("stream", C.c_void_p), ("check_every", C.c_int32),
                 ("group_blocks", C.c_int32), ("x_chunk", C.c_int32),
-                ("profile", C.c_int32), ("use_graph", C.c_int32), ("rows", C.c_int32)]
+                ("profile", C.c_int32), ("use_graph", C.c_int32), ("rows", C.c_int32),
+                ("workers", C.c_int32)]
 
 
 class ms_stats(C.Structure):
@@ -231,7 +232,7 @@ class Stats:
 
 def _opts(precision="fp64", max_sweeps=100000, inner_tol=0.0, staleness=2, stream=None,
           check_every=0, group_blocks=0, x_chunk=0, profile=False, use_graph=True,
-          rows=0) -> ms_opts:
+          rows=0, workers=0) -> ms_opts:
     o = ms_default_opts()
     o.max_sweeps = int(max_sweeps)
     o.inner_tol = float(inner_tol)
@@ -245,6 +246,7 @@ def _opts(precision="fp64", max_sweeps=100000, inner_tol=0.0, staleness=2, strea
     o.profile = 1 if profile else 0
     o.use_graph = 1 if use_graph else 0
     o.rows = int(rows)
+    o.workers = int(workers)
     return o
 
 

@@ -38,7 +38,7 @@ def test_struct_sizes_match_c_layout():
     assert C.sizeof(ms.ms_grid) == 24
     assert C.sizeof(ms.ms_blocks) == 12 + 4 + 24
     assert C.sizeof(ms.ms_bc) == 48
-    assert C.sizeof(ms.ms_opts) == 4 + 4 + 8 + 4 + 4 + 8 + 4 * 5 + 4
+    assert C.sizeof(ms.ms_opts) == 4 + 4 + 8 + 4 + 4 + 8 + 4 * 5 + 4 + 4 + 4
     assert C.sizeof(ms.ms_stats) == 4 + 4 + 8 + 8 + 8 + 4 + 4 + 4 + 4 + 8 + 4 + 4 + 64 + 64
 
 
