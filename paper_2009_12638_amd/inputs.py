@@ -101,6 +101,21 @@ def gaussian_bumps(shape, seed_bumps: int, seed_noise: int, nbumps: int = 8,
     return out
 
 
+def smooth_field(shape, seed: int, kmax: int = 3) -> np.ndarray:
+    """Seeded smooth target: sum over a,b,c <= kmax of N(0,1)/(a^2+b^2+c^2)
+    sin(a pi x) sin(b pi y) sin(c pi z) on the interior points."""
+    rng = np.random.default_rng(seed)
+    X, Y, Z = (axis_coords(n) for n in shape)
+    out = np.zeros(shape)
+    for a in range(1, kmax + 1):
+        for b in range(1, kmax + 1):
+            for c in range(1, kmax + 1):
+                w = rng.standard_normal() / (a * a + b * b + c * c)
+                out += w * np.einsum("i,j,k->ijk", np.sin(a * np.pi * X), np.sin(b * np.pi * Y),
+                                     np.sin(c * np.pi * Z))
+    return out
+
+
 def random_faces(nx: int, ny: int, nz: int, seed: int, lo=-1.0, hi=1.0):
     """Boundary data g ~ U(lo, hi) per face node, faces drawn in order."""
     rng = np.random.default_rng(seed)
