@@ -33,7 +33,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time-to-1e-8 residual & stencil/CG HBM GB/s, 512^3 Laplace; mixed vs plain FP64"
 HBM_PEAK_GBPS = 8000.0
-ALL_MODES = ["sync-mixed", "sync-fp64", "async-mixed", "async-fp64", "cg-fp64"]
+ALL_MODES = ["sync-mixed", "sync-fp64", "async-mixed", "async-fp64", "cg-fp64",
+             "batch-mixed", "batch-fp64"]
+BATCH_WORKLOAD = "uneven384"   # batched modes: 16 right-hand sides, uneven blocks
 
 
 def log(*a):
@@ -96,12 +98,25 @@ def run_mode(args, torch, ms, w, mode: str, oracle_check):
     T = 4 if prec == "mixed" else 8
     precision = "mixed" if prec == "mixed" else "fp64"
     b = torch.from_numpy(w["b"]).to("cuda")
+    nrhs = b.shape[0] if kind == "batch" else 1
     h = ms.ms_create(shape, cuts=[list(map(int, c)) for c in cuts], faces=None)
-    x = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+    tuned = {}
+    if kind == "batch":
+        ms.ms_reserve(h, nrhs)
+        if args.autotune:
+            from paper_2009_12638_amd import tune
+            log(f"{mode}: autotuning tiles and m")
+            tuned = tune.autotune(shape, cuts, b, precision=precision, refresh=True)
+            m = tuned["inner_iters"]
+    tile_kw = {k: tuned[k] for k in ("rows", "x_chunk") if k in tuned}
 
     def step(k, **kw):
         if kind == "cg":
             return ms.ms_cg(h, b, x, 0.0, k, **kw)
+        if kind == "batch":
+            return ms.ms_solve_batch(h, b, x, 0.0, m, max_sweeps=k, precision=precision,
+                                     **tile_kw, **kw)[0]
         return ms.ms_solve(h, b, x, 0.0, m, kind, max_sweeps=k, precision=precision, **kw)
 
     log(f"{mode}: warmup {args.warmup}")
@@ -114,25 +129,27 @@ def run_mode(args, torch, ms, w, mode: str, oracle_check):
     sec = time.perf_counter() - t0
     log(f"{mode}: {args.steps} steps in {sec:.3f} s")
     res = {"mode": mode, "steps": args.steps, "seconds": round(sec, 4),
-           "ms_per_step": round(1e3 * sec / args.steps, 4)}
+           "ms_per_step": round(1e3 * sec / args.steps, 4), "nrhs": nrhs, "inner_iters": m}
+    if tuned:
+        res["autotuned"] = {k: tuned[k] for k in ("rows", "x_chunk", "inner_iters")}
     if kind == "cg":
         bpu = sum(CG_BYTES.values())
         res["GBps"] = round(bpu * N * args.steps / sec / 1e9, 1)
         res["bytes_per_unknown_step"] = bpu
     else:
-        res["GBps"] = round(sweep_bytes(m, T) * N * args.steps / sec / 1e9, 1)
+        res["GBps"] = round(sweep_bytes(m, T) * N * nrhs * args.steps / sec / 1e9, 1)
         res["bytes_per_unknown_step"] = sweep_bytes(m, T)
-        res["model_GBps"] = round(model_sweep_bytes(m, T == 4) * N * args.steps / sec / 1e9, 1)
-        res["unknown_iters_per_s"] = N * m * args.steps / sec
+        res["model_GBps"] = round(model_sweep_bytes(m, T == 4) * N * nrhs * args.steps / sec / 1e9, 1)
+        res["unknown_iters_per_s"] = N * nrhs * m * args.steps / sec
     if kind == "async":
         res["max_staleness_seen"] = st.max_staleness_seen
-    if kind == "sync" or kind == "cg":
+    if kind in ("sync", "cg", "batch"):
         prof = step(max(2, min(args.steps, 5)), profile=True)
-        if kind == "sync":
+        if kind in ("sync", "batch"):
             lists = {}
             for name, by in kernel_bytes(m, T):
                 lists.setdefault(name, []).append(by)
-            res["kernels"] = per_kernel(prof, N, lists, extra={"resid": 16 * N})
+            res["kernels"] = per_kernel(prof, N * nrhs, lists, extra={"resid": 16 * N * nrhs})
         else:
             res["kernels"] = per_kernel(prof, N, {k: [v] for k, v in CG_BYTES.items()})
     if args.full_solve:
@@ -143,6 +160,11 @@ def run_mode(args, torch, ms, w, mode: str, oracle_check):
         if kind == "cg":
             fs = ms.ms_cg(h, b, x, w["tol"], 100000)
             total = fs.sweeps
+        elif kind == "batch":
+            sts = ms.ms_solve_batch(h, b, x, w["tol"], m, precision=precision, **tile_kw)
+            fs = sts[0]
+            total = max(t.sweeps for t in sts)
+            res["sweeps_to_tol_per_rhs"] = [t.sweeps for t in sts]
         else:
             # in chunks so progress is printed; a sweep resumed from x is the
             # same sweep (the whole outer state is x)
@@ -160,10 +182,14 @@ def run_mode(args, torch, ms, w, mode: str, oracle_check):
         torch.cuda.synchronize()
         res["time_to_tol_s"] = round(time.perf_counter() - t0, 3)
         res["sweeps_to_tol"] = total
-        rel, _ = ms.ms_residual(h, b, x)
+        if kind == "batch":
+            rels = [ms.ms_residual(h, b[k].contiguous(), x[k].contiguous())[0] for k in range(nrhs)]
+            rel = max(rels)
+        else:
+            rel, _ = ms.ms_residual(h, b, x)
+            if oracle_check is not None:
+                res["final_rel_residual_oracle"] = oracle_check(x.cpu().numpy())
         res["final_rel_residual_gpu"] = rel
-        if oracle_check is not None:
-            res["final_rel_residual_oracle"] = oracle_check(x.cpu().numpy())
         log(f"{mode}: {total} sweeps, {res['time_to_tol_s']} s, residual {rel:.3e}")
     ms.ms_destroy(h)
     del x, b
@@ -202,6 +228,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=4)
     ap.add_argument("--chunk", type=int, default=400, help="sweeps per call in --full-solve")
+    ap.add_argument("--autotune", action="store_true",
+                    help="batched modes: pick tile shape and m with the autotuner first")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for hardware counters)")
     args = ap.parse_args()
@@ -243,8 +271,17 @@ def main():
             return o.residual(beff, xh) / nbeff
     else:
         oracle_check = None
-    results = {mo: run_mode(args, torch, ms, w, mo, oracle_check if args.full_solve else None)
-               for mo in modes}
+    results = {}
+    wb = None
+    for mo in modes:
+        if mo.startswith("batch"):
+            if wb is None:
+                log(f"building inputs for {BATCH_WORKLOAD}")
+                wb = inputs.workload(BATCH_WORKLOAD)
+            results[mo] = run_mode(args, torch, ms, wb, mo, None)
+        else:
+            results[mo] = run_mode(args, torch, ms, w, mo,
+                                   oracle_check if args.full_solve else None)
     head = results[modes[0]]
     roof = None
     if "kernels" in head and head["kernels"]:

@@ -174,6 +174,25 @@ ms_status ms_solve(ms_handle *h, const double *b, double *x, double tol,
                    int32_t inner_iters, ms_mode mode, const ms_opts *opts,
                    ms_stats *stats);
 
+/* Make room for solving nrhs right-hand sides at once with ms_solve_batch
+ * (allocates per-right-hand-side device buffers; every other call keeps
+ * working).  Errors: MS_ERR_ARG (nrhs outside [1, 4096]), MS_ERR_NOMEM (the
+ * handle keeps its previous capacity). */
+ms_status ms_reserve(ms_handle *h, int32_t nrhs);
+
+/* Synchronous solve of nrhs independent right-hand sides with the same grid,
+ * blocks and boundary data in the same kernel launches (each launch covers
+ * every block of every right-hand side; Section 3's sweep applied to each).
+ * b and x hold the right-hand sides and iterates one after another
+ * ([nrhs][nx][ny][nz], device, FP64).  Each right-hand side stops on its own
+ * test (the others keep going).  stats: NULL or an array of nrhs entries.
+ * Needs ms_reserve(h, n >= nrhs) first.  Returns MS_OK when every right-hand
+ * side converged, else the first failure status.  mode must be MS_SYNC
+ * (MS_ERR_UNSUPPORTED otherwise). */
+ms_status ms_solve_batch(ms_handle *h, int32_t nrhs, const double *b, double *x, double tol,
+                         int32_t inner_iters, ms_mode mode, const ms_opts *opts,
+                         ms_stats *stats);
+
 /* True FP64 relative residual ||b_eff - A x||_2 / ||b_eff||_2 (Section 2.1
  * stopping quantity; Section 3 root-sum-square of block residuals).  b, x:
  * device FP64.  *rel_out (host) receives the value (0 if ||b_eff|| = 0);

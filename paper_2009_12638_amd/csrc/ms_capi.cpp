@@ -31,6 +31,7 @@ using ms::Ctrl;
 using ms::Faces;
 using ms::Geom;
 using ms::AsyncState;
+using ms::Batch;
 
 namespace {
 
@@ -77,6 +78,13 @@ struct ms_handle {
     int *version_d = nullptr, *claim_d = nullptr, *nbr_d = nullptr, *finished_d = nullptr;
     double *board_d = nullptr;
     int num_cu = 0;
+    // right-hand sides the per-RHS buffers hold (ms_reserve grows it)
+    int rhs_cap = 1;
+    // replayed sweep pairs
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    unsigned char graph_key[128] = {0};
     // profiling
     std::vector<hipEvent_t> ev;
     std::vector<int> ev_class;
@@ -218,6 +226,9 @@ void free_all(ms_handle *h) {
     for (int t = 0; t < 6; t++)
         if (h->faces_d[t]) (void)hipFree(h->faces_d[t]);
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
 }
 
 // ---- profiling -------------------------------------------------------
@@ -284,6 +295,18 @@ Bufs<T> bufs(ms_handle *h) {
     return B;
 }
 
+// Strides of the per-right-hand-side arrays (a right-hand side owns N
+// elements of every vector buffer, tiles_cap partial slots and nblocks flags).
+Batch batch_of(const ms_handle *h, int nrhs) {
+    Batch bt;
+    bt.nt = 0;
+    bt.nrhs = nrhs;
+    bt.vs = h->N;
+    bt.ps = h->tiles_cap;
+    bt.bs = h->nblocks;
+    return bt;
+}
+
 std::vector<Group> make_groups(const ms_handle *h, long long cap_cells) {
     std::vector<Group> gs;
     int b = 0;
@@ -307,12 +330,12 @@ std::vector<Group> make_groups(const ms_handle *h, long long cap_cells) {
     return gs;
 }
 
-// Enqueue one sweep from xa into xb (or, final_only, just the residual check
-// of xa).
+// Enqueue one sweep of every right-hand side from xa into xb (or, final_only,
+// just the residual check of xa).
 template <typename T>
 ms_status enqueue_sweep(ms_handle *h, const std::vector<Group> &groups, const double *b,
                         const double *xa, double *xb, double tol, int m, double inner_tol,
-                        bool final_only, hipStream_t st) {
+                        bool final_only, Batch bt, hipStream_t st) {
     const Geom g = geom(h);
     const int vz = h->cur_vz;
     Bufs<T> B = bufs<T>(h);
@@ -322,7 +345,7 @@ ms_status enqueue_sweep(ms_handle *h, const std::vector<Group> &groups, const do
             Prof p(h, st, MS_K_RESID);
             HIPCHK(h, ms::launch_resid<T>(g, vz, G.t0, G.t1, G.off, b, xa, F,
                                           final_only ? nullptr : B.r, h->part64, B.pT, h->ctrl,
-                                          st));
+                                          bt, st));
         }
         if (final_only) continue;
         T *prho[3] = {B.pT, B.prA, B.prB};
@@ -337,30 +360,38 @@ ms_status enqueue_sweep(ms_handle *h, const std::vector<Group> &groups, const do
                 Prof p(h, st, MS_K_STENCIL);
                 HIPCHK(h, ms::launch_stencil<T>(g, vz, G.t0, G.t1, G.off, B.r, pold, pnew,
                                                 B.psig, cur, prev, prho[0], h->active, j,
-                                                inner_tol, h->ctrl, st));
+                                                inner_tol, h->ctrl, bt, st));
             }
             {
                 Prof p(h, st, last ? MS_K_FINAL : MS_K_UPDATE);
                 HIPCHK(h, ms::launch_update<T>(g, vz, G.t0, G.t1, G.off, B.r, pnew, B.d,
                                                B.psig, cur, next, h->active, j, last ? 1 : 0,
-                                               xa, xb, h->ctrl, st));
+                                               xa, xb, h->ctrl, bt, st));
             }
         }
     }
     {
         Prof p(h, st, MS_K_CHECK);
         HIPCHK(h, ms::launch_check(h->part64, h->ntiles, tol, final_only ? 1 : 0, h->history_d,
-                                   kHistoryCap, h->ctrl, st));
+                                   kHistoryCap, h->ctrl, bt, st));
     }
     return MS_OK;
 }
 
-__global__ void k_ctrl_init(Ctrl *c) {
-    if (threadIdx.x == 0) {
-        c->done = 0; c->status = 0; c->sweep = 0; c->final_sweep = 0;
-        c->nbeff = 0.0; c->res0 = 0.0; c->last_res = 0.0; c->inner_iters = 0ull; c->inner_snap = 0ull;
-        c->stop = 0; c->max_stale = 0; c->work_items = 0ull;
+__global__ void k_ctrl_init(Ctrl *c, int n) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) {
+        c[k].done = 0; c[k].status = 0; c[k].sweep = 0; c[k].final_sweep = 0;
+        c[k].nbeff = 0.0; c[k].res0 = 0.0; c[k].last_res = 0.0;
+        c[k].inner_iters = 0ull; c[k].inner_snap = 0ull;
+        c[k].stop = 0; c[k].max_stale = 0; c[k].work_items = 0ull;
     }
+}
+
+// A right-hand side with b_eff = 0 is solved by x = 0 before any sweep.
+__global__ void k_mark_zero_rhs(Ctrl *c, int n) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n && c[k].nbeff == 0.0) { c[k].done = 1; c[k].status = 0; c[k].final_sweep = 0; }
 }
 
 __global__ void k_fill_zero(double *x, long long n) {
@@ -377,21 +408,29 @@ ms_status zero_vec(ms_handle *h, double *x, long long n, hipStream_t st) {
     return MS_OK;
 }
 
-// ||b_eff|| into ctrl->nbeff and *out (host); resets the control block.
+// ||b_eff|| of every right-hand side into ctrl[k].nbeff and out[k] (host);
+// resets the control blocks.
 template <typename T>
-ms_status beff_norm(ms_handle *h, const double *b, hipStream_t st, double *out) {
-    hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, st, h->ctrl);
+ms_status beff_norms(ms_handle *h, const double *b, int nrhs, hipStream_t st, double *out) {
+    hipLaunchKernelGGL(k_ctrl_init, dim3((nrhs + 63) / 64), dim3(64), 0, st, h->ctrl, nrhs);
     HIPCHK(h, hipGetLastError());
     const Geom g = geom(h);
     Bufs<T> B = bufs<T>(h);
+    const Batch bt = batch_of(h, nrhs);
     HIPCHK(h, ms::launch_resid<T>(g, h->cur_vz, 0, h->ntiles, 0, b, nullptr, faces(h), nullptr,
-                                  h->part64, B.pT, nullptr, st));
-    HIPCHK(h, ms::launch_norm(h->part64, h->ntiles, h->ctrl, st));
-    Ctrl c;
-    HIPCHK(h, hipMemcpyAsync(&c, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+                                  h->part64, B.pT, nullptr, bt, st));
+    for (int k = 0; k < nrhs; k++)
+        HIPCHK(h, ms::launch_norm(h->part64 + (long long)k * h->tiles_cap, h->ntiles, h->ctrl + k, st));
+    std::vector<Ctrl> c(nrhs);
+    HIPCHK(h, hipMemcpyAsync(c.data(), h->ctrl, sizeof(Ctrl) * nrhs, hipMemcpyDeviceToHost, st));
     HIPCHK(h, hipStreamSynchronize(st));
-    *out = c.nbeff;
+    for (int k = 0; k < nrhs; k++) out[k] = c[k].nbeff;
     return MS_OK;
+}
+
+template <typename T>
+ms_status beff_norm(ms_handle *h, const double *b, hipStream_t st, double *out) {
+    return beff_norms<T>(h, b, 1, st, out);
 }
 
 // Tile choice when the caller leaves it open: the largest rows-per-thread
@@ -413,43 +452,84 @@ long long count_tiles(const ms_handle *h, int vz, int tx, int rows) {
     return n;
 }
 
-void auto_tiling(const ms_handle *h, int vz, int *tx, int *rows) {
+void auto_tiling(const ms_handle *h, int vz, int nrhs, int *tx, int *rows) {
     for (int r : {4, 2, 1})
         for (int t : {32, 16, 8, 4})
-            if (count_tiles(h, vz, t, r) >= kMinTiles) { *tx = t; *rows = r; return; }
+            if (count_tiles(h, vz, t, r) * nrhs >= kMinTiles) { *tx = t; *rows = r; return; }
     *tx = kTxMin;
     *rows = 1;
 }
 
+// A HIP graph holding two sweeps (even then odd parity) of one solve
+// configuration, replayed instead of launching the kernels one by one.
+struct GraphKey {
+    const double *b;
+    double *x;
+    double tol, inner_tol;
+    long long cap_cells;
+    int m, tsize, vz, tx, rows, nrhs;
+};
+
+void drop_graph(ms_handle *h) {
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    h->graph_exec = nullptr;
+    h->graph = nullptr;
+}
+
 template <typename T>
-ms_status solve_sync(ms_handle *h, const double *b, double *x, double tol, int m,
+ms_status sweep_pair_graph(ms_handle *h, const GraphKey &key, const std::vector<Group> &groups,
+                           const double *b, double *const X[2], double tol, int m,
+                           double inner_tol, Batch bt) {
+    if (h->graph_exec && memcmp(&h->graph_key, &key, sizeof(GraphKey)) == 0) return MS_OK;
+    drop_graph(h);
+    if (!h->cap_stream) HIPCHK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    ms_status s = enqueue_sweep<T>(h, groups, b, X[0], X[1], tol, m, inner_tol, false, bt,
+                                   h->cap_stream);
+    if (s == MS_OK)
+        s = enqueue_sweep<T>(h, groups, b, X[1], X[0], tol, m, inner_tol, false, bt, h->cap_stream);
+    hipGraph_t gr = nullptr;
+    const hipError_t e = hipStreamEndCapture(h->cap_stream, &gr);
+    if (s != MS_OK) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return s;
+    }
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamEndCapture");
+    h->graph = gr;
+    HIPCHK(h, hipGraphInstantiate(&h->graph_exec, gr, nullptr, nullptr, 0));
+    memcpy(&h->graph_key, &key, sizeof(GraphKey));
+    return MS_OK;
+}
+
+// Synchronous solve of nrhs right-hand sides stored one after another in b
+// and x (each nx*ny*nz).  stats: nrhs entries or NULL.
+template <typename T>
+ms_status solve_sync(ms_handle *h, const double *b, double *x, int nrhs, double tol, int m,
                      const ms_opts &o, ms_stats *stats, hipStream_t st) {
+    if (nrhs > h->rhs_cap) return fail(h, MS_ERR_ARG, "more right-hand sides than reserved");
     const int vz = std::min(h->vzmax, (int)(16 / sizeof(T)));
     int tx = 0, rows = 0;
-    auto_tiling(h, vz, &tx, &rows);
+    auto_tiling(h, vz, nrhs, &tx, &rows);
     if (o.x_chunk > 0) tx = std::max(kTxMin, o.x_chunk);
     if (o.rows == 1 || o.rows == 2 || o.rows == 4) rows = o.rows;
     ms_status s = set_tiling(h, vz, tx, rows, st);
     if (s != MS_OK) return s;
-    double nbeff = 0.0;
-    s = beff_norm<T>(h, b, st, &nbeff);
+    std::vector<double> nbeff(nrhs, 0.0);
+    s = beff_norms<T>(h, b, nrhs, st, nbeff.data());
     if (s != MS_OK) return s;
-    if (!std::isfinite(nbeff)) return fail(h, MS_ERR_NONFINITE, "b_eff is not finite");
-    if (nbeff == 0.0) {
-        s = zero_vec(h, x, h->N, st);
-        if (s != MS_OK) return s;
-        HIPCHK(h, hipStreamSynchronize(st));
-        if (stats) { stats->sweeps = 0; stats->rel_residual = 0.0; }
-        if (stats && stats->history && stats->history_cap > 0) {
-            stats->history[0] = 0.0;
-            stats->history_len = 1;
+    for (int k = 0; k < nrhs; k++) {
+        if (!std::isfinite(nbeff[k])) return fail(h, MS_ERR_NONFINITE, "b_eff is not finite");
+        if (nbeff[k] == 0.0) {
+            s = zero_vec(h, x + (long long)k * h->N, h->N, st);
+            if (s != MS_OK) return s;
         }
-        return MS_OK;
     }
-    // groups: inner vectors r, d, p0, p1 of one group sized for the cache
-    // groups: blocks per launch (all of them unless the caller asks for
-    // cache-sized groups; small launches lose more to kernel ramp-up and
-    // drain than the cache gives back)
+    hipLaunchKernelGGL(k_mark_zero_rhs, dim3((nrhs + 63) / 64), dim3(64), 0, st, h->ctrl, nrhs);
+    HIPCHK(h, hipGetLastError());
+    // blocks per launch: all of them unless the caller asks for cache-sized
+    // groups (small launches lose more to ramp-up and drain than the cache
+    // gives back)
     long long cap_cells = h->N;
     if (o.group_blocks > 0) {
         long long mx = 0;
@@ -457,51 +537,90 @@ ms_status solve_sync(ms_handle *h, const double *b, double *x, double tol, int m
         cap_cells = mx * o.group_blocks;
     }
     const std::vector<Group> groups = make_groups(h, cap_cells);
-    const long long cells_per_sweep = h->N * (long long)m;
+    const Batch bt = batch_of(h, nrhs);
+    const long long cells_per_sweep = h->N * (long long)m * nrhs;
     int batch = o.check_every > 0 ? o.check_every
                                   : (int)std::max(2ll, std::min(256ll, (1ll << 31) / std::max(1ll, cells_per_sweep)));
+    const bool graph = o.use_graph != 0 && o.profile == 0;
+    if (graph) batch += batch % 2;   // whole sweep pairs
     s = prof_begin(h, o.profile != 0);
     if (s != MS_OK) return s;
     double *X[2] = {x, h->x1};
-    Ctrl c;
-    memset(&c, 0, sizeof(c));
+    if (graph) {
+        GraphKey key;
+        memset(&key, 0, sizeof(key));
+        key.b = b; key.x = x; key.tol = tol; key.inner_tol = o.inner_tol; key.cap_cells = cap_cells;
+        key.m = m; key.tsize = (int)sizeof(T); key.vz = vz; key.tx = tx; key.rows = rows;
+        key.nrhs = nrhs;
+        s = sweep_pair_graph<T>(h, key, groups, b, X, tol, m, o.inner_tol, bt);
+        if (s != MS_OK) return s;
+    }
+    std::vector<Ctrl> c(nrhs);
     int next = 0;   // next sweep to enqueue
     for (;;) {
         const int nb = std::min(batch, o.max_sweeps - next);
-        for (int q = 0; q < nb; q++, next++) {
+        int q = 0;
+        if (graph) {
+            for (; q + 2 <= nb; q += 2, next += 2) HIPCHK(h, hipGraphLaunch(h->graph_exec, st));
+        }
+        for (; q < nb; q++, next++) {
             s = enqueue_sweep<T>(h, groups, b, X[next % 2], X[(next + 1) % 2], tol, m, o.inner_tol,
-                                 false, st);
+                                 false, bt, st);
             if (s != MS_OK) return s;
         }
         if (next == o.max_sweeps) {
-            s = enqueue_sweep<T>(h, groups, b, X[next % 2], nullptr, tol, m, o.inner_tol, true, st);
+            s = enqueue_sweep<T>(h, groups, b, X[next % 2], nullptr, tol, m, o.inner_tol, true, bt,
+                                 st);
             if (s != MS_OK) return s;
         }
-        HIPCHK(h, hipMemcpyAsync(&c, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+        HIPCHK(h, hipMemcpyAsync(c.data(), h->ctrl, sizeof(Ctrl) * nrhs, hipMemcpyDeviceToHost, st));
         HIPCHK(h, hipStreamSynchronize(st));
         prof_collect(h, stats);
-        if (c.done) break;
+        bool all = true;
+        for (int k = 0; k < nrhs; k++) all = all && c[k].done;
+        if (all) break;
         if (next >= o.max_sweeps) return fail(h, MS_ERR_HIP, "device did not finish the solve");
     }
-    if (c.final_sweep % 2 == 1)
-        HIPCHK(h, hipMemcpyAsync(x, h->x1, sizeof(double) * h->N, hipMemcpyDeviceToDevice, st));
+    ms_status result = MS_OK;
+    for (int k = 0; k < nrhs; k++) {
+        if (c[k].final_sweep % 2 == 1)
+            HIPCHK(h, hipMemcpyAsync(x + (long long)k * h->N, h->x1 + (long long)k * h->N,
+                                     sizeof(double) * h->N, hipMemcpyDeviceToDevice, st));
+        ms_status sk = MS_OK;
+        switch (c[k].status) {
+            case 0: break;
+            case 4: sk = MS_ERR_NOT_CONVERGED; break;
+            case 5: sk = MS_ERR_NONFINITE; break;
+            case 6: sk = MS_ERR_DIVERGED; break;
+            default: sk = MS_ERR_HIP; break;
+        }
+        if (sk != MS_OK && (result == MS_OK || result == MS_ERR_NOT_CONVERGED)) result = sk;
+    }
     HIPCHK(h, hipStreamSynchronize(st));
     if (stats) {
-        stats->sweeps = c.final_sweep;
-        stats->inner_iters = (int64_t)c.inner_snap;
-        stats->rel_residual = c.last_res;
-        if (stats->history && stats->history_cap > 0) {
-            const int n = std::min(std::min(stats->history_cap, kHistoryCap), c.final_sweep + 1);
-            HIPCHK(h, hipMemcpy(stats->history, h->history_d, sizeof(double) * n,
-                                hipMemcpyDeviceToHost));
-            stats->history_len = n;
+        for (int k = 0; k < nrhs; k++) {
+            ms_stats &S = stats[k];
+            S.sweeps = c[k].final_sweep;
+            S.inner_iters = (int64_t)c[k].inner_snap;
+            S.rel_residual = nbeff[k] == 0.0 ? 0.0 : c[k].last_res;
+            if (S.history && S.history_cap > 0) {
+                const int n = std::min(std::min(S.history_cap, kHistoryCap), c[k].final_sweep + 1);
+                if (nbeff[k] == 0.0) {
+                    S.history[0] = 0.0;
+                    S.history_len = 1;
+                } else {
+                    HIPCHK(h, hipMemcpy(S.history, h->history_d + (long long)k * kHistoryCap,
+                                        sizeof(double) * n, hipMemcpyDeviceToHost));
+                    S.history_len = n;
+                }
+            }
         }
     }
-    switch (c.status) {
-        case 0: return MS_OK;
-        case 4: return fail(h, MS_ERR_NOT_CONVERGED, "max_sweeps reached above tol");
-        case 5: return fail(h, MS_ERR_NONFINITE, "residual became non-finite");
-        case 6: return fail(h, MS_ERR_DIVERGED, "residual grew by 1e6");
+    switch (result) {
+        case MS_OK: return MS_OK;
+        case MS_ERR_NOT_CONVERGED: return fail(h, result, "max_sweeps reached above tol");
+        case MS_ERR_NONFINITE: return fail(h, result, "residual became non-finite");
+        case MS_ERR_DIVERGED: return fail(h, result, "residual grew by 1e6");
         default: return fail(h, MS_ERR_HIP, "unknown device status");
     }
 }
@@ -512,10 +631,10 @@ ms_status residual_norms(ms_handle *h, const double *b, const double *x, hipStre
                          double *nbeff, double *absres) {
     const Geom g = geom(h);
     HIPCHK(h, ms::launch_resid<double>(g, h->cur_vz, 0, h->ntiles, 0, b, nullptr, faces(h),
-                                       nullptr, h->part64, h->part64, nullptr, st));
+                                       nullptr, h->part64, h->part64, nullptr, ms::single_rhs(), st));
     HIPCHK(h, ms::launch_sum(h->part64, h->ntiles, h->scal_d, st));
     HIPCHK(h, ms::launch_resid<double>(g, h->cur_vz, 0, h->ntiles, 0, b, x, faces(h), nullptr,
-                                       h->part64, h->part64, nullptr, st));
+                                       h->part64, h->part64, nullptr, ms::single_rhs(), st));
     HIPCHK(h, ms::launch_sum(h->part64, h->ntiles, h->scal_d + 1, st));
     double ss[2] = {0.0, 0.0};
     HIPCHK(h, hipMemcpyAsync(ss, h->scal_d, sizeof(ss), hipMemcpyDeviceToHost, st));
@@ -547,7 +666,7 @@ ms_status solve_async(ms_handle *h, const double *b, double *x, double tol, int 
         return fail(h, MS_ERR_ARG, "asynchronous mode needs staleness >= 1");
     const int vz = std::min(h->vzmax, (int)(16 / sizeof(T)));
     int tx = 0, rows = 0;
-    auto_tiling(h, vz, &tx, &rows);
+    auto_tiling(h, vz, 1, &tx, &rows);
     if (o.x_chunk > 0) tx = std::max(kTxMin, o.x_chunk);
     if (o.rows == 1 || o.rows == 2 || o.rows == 4) rows = o.rows;
     ms_status s = set_tiling(h, vz, tx, rows, st);
@@ -720,7 +839,7 @@ ms_status solve_cg(ms_handle *h, const double *b, double *x, double tol, int max
     {
         Prof p(h, st, MS_K_RESID);
         HIPCHK(h, ms::launch_resid<double>(g1, vz, 0, nt, 0, b, x, faces(h), r, h->part64,
-                                           h->part64, h->ctrl, st));
+                                           h->part64, h->ctrl, ms::single_rhs(), st));
     }
     HIPCHK(h, ms::launch_gcg_reduce(h->part64, nt, 0, tol, max_iters, h->history_d, kHistoryCap,
                                     scal, h->ctrl, st));
@@ -954,12 +1073,43 @@ void ms_destroy(ms_handle *h) {
     delete h;
 }
 
-static ms_status check_vec(ms_handle *h, const void *p, const char *name) {
+static ms_status check_vec(ms_handle *h, const void *p, const char *name, long long n = 0) {
+    if (n <= 0) n = h->N;
     if (!p) return fail(h, MS_ERR_ARG, std::string(name) + " is NULL");
     if ((uintptr_t)p % 16) return fail(h, MS_ERR_ARG, std::string(name) + " must be 16-byte aligned");
-    if (!dev_range_ok(p, sizeof(double) * (size_t)h->N))
-        return fail(h, MS_ERR_ARG, std::string(name) + " is not a device buffer of nx*ny*nz doubles");
+    if (!dev_range_ok(p, sizeof(double) * (size_t)n))
+        return fail(h, MS_ERR_ARG, std::string(name) + " is not a device buffer of the right size");
     return MS_OK;
+}
+
+// Argument checks shared by ms_solve and ms_solve_batch.
+static ms_status check_solve(ms_handle *h, const double *b, double *x, long long n,
+                             int32_t inner_iters, const ms_opts &o, double tol) {
+    ms_status s = check_vec(h, b, "b", n);
+    if (s != MS_OK) return s;
+    s = check_vec(h, x, "x", n);
+    if (s != MS_OK) return s;
+    const char *bb = (const char *)b, *xx = (const char *)x;
+    const size_t bytes = sizeof(double) * (size_t)n;
+    if (bb < xx + bytes && xx < bb + bytes) return fail(h, MS_ERR_ARG, "b and x overlap");
+    if (inner_iters < 1) return fail(h, MS_ERR_ARG, "inner_iters must be >= 1");
+    if (o.max_sweeps < 0) return fail(h, MS_ERR_ARG, "max_sweeps must be >= 0");
+    if (o.staleness < 0) return fail(h, MS_ERR_ARG, "staleness must be >= 0");
+    if (std::isnan(tol) || !(o.inner_tol >= 0.0) || !std::isfinite(o.inner_tol))
+        return fail(h, MS_ERR_ARG, "tol or inner_tol invalid");
+    if (o.precision != MS_FP64 && o.precision != MS_MIXED)
+        return fail(h, MS_ERR_ARG, "unknown precision");
+    return MS_OK;
+}
+
+static void reset_stats(ms_stats *stats, int n) {
+    for (int k = 0; stats && k < n; k++) {
+        double *hist = stats[k].history;
+        const int cap = stats[k].history_cap;
+        memset(&stats[k], 0, sizeof(ms_stats));
+        stats[k].history = hist;
+        stats[k].history_cap = cap;
+    }
 }
 
 ms_status ms_solve(ms_handle *h, const double *b, double *x, double tol, int32_t inner_iters,
@@ -969,37 +1119,73 @@ ms_status ms_solve(ms_handle *h, const double *b, double *x, double tol, int32_t
     ms_opts o;
     ms_default_opts(&o);
     if (opts) o = *opts;
-    ms_status s = check_vec(h, b, "b");
+    ms_status s = check_solve(h, b, x, h->N, inner_iters, o, tol);
     if (s != MS_OK) return s;
-    s = check_vec(h, x, "x");
-    if (s != MS_OK) return s;
-    const char *bb = (const char *)b, *xx = (const char *)x;
-    const size_t bytes = sizeof(double) * (size_t)h->N;
-    if (bb < xx + bytes && xx < bb + bytes) return fail(h, MS_ERR_ARG, "b and x overlap");
-    if (inner_iters < 1) return fail(h, MS_ERR_ARG, "inner_iters must be >= 1");
-    if (o.max_sweeps < 0) return fail(h, MS_ERR_ARG, "max_sweeps must be >= 0");
-    if (o.staleness < 0) return fail(h, MS_ERR_ARG, "staleness must be >= 0");
-    if (std::isnan(tol) || !(o.inner_tol >= 0.0) || !std::isfinite(o.inner_tol))
-        return fail(h, MS_ERR_ARG, "tol or inner_tol invalid");
-    if (o.precision != MS_FP64 && o.precision != MS_MIXED)
-        return fail(h, MS_ERR_ARG, "unknown precision");
     if (mode != MS_SYNC && mode != MS_ASYNC) return fail(h, MS_ERR_ARG, "unknown mode");
-    if (stats) {
-        double *hist = stats->history;
-        const int cap = stats->history_cap;
-        memset(stats, 0, sizeof(*stats));
-        stats->history = hist;
-        stats->history_cap = cap;
-    }
+    reset_stats(stats, 1);
     hipStream_t st = (hipStream_t)o.stream;
     if (mode == MS_ASYNC)
         s = o.precision == MS_FP64 ? solve_async<double>(h, b, x, tol, inner_iters, o, stats, st)
                                    : solve_async<float>(h, b, x, tol, inner_iters, o, stats, st);
     else
-        s = o.precision == MS_FP64 ? solve_sync<double>(h, b, x, tol, inner_iters, o, stats, st)
-                                   : solve_sync<float>(h, b, x, tol, inner_iters, o, stats, st);
+        s = o.precision == MS_FP64 ? solve_sync<double>(h, b, x, 1, tol, inner_iters, o, stats, st)
+                                   : solve_sync<float>(h, b, x, 1, tol, inner_iters, o, stats, st);
     if (stats)
         stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    return s;
+}
+
+ms_status ms_reserve(ms_handle *h, int32_t nrhs) {
+    if (!h) return fail(nullptr, MS_ERR_ARG, "handle is NULL");
+    if (nrhs < 1 || nrhs > 4096) return fail(h, MS_ERR_ARG, "nrhs must be in [1, 4096]");
+    if (nrhs <= h->rhs_cap) return MS_OK;
+    const size_t vb = sizeof(double) * (size_t)h->N * nrhs;
+    const size_t tb = sizeof(double) * (size_t)h->tiles_cap * nrhs;
+    void **slots[] = {(void **)&h->x1, &h->r, &h->d, &h->p0, &h->p1, (void **)&h->part64,
+                      &h->partT, &h->psig, &h->prhoA, &h->prhoB, (void **)&h->active,
+                      (void **)&h->ctrl, (void **)&h->history_d};
+    const size_t sizes[] = {vb, vb, vb, vb, vb, tb, tb, tb, tb, tb,
+                            sizeof(int) * (size_t)h->nblocks * nrhs, sizeof(Ctrl) * (size_t)nrhs,
+                            sizeof(double) * (size_t)kHistoryCap * nrhs};
+    constexpr int n = sizeof(sizes) / sizeof(sizes[0]);
+    void *fresh[n] = {};
+    for (int i = 0; i < n; i++) {
+        const hipError_t e = hipMalloc(&fresh[i], sizes[i]);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            for (int j = 0; j < i; j++) (void)hipFree(fresh[j]);
+            return fail(h, e == hipErrorOutOfMemory ? MS_ERR_NOMEM : MS_ERR_HIP,
+                        std::string("ms_reserve: ") + hipGetErrorString(e));
+        }
+    }
+    drop_graph(h);
+    for (int i = 0; i < n; i++) {
+        (void)hipFree(*slots[i]);
+        *slots[i] = fresh[i];
+    }
+    h->rhs_cap = nrhs;
+    return MS_OK;
+}
+
+ms_status ms_solve_batch(ms_handle *h, int32_t nrhs, const double *b, double *x, double tol,
+                         int32_t inner_iters, ms_mode mode, const ms_opts *opts,
+                         ms_stats *stats) {
+    const auto t_start = std::chrono::steady_clock::now();
+    if (!h) return fail(nullptr, MS_ERR_ARG, "handle is NULL");
+    if (nrhs < 1) return fail(h, MS_ERR_ARG, "nrhs must be >= 1");
+    if (nrhs > h->rhs_cap) return fail(h, MS_ERR_ARG, "nrhs exceeds the capacity set by ms_reserve");
+    if (mode != MS_SYNC) return fail(h, MS_ERR_UNSUPPORTED, "batched solves are synchronous only");
+    ms_opts o;
+    ms_default_opts(&o);
+    if (opts) o = *opts;
+    ms_status s = check_solve(h, b, x, h->N * nrhs, inner_iters, o, tol);
+    if (s != MS_OK) return s;
+    reset_stats(stats, nrhs);
+    hipStream_t st = (hipStream_t)o.stream;
+    s = o.precision == MS_FP64 ? solve_sync<double>(h, b, x, nrhs, tol, inner_iters, o, stats, st)
+                               : solve_sync<float>(h, b, x, nrhs, tol, inner_iters, o, stats, st);
+    const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    for (int k = 0; stats && k < nrhs; k++) stats[k].seconds = sec;
     return s;
 }
 

@@ -52,6 +52,19 @@ struct Faces {
     const double *f[6];      // -x,+x,-y,+y,-z,+z (nullable)
 };
 
+// Several right-hand sides solved by the same launches: workgroup w of a
+// launch over nt tiles serves right-hand side w / nt; per-RHS arrays are
+// offset by these strides.
+struct Batch {
+    int nt;          // tiles per right-hand side in this launch (set by the launcher)
+    int nrhs;        // right-hand sides
+    long long vs;    // element stride between right-hand sides' vectors
+    long long ps;    // stride of per-tile partial arrays
+    long long bs;    // stride of per-block arrays
+};
+
+inline Batch single_rhs() { return Batch{0, 1, 0, 0, 0}; }
+
 // Shared state of an asynchronous solve (one entry per block).
 struct AsyncState {
     int *version;        // sweeps the block has completed
@@ -71,7 +84,7 @@ struct AsyncState {
 template <typename T>
 hipError_t launch_resid(const Geom &g, int vz, int t0, int t1, long long goff,
                         const double *b, const double *x, Faces faces, T *r,
-                        double *p64, T *pT, const Ctrl *ctrl, hipStream_t st);
+                        double *p64, T *pT, const Ctrl *ctrl, Batch bt, hipStream_t st);
 
 // Inner CG phase 1: p_new = r + beta p_old (beta = 0 at iter 0), per-tile
 // partials of sigma = p_new . A_ii p_new.
@@ -80,7 +93,7 @@ hipError_t launch_stencil(const Geom &g, int vz, int t0, int t1, long long goff,
                           const T *r, const T *p_old, T *p_new, T *psig,
                           const T *prho_cur, const T *prho_prev, const T *prho0,
                           int *active, int iter, double inner_tol,
-                          Ctrl *ctrl, hipStream_t st);
+                          Ctrl *ctrl, Batch bt, hipStream_t st);
 
 // Inner CG phase 2: alpha = rho/sigma; d += alpha p; r -= alpha A_ii p;
 // partials of r.r.  When last != 0: xb = xa + d + alpha p instead (r and d
@@ -90,7 +103,7 @@ hipError_t launch_update(const Geom &g, int vz, int t0, int t1, long long goff,
                          T *r, const T *p, T *d, const T *psig,
                          const T *prho_cur, T *prho_next, int *active, int iter,
                          int last, const double *xa, double *xb, Ctrl *ctrl,
-                         hipStream_t st);
+                         Batch bt, hipStream_t st);
 
 // Persistent asynchronous sweep kernel (grid = workers).
 template <typename T>
@@ -114,7 +127,8 @@ hipError_t launch_gcg_reduce(const double *part, int ntiles, int which, double t
 // Residual check after a sweep's residual kernels: fixed-order sum of the
 // FP64 partials of tiles [0, ntiles), convergence/divergence decision.
 hipError_t launch_check(const double *p64, int ntiles, double tol, int final_check,
-                        double *history, int history_cap, Ctrl *ctrl, hipStream_t st);
+                        double *history, int history_cap, Ctrl *ctrl, Batch bt,
+                        hipStream_t st);
 
 // ||b_eff||: fixed-order sum of partials into ctrl->nbeff.
 hipError_t launch_norm(const double *p64, int ntiles, Ctrl *ctrl, hipStream_t st);

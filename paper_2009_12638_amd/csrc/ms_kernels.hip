@@ -524,9 +524,18 @@ __global__ __launch_bounds__(kThreads) void k_resid(Geom g, int t0, long long go
                                                     const double *__restrict__ b,
                                                     const double *__restrict__ x, Faces F,
                                                     T *__restrict__ r, double *__restrict__ p64,
-                                                    T *__restrict__ pT, const Ctrl *ctrl) {
-    if (ctrl && ctrl->done) return;
-    const int tile = t0 + xcd_tile(blockIdx.x, gridDim.x);
+                                                    T *__restrict__ pT, const Ctrl *ctrl,
+                                                    Batch bt) {
+    // workgroup w of the launch: right-hand side k, tile t0 + (w mod nt)
+    const int w = xcd_tile(blockIdx.x, gridDim.x);
+    const int k = w / bt.nt;
+    if (ctrl && ctrl[k].done) return;
+    const int tile = t0 + (w - k * bt.nt);
+    if (b) b += k * bt.vs;
+    if (x) x += k * bt.vs;
+    if (r) r += k * bt.vs;
+    p64 += (long long)k * bt.ps;
+    pT += (long long)k * bt.ps;
     const Tile t = decode_tile<VZ, R>(g, tile, threadIdx.x);
     double acc64 = 0.0;
     T accT = T(0);
@@ -549,9 +558,19 @@ __global__ __launch_bounds__(kThreads) void k_stencil(Geom g, int t0, long long 
                                                       const T *__restrict__ prho_prev,
                                                       const T *__restrict__ prho0,
                                                       int *active, int iter, double inner_tol,
-                                                      Ctrl *ctrl) {
-    if (ctrl->done) return;
-    const int tile = t0 + xcd_tile(blockIdx.x, gridDim.x);
+                                                      Ctrl *ctrl, Batch bt) {
+    const int w = xcd_tile(blockIdx.x, gridDim.x);
+    const int k = w / bt.nt;
+    if (ctrl[k].done) return;
+    const int tile = t0 + (w - k * bt.nt);
+    r += k * bt.vs;
+    pold += k * bt.vs;
+    pnew += k * bt.vs;
+    psig += (long long)k * bt.ps;
+    prho_cur += (long long)k * bt.ps;
+    prho_prev += (long long)k * bt.ps;
+    prho0 += (long long)k * bt.ps;
+    active += (long long)k * bt.bs;
     const Tile t = decode_tile<VZ, R>(g, tile, threadIdx.x);
     const T rho = tiles_sum(prho_cur, t.B.tile0, t.B.ntiles);
     bool act;
@@ -585,9 +604,24 @@ __global__ __launch_bounds__(kThreads) void k_update(Geom g, int t0, long long g
                                                      const T *__restrict__ prho_cur,
                                                      T *__restrict__ prho_next, int *active,
                                                      int iter, const double *__restrict__ xa,
-                                                     double *__restrict__ xb, Ctrl *ctrl) {
+                                                     double *__restrict__ xb, Ctrl *ctrl,
+                                                     Batch bt) {
+    const int w = xcd_tile(blockIdx.x, gridDim.x);
+    const int k = w / bt.nt;
+    ctrl += k;
     if (ctrl->done) return;
-    const int tile = t0 + xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = t0 + (w - k * bt.nt);
+    r += k * bt.vs;
+    p += k * bt.vs;
+    d += k * bt.vs;
+    psig += (long long)k * bt.ps;
+    prho_cur += (long long)k * bt.ps;
+    prho_next += (long long)k * bt.ps;
+    active += (long long)k * bt.bs;
+    if (LAST) {
+        xa += k * bt.vs;
+        xb += k * bt.vs;
+    }
     const Tile t = decode_tile<VZ, R>(g, tile, threadIdx.x);
     bool act = active[t.b] != 0;
     T alpha = T(0);
@@ -900,7 +934,12 @@ __global__ __launch_bounds__(kAsyncThreads) void k_async(Geom g, const double *_
 __global__ __launch_bounds__(kThreads) void k_check(const double *__restrict__ p64, int ntiles,
                                                     double tol, int final_check,
                                                     double *history, int history_cap,
-                                                    Ctrl *ctrl) {
+                                                    Ctrl *ctrl, Batch bt) {
+    // workgroup k checks right-hand side k
+    const int k = blockIdx.x;
+    ctrl += k;
+    p64 += (long long)k * bt.ps;
+    history += (long long)k * history_cap;
     if (ctrl->done) return;
     const double total = fixed_sum_1wg(p64, ntiles);
     if (threadIdx.x != 0) return;
@@ -980,19 +1019,26 @@ __global__ __launch_bounds__(kThreads) void k_apply(long long nx, long long ny, 
         default: return hipErrorInvalidValue;                         \
     }
 
+// Grid for tiles [t0, t1) of every right-hand side of the batch.
+inline dim3 batch_grid(int t0, int t1, Batch &bt) {
+    bt.nt = t1 - t0;
+    return dim3((unsigned)((long long)bt.nt * bt.nrhs));
+}
+
 template <typename T>
 hipError_t launch_resid(const Geom &g, int vz, int t0, int t1, long long goff,
                         const double *b, const double *x, Faces faces, T *r, double *p64,
-                        T *pT, const Ctrl *ctrl, hipStream_t st) {
+                        T *pT, const Ctrl *ctrl, Batch bt, hipStream_t st) {
     if (t1 <= t0) return hipSuccess;
+    const dim3 grid = batch_grid(t0, t1, bt);
     if (r) {
-        MS_DISPATCH(vz, g.rows, hipLaunchKernelGGL((k_resid<T, VZ, RR, true>), dim3(t1 - t0),
+        MS_DISPATCH(vz, g.rows, hipLaunchKernelGGL((k_resid<T, VZ, RR, true>), grid,
                                                    dim3(kThreads), 0, st, g, t0, goff, b, x,
-                                                   faces, r, p64, pT, ctrl));
+                                                   faces, r, p64, pT, ctrl, bt));
     } else {
-        MS_DISPATCH(vz, g.rows, hipLaunchKernelGGL((k_resid<T, VZ, RR, false>), dim3(t1 - t0),
+        MS_DISPATCH(vz, g.rows, hipLaunchKernelGGL((k_resid<T, VZ, RR, false>), grid,
                                                    dim3(kThreads), 0, st, g, t0, goff, b, x,
-                                                   faces, r, p64, pT, ctrl));
+                                                   faces, r, p64, pT, ctrl, bt));
     }
     return hipGetLastError();
 }
@@ -1001,12 +1047,13 @@ template <typename T>
 hipError_t launch_stencil(const Geom &g, int vz, int t0, int t1, long long goff,
                           const T *r, const T *p_old, T *p_new, T *psig, const T *prho_cur,
                           const T *prho_prev, const T *prho0, int *active, int iter,
-                          double inner_tol, Ctrl *ctrl, hipStream_t st) {
+                          double inner_tol, Ctrl *ctrl, Batch bt, hipStream_t st) {
     if (t1 <= t0) return hipSuccess;
-    MS_DISPATCH(vz, g.rows, hipLaunchKernelGGL((k_stencil<T, VZ, RR>), dim3(t1 - t0),
+    const dim3 grid = batch_grid(t0, t1, bt);
+    MS_DISPATCH(vz, g.rows, hipLaunchKernelGGL((k_stencil<T, VZ, RR>), grid,
                                                dim3(kThreads), 0, st, g, t0, goff, r, p_old,
                                                p_new, psig, prho_cur, prho_prev, prho0, active,
-                                               iter, inner_tol, ctrl));
+                                               iter, inner_tol, ctrl, bt));
     return hipGetLastError();
 }
 
@@ -1014,18 +1061,19 @@ template <typename T>
 hipError_t launch_update(const Geom &g, int vz, int t0, int t1, long long goff, T *r,
                          const T *p, T *d, const T *psig, const T *prho_cur, T *prho_next,
                          int *active, int iter, int last, const double *xa, double *xb,
-                         Ctrl *ctrl, hipStream_t st) {
+                         Ctrl *ctrl, Batch bt, hipStream_t st) {
     if (t1 <= t0) return hipSuccess;
+    const dim3 grid = batch_grid(t0, t1, bt);
     if (last) {
-        MS_DISPATCH(vz, g.rows, hipLaunchKernelGGL((k_update<T, VZ, RR, true>), dim3(t1 - t0),
+        MS_DISPATCH(vz, g.rows, hipLaunchKernelGGL((k_update<T, VZ, RR, true>), grid,
                                                    dim3(kThreads), 0, st, g, t0, goff, r, p, d,
                                                    psig, prho_cur, prho_next, active, iter, xa,
-                                                   xb, ctrl));
+                                                   xb, ctrl, bt));
     } else {
-        MS_DISPATCH(vz, g.rows, hipLaunchKernelGGL((k_update<T, VZ, RR, false>), dim3(t1 - t0),
+        MS_DISPATCH(vz, g.rows, hipLaunchKernelGGL((k_update<T, VZ, RR, false>), grid,
                                                    dim3(kThreads), 0, st, g, t0, goff, r, p, d,
                                                    psig, prho_cur, prho_next, active, iter, xa,
-                                                   xb, ctrl));
+                                                   xb, ctrl, bt));
     }
     return hipGetLastError();
 }
@@ -1077,9 +1125,10 @@ hipError_t launch_gcg_reduce(const double *part, int ntiles, int which, double t
 }
 
 hipError_t launch_check(const double *p64, int ntiles, double tol, int final_check,
-                        double *history, int history_cap, Ctrl *ctrl, hipStream_t st) {
-    hipLaunchKernelGGL(k_check, dim3(1), dim3(kThreads), 0, st, p64, ntiles, tol,
-                       final_check, history, history_cap, ctrl);
+                        double *history, int history_cap, Ctrl *ctrl, Batch bt,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_check, dim3(bt.nrhs), dim3(kThreads), 0, st, p64, ntiles, tol,
+                       final_check, history, history_cap, ctrl, bt);
     return hipGetLastError();
 }
 
@@ -1106,14 +1155,14 @@ hipError_t launch_apply(long long nx, long long ny, long long nz, const double *
 #define MS_INST(T)                                                                          \
     template hipError_t launch_resid<T>(const Geom &, int, int, int, long long, const double *, \
                                         const double *, Faces, T *, double *, T *,            \
-                                        const Ctrl *, hipStream_t);                           \
+                                        const Ctrl *, Batch, hipStream_t);                    \
     template hipError_t launch_stencil<T>(const Geom &, int, int, int, long long, const T *,  \
                                           const T *, T *, T *, const T *, const T *,          \
-                                          const T *, int *, int, double, Ctrl *,              \
+                                          const T *, int *, int, double, Ctrl *, Batch,       \
                                           hipStream_t);                                       \
     template hipError_t launch_update<T>(const Geom &, int, int, int, long long, T *,         \
                                          const T *, T *, const T *, const T *, T *, int *,    \
-                                         int, int, const double *, double *, Ctrl *,          \
+                                         int, int, const double *, double *, Ctrl *, Batch,   \
                                          hipStream_t);                                        \
     template hipError_t launch_async<T>(const Geom &, int, int, const double *, double *,     \
                                         Faces, T *, T *, T *, T *, AsyncState, int, int, int, \

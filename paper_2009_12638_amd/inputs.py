@@ -170,6 +170,9 @@ def workload(name: str):
     poisson256  256^3 Poisson, f ~ N(0,1) seed 20, zero Dirichlet, 4^3 blocks of 64^3
     bumps512    512^3 Poisson, 8 Gaussian bumps (seed 30) + noise (seed 31),
                 zero Dirichlet, 8^3 blocks of 64^3, m=10
+    uneven384   384x320x448 Poisson, per-axis block edges drawn from
+                {32, 48, 64, 96} (seeds 40, 41, 42), 16 right-hand sides
+                f_k ~ N(0,1) (seed 400+k), zero Dirichlet; b is [16, nx, ny, nz]
     """
     if name == "laplace32":
         n = 32
@@ -183,4 +186,12 @@ def workload(name: str):
         n = 512
         return dict(shape=(n, n, n), cuts=[uniform_cuts(n, 8)] * 3,
                     b=gaussian_bumps((n, n, n), 30, 31), faces=[None] * 6, m=10, tol=1e-8)
+    if name.startswith("uneven384"):
+        nrhs = int(name.split(":")[1]) if ":" in name else 16
+        shape = (384, 320, 448)
+        cuts = [uneven_cuts(n, 40 + a) for a, n in enumerate(shape)]
+        b = np.empty((nrhs,) + shape)
+        for k in range(nrhs):
+            b[k] = poisson_randn(shape, 400 + k)
+        return dict(shape=shape, cuts=cuts, b=b, faces=[None] * 6, m=10, tol=1e-8)
     raise KeyError(name)

@@ -91,6 +91,11 @@ def lib() -> C.CDLL:
         L.ms_cg.argtypes = [H, C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
                             C.POINTER(ms_opts), C.POINTER(ms_stats)]
         L.ms_cg.restype = C.c_int
+        L.ms_reserve.argtypes = [H, C.c_int32]
+        L.ms_reserve.restype = C.c_int
+        L.ms_solve_batch.argtypes = [H, C.c_int32, C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
+                                     C.c_int, C.POINTER(ms_opts), C.POINTER(ms_stats)]
+        L.ms_solve_batch.restype = C.c_int
         L.ms_destroy.argtypes = [H]
         L.ms_destroy.restype = None
         L.ms_status_string.argtypes = [C.c_int]
@@ -276,6 +281,47 @@ def ms_solve(h: Handle, b, x, tol: float, inner_iters: int, mode="sync", history
     st = lib().ms_solve(h.raw, _vec(h, b, "b"), _vec(h, x, "x"), float(tol), int(inner_iters), md,
                         C.byref(o), C.byref(s))
     out = _stats_of(st, s, hist)
+    if raise_on_error and st != MS_OK:
+        _check(h, st)
+    return out
+
+
+def ms_reserve(h: Handle, nrhs: int) -> None:
+    """Room for ms_solve_batch with up to nrhs right-hand sides."""
+    _check(h, lib().ms_reserve(h.raw, int(nrhs)))
+
+
+def _vecs(h, t, name, nrhs):
+    if hasattr(t, "data_ptr"):
+        import torch
+        n = h.shape[0] * h.shape[1] * h.shape[2] * nrhs
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() \
+                or t.numel() != n:
+            raise MsError(MS_ERR_ARG, f"{name} must be a contiguous float64 GPU tensor "
+                                      f"of {n} elements")
+        return t.data_ptr()
+    return int(t)
+
+
+def ms_solve_batch(h: Handle, b, x, tol: float, inner_iters: int, history=0,
+                   raise_on_error=True, **opts):
+    """Solve every right-hand side of b ([nrhs, nx, ny, nz]) into x in the same
+    launches (synchronous sweeps).  Returns a list of Stats."""
+    nrhs = int(b.shape[0]) if hasattr(b, "shape") else int(opts.pop("nrhs"))
+    o = _opts(**opts)
+    arr = (ms_stats * nrhs)()
+    hists = []
+    for k in range(nrhs):
+        if history:
+            hk = (C.c_double * int(history))()
+            arr[k].history = C.cast(hk, C.POINTER(C.c_double))
+            arr[k].history_cap = int(history)
+            hists.append(hk)
+        else:
+            hists.append(None)
+    st = lib().ms_solve_batch(h.raw, nrhs, _vecs(h, b, "b", nrhs), _vecs(h, x, "x", nrhs),
+                              float(tol), int(inner_iters), MS_SYNC, C.byref(o), arr)
+    out = [_stats_of(st, arr[k], hists[k]) for k in range(nrhs)]
     if raise_on_error and st != MS_OK:
         _check(h, st)
     return out

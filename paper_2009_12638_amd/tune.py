@@ -1,0 +1,136 @@
+"""Autotuner for the multisplitting solve.
+
+The paper fixes the number of inner iterations by hand and names run-time
+auto-tuning of such parameters as future work (Sections 3.2 and 5).  This
+module chooses, for one problem (grid, partition, precision, right-hand
+sides):
+
+* the tile shape (rows per thread, x chunk) by timing a few sweeps of each
+  candidate, and
+* the number of inner CG iterations m by the residual reduction each
+  candidate achieves per second of solve time, measured from a common
+  iterate past the initial transient.
+
+Every timed run goes through the C ABI (ms_solve / ms_solve_batch); results
+are cached in a JSON file keyed by the problem.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import math
+import os
+import time
+
+import torch
+
+from . import ms
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2009_12638_amd",
+                             "tune.json")
+TILE_CANDIDATES = [(r, t) for r in (1, 2, 4) for t in (8, 16, 32)]
+INNER_CANDIDATES = (5, 10, 20, 40)
+
+
+def problem_key(shape, cuts, precision, nrhs=1) -> str:
+    dev = torch.cuda.get_device_name() if torch.cuda.is_available() else "cpu"
+    raw = json.dumps([list(shape), [list(map(int, c)) for c in cuts], precision, nrhs, dev])
+    return hashlib.sha1(raw.encode()).hexdigest()[:16]
+
+
+def _run(h, b, x, sweeps, m, batch, **kw):
+    if batch:
+        return ms.ms_solve_batch(h, b, x, 0.0, m, max_sweeps=sweeps, **kw)
+    return ms.ms_solve(h, b, x, 0.0, m, "sync", max_sweeps=sweeps, **kw)
+
+
+def tune_tiles(h, b, x, precision="mixed", m=10, sweeps=4, candidates=TILE_CANDIDATES):
+    """Fastest (rows, x_chunk) by wall time of `sweeps` synchronous sweeps."""
+    batch = b.dim() == 4
+    best = None
+    results = []
+    for rows, tx in candidates:
+        kw = dict(precision=precision, rows=rows, x_chunk=tx)
+        _run(h, b, x, 1, m, batch, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _run(h, b, x, sweeps, m, batch, **kw)
+        torch.cuda.synchronize()
+        ms_sweep = 1e3 * (time.perf_counter() - t0) / sweeps
+        results.append(dict(rows=rows, x_chunk=tx, ms_per_sweep=ms_sweep))
+        if best is None or ms_sweep < best["ms_per_sweep"]:
+            best = results[-1]
+    return best, results
+
+
+def tune_inner(h, b, precision="mixed", candidates=INNER_CANDIDATES, warm_res=0.05,
+               budget_s=0.5, tile=None, warm_max=300):
+    """m with the largest log10 residual reduction per second, measured for
+    each candidate from the same iterate (first one with residual <= warm_res
+    under the default m), each for about budget_s seconds."""
+    batch = b.dim() == 4
+    tile = tile or {}
+    kw = dict(precision=precision, **{k: tile[k] for k in ("rows", "x_chunk") if k in tile})
+    x0 = torch.zeros_like(b)
+    if batch:
+        ms.ms_solve_batch(h, b, x0, warm_res, 10, raise_on_error=False, max_sweeps=warm_max,
+                          **kw)
+    else:
+        ms.ms_solve(h, b, x0, warm_res, 10, "sync", raise_on_error=False,
+                    max_sweeps=warm_max, **kw)
+    results = []
+    for m in candidates:
+        x = x0.clone()
+        # sweeps that fit the budget, from one timed probe sweep
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _run(h, b, x.clone(), 1, m, batch, **kw)
+        torch.cuda.synchronize()
+        per = max(time.perf_counter() - t0, 1e-5)
+        sweeps = max(2, int(budget_s / per))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = _run(h, b, x, sweeps, m, batch, history=sweeps + 1, **kw)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        hists = [t.history for t in s] if batch else [s.history]
+        drop = min(math.log10(hh[0] / max(hh[-1], 1e-300)) for hh in hists)
+        results.append(dict(m=m, sweeps=sweeps, seconds=sec, decades_per_s=drop / sec))
+    best = max(results, key=lambda r: r["decades_per_s"])
+    return best, results
+
+
+def autotune(shape, cuts, b, precision="mixed", cache=DEFAULT_CACHE, tune_m=True,
+             refresh=False):
+    """Tuned options {rows, x_chunk, inner_iters} for this problem, from the
+    cache when present.  b: device tensor [nx,ny,nz] or [nrhs,nx,ny,nz]."""
+    nrhs = b.shape[0] if b.dim() == 4 else 1
+    key = problem_key(shape, cuts, precision, nrhs)
+    db = {}
+    if os.path.exists(cache):
+        try:
+            with open(cache) as f:
+                db = json.load(f)
+        except (OSError, ValueError):
+            db = {}
+    if key in db and not refresh:
+        return db[key]
+    h = ms.ms_create(shape, cuts=[list(map(int, c)) for c in cuts])
+    if nrhs > 1:
+        ms.ms_reserve(h, nrhs)
+    x = torch.zeros_like(b)
+    tile, tile_all = tune_tiles(h, b, x, precision)
+    out = dict(rows=tile["rows"], x_chunk=tile["x_chunk"], inner_iters=10,
+               ms_per_sweep=tile["ms_per_sweep"], tiles=tile_all)
+    if tune_m:
+        inner, inner_all = tune_inner(h, b, precision, tile=tile)
+        out["inner_iters"] = inner["m"]
+        out["inner"] = inner_all
+    ms.ms_destroy(h)
+    db[key] = out
+    os.makedirs(os.path.dirname(cache), exist_ok=True)
+    tmp = cache + f".tmp{os.getpid()}"
+    with open(tmp, "w") as f:
+        json.dump(db, f, indent=1)
+    os.replace(tmp, cache)
+    return out

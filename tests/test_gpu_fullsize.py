@@ -76,3 +76,42 @@ def test_sampled_block_sweep(orc, name, precision):
     moved = np.abs(x3 - x2).reshape(g, shape[0] // g, g, shape[1] // g, g, shape[2] // g)
     assert (moved.max(axis=(1, 3, 5)) > 0).all()
     print(f"{name} {precision}: worst block correction error {worst:.2e}")
+
+
+def test_uneven384_batch_sampled_blocks(orc):
+    """The batched workload at full size (384x320x448, uneven blocks with
+    edges from {32,48,64,96}, 16 right-hand sides, mixed precision): sampled
+    blocks of sampled right-hand sides against the oracle's block sweep."""
+    torch = torch_cuda()
+    w = workload("uneven384")
+    shape, cuts = w["shape"], w["cuts"]
+    nrhs = w["b"].shape[0]
+    h = ms.ms_create(shape, cuts=[list(map(int, c)) for c in cuts], faces=None)
+    ms.ms_reserve(h, nrhs)
+    B = torch.from_numpy(w["b"]).to("cuda")
+    X = torch.zeros_like(B)
+    say("uneven384 batch 2 sweeps")
+    ms.ms_solve_batch(h, B, X, 0.0, w["m"], max_sweeps=2, precision="mixed")
+    picks = [0, 7, nrhs - 1]
+    x2 = {k: host(X[k]) for k in picks}
+    say("uneven384 batch 1 more sweep")
+    ms.ms_solve_batch(h, B, X, 0.0, w["m"], max_sweeps=1, precision="mixed")
+    x3 = {k: host(X[k]) for k in picks}
+    del X, B
+    ms.ms_destroy(h)
+    torch.cuda.empty_cache()
+    gx, gy, gz = (len(c) - 1 for c in cuts)
+    blocks = sorted({0, gx * gy * gz - 1, (gx // 2 * gy + gy // 2) * gz + gz // 2,
+                     (1 * gy + 0) * gz + gz - 2})
+    worst = 0.0
+    for k in picks:
+        beff = orc.lift_bc(w["b"][k], [None] * 6)
+        xo = orc.block_sweep_some(beff, x2[k], cuts, blocks, m=w["m"])
+        for blk in blocks:
+            bi, bj, bk = blk // (gy * gz), (blk // gz) % gy, blk % gz
+            sl = (slice(cuts[0][bi], cuts[0][bi + 1]), slice(cuts[1][bj], cuts[1][bj + 1]),
+                  slice(cuts[2][bk], cuts[2][bk + 1]))
+            e = rel(x3[k][sl] - x2[k][sl], xo[sl] - x2[k][sl])
+            worst = max(worst, e)
+            assert e <= D_TOL["mixed"], (k, blk, e)
+    print(f"uneven384 batch: worst block correction error {worst:.2e}")

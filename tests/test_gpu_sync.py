@@ -227,3 +227,80 @@ def test_error_paths():
     bn[3, 4, 5] = float("nan")
     st = ms.ms_solve(h, bn, x, 1e-8, 10, "sync", raise_on_error=False)
     assert st.status == ms.MS_ERR_NONFINITE
+
+
+def test_batch_of_rhs_matches_single_solves(orc):
+    """Several right-hand sides in the same launches give, for each, exactly
+    the single-right-hand-side sweep (same kernels, fixed reduction order)
+    and match the oracle."""
+    torch = torch_cuda()
+    shape = (40, 36, 44)
+    cuts = ([0, 14, 40], [0, 10, 36], [0, 20, 44])
+    faces = inputs.random_faces(*shape, seed=110)
+    bs = [inputs.poisson_randn(shape, 111 + k) for k in range(3)]
+    bs.append(np.zeros(shape))                  # a right-hand side with b_eff = ... faces only
+    h, _ = make(ms, shape, cuts, faces)
+    ms.ms_reserve(h, 4)
+    B = torch.stack([dev(b) for b in bs]).contiguous()
+    X = torch.zeros_like(B)
+    K, m = 14, 6
+    say("batch of 4 rhs")
+    sts = ms.ms_solve_batch(h, B, X, 0.0, m, max_sweeps=K, history=K + 1)
+    for k in range(4):
+        x1 = torch.zeros(shape, dtype=torch.float64, device="cuda")
+        ms.ms_solve(h, dev(bs[k]), x1, 0.0, m, "sync", max_sweeps=K)
+        assert torch.equal(X[k], x1), k
+        beff = orc.lift_bc(bs[k], faces)
+        _, xo, _, _, hist = orc.block_jacobi(beff, np.zeros(shape), cuts, tol=0.0, m=m,
+                                             max_sweeps=K)
+        assert rel(host(X[k]), xo) <= TOL_FP64
+        assert sts[k].sweeps == K
+        np.testing.assert_allclose(sts[k].history, hist, rtol=1e-9, atol=HIST_ATOL)
+
+
+def test_batch_each_rhs_stops_on_its_own():
+    torch = torch_cuda()
+    shape = (32, 32, 32)
+    cuts = [inputs.uniform_cuts(32, 2)] * 3
+    h, _ = make(ms, shape, cuts, [None] * 6)
+    ms.ms_reserve(h, 3)
+    B = torch.stack([dev(inputs.poisson_randn(shape, 120)), torch.zeros(shape, dtype=torch.float64,
+                     device="cuda"), dev(inputs.poisson_randn(shape, 121) * 1e3)]).contiguous()
+    X = torch.zeros_like(B)
+    X[1].fill_(5.0)
+    say("batch stops per rhs")
+    sts = ms.ms_solve_batch(h, B, X, 1e-8, 10, precision="mixed")
+    assert sts[1].sweeps == 0 and not host(X[1]).any()
+    for k in (0, 2):
+        assert sts[k].rel_residual <= 1e-8
+        rel_k, _ = ms.ms_residual(h, B[k].contiguous(), X[k].contiguous())
+        assert rel_k <= 1e-8
+    with pytest.raises(ms.MsError):
+        ms.ms_solve_batch(h, torch.zeros((4,) + shape, dtype=torch.float64, device="cuda"),
+                          torch.zeros((4,) + shape, dtype=torch.float64, device="cuda"), 1e-8, 10)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_replay_equals_eager(precision):
+    """Sweeps replayed from a captured HIP graph equal eagerly launched ones
+    bitwise, over several replays with eager work and synchronisation in
+    between, and after switching precision and back."""
+    torch = torch_cuda()
+    shape = (24, 24, 48)
+    cuts = [[0, 12, 24], [0, 24], [0, 16, 48]]
+    h, _ = make(ms, shape, cuts, [None] * 6)
+    b = dev(inputs.poisson_randn(shape, 130))
+    say("graph vs eager", precision)
+    xe = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    ms.ms_solve(h, b, xe, 0.0, 7, "sync", max_sweeps=9, precision=precision, use_graph=False)
+    for rep in range(3):
+        xg = torch.zeros(shape, dtype=torch.float64, device="cuda")
+        ms.ms_solve(h, b, xg, 0.0, 7, "sync", max_sweeps=9, precision=precision, use_graph=True,
+                    check_every=4)
+        torch.cuda.synchronize()
+        assert torch.equal(xg, xe), rep
+        # eager work in between replays
+        y = torch.empty_like(xg)
+        ms.ms_apply(h, xg, y)
+        other = "mixed" if precision == "fp64" else "fp64"
+        ms.ms_solve(h, b, torch.zeros_like(xg), 0.0, 3, "sync", max_sweeps=2, precision=other)
