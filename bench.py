@@ -32,6 +32,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "time-to-1e-8 residual & stencil/CG HBM GB/s, 512^3 Laplace; mixed vs plain FP64"
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2009_12638_amd", "csrc", "ms_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_bumps512_sync_mixed.json")
 HBM_PEAK_GBPS = 8000.0
 ALL_MODES = ["sync-mixed", "sync-fp64", "async-mixed", "async-fp64", "cg-fp64",
              "batch-mixed", "batch-fp64"]
@@ -197,6 +199,24 @@ def run_mode(args, torch, ms, w, mode: str, oracle_check):
     return res
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a
+    plain copy of known size), or None when the kernels changed since."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            data = json.load(f)
+        with open(KERNEL_SOURCE, "rb") as f:
+            sha = hashlib.sha1(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if data.get("kernel_source_sha1") != sha or kernel not in data.get("kernels", {}):
+        return None
+    k = data["kernels"][kernel]
+    return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
+
+
 def cpu_baseline(o, beff, w, m: int, sweeps: int):
     import numpy as np
     shape, cuts = w["shape"], w["cuts"]
@@ -286,9 +306,15 @@ def main():
     roof = None
     if "kernels" in head and head["kernels"]:
         dom_name, dom = max(head["kernels"].items(), key=lambda kv: kv[1]["total_ms"])
+        N = w["shape"][0] * w["shape"][1] * w["shape"][2]
+        tb = measured_traffic(f"{dom_name}:{head['mode']}")
         roof = {"bound": "hbm", "kernel": f"k_{dom_name} ({head['mode']})",
                 "achieved": dom["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(dom["GBps"] / HBM_PEAK_GBPS, 4), "traffic": None}
+                "frac": round(dom["GBps"] / HBM_PEAK_GBPS, 4),
+                "traffic": None if tb is None else round(tb / (dom["avg_us"] * 1e-6) / 1e9, 1),
+                "algorithmic_bytes_per_launch": int(sum(dom["bytes_per_unknown"]) /
+                                                    len(dom["bytes_per_unknown"]) * N),
+                "traffic_bytes_per_launch": None if tb is None else int(tb)}
     cpu = None if args.no_cpu else cpu_baseline(o, beff, w, args.m, args.cpu_sweeps)
     shape = w["shape"]
     kind, prec = modes[0].split("-")
