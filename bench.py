@@ -78,6 +78,8 @@ CG_BYTES = {"stencil": 24, "update": 40}   # FP64 global CG, per unknown per ite
 
 
 def per_kernel(prof, N, byte_lists, extra=None):
+    """Per kernel class: launches, average duration, compulsory GB/s and the
+    unknowns one launch processes (launches cover groups of blocks)."""
     out = {}
     for name, lst in byte_lists.items():
         launches = prof.kernel_launches.get(name, 0)
@@ -85,9 +87,12 @@ def per_kernel(prof, N, byte_lists, extra=None):
         if launches == 0 or ms_tot <= 0:
             continue
         bytes_tot = sum(lst) * N * prof.sweeps + (extra or {}).get(name, 0)
+        passes = len(lst) * prof.sweeps + (1 if (extra or {}).get(name) else 0)
         out[name] = {"launches": launches, "avg_us": round(1e3 * ms_tot / launches, 2),
                      "total_ms": round(ms_tot, 3),
                      "GBps": round(bytes_tot / (ms_tot * 1e-3) / 1e9, 1),
+                     "bytes_per_launch": int(bytes_tot / launches),
+                     "unknowns_per_launch": int(round(N * passes / launches)),
                      "bytes_per_unknown": lst}
     return out
 
@@ -199,10 +204,11 @@ def run_mode(args, torch, ms, w, mode: str, oracle_check):
     return res
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, unknowns_per_launch: int):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a
-    plain copy of known size), or None when the kernels changed since."""
+    plain copy of known size), or None when the kernels or the launch size
+    changed since the counters were taken."""
     import hashlib
     try:
         with open(TRAFFIC_FILE) as f:
@@ -211,9 +217,11 @@ def measured_traffic(kernel: str):
             sha = hashlib.sha1(f.read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if data.get("kernel_source_sha1") != sha or kernel not in data.get("kernels", {}):
+    k = data.get("kernels", {}).get(kernel)
+    if data.get("kernel_source_sha1") != sha or k is None:
         return None
-    k = data["kernels"][kernel]
+    if k.get("unknowns_per_launch") != unknowns_per_launch:
+        return None
     return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
 
 
@@ -306,18 +314,19 @@ def main():
     roof = None
     if "kernels" in head and head["kernels"]:
         dom_name, dom = max(head["kernels"].items(), key=lambda kv: kv[1]["total_ms"])
-        N = w["shape"][0] * w["shape"][1] * w["shape"][2]
-        tb = measured_traffic(f"{dom_name}:{head['mode']}")
+        tb = measured_traffic(f"{dom_name}:{head['mode']}", dom["unknowns_per_launch"])
         roof = {"bound": "hbm", "kernel": f"k_{dom_name} ({head['mode']})",
                 "achieved": dom["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(dom["GBps"] / HBM_PEAK_GBPS, 4),
                 "traffic": None if tb is None else round(tb / (dom["avg_us"] * 1e-6) / 1e9, 1),
-                "algorithmic_bytes_per_launch": int(sum(dom["bytes_per_unknown"]) /
-                                                    len(dom["bytes_per_unknown"]) * N),
-                "traffic_bytes_per_launch": None if tb is None else int(tb)}
+                "algorithmic_bytes_per_launch": dom["bytes_per_launch"],
+                "traffic_bytes_per_launch": None if tb is None else int(tb),
+                "unknowns_per_launch": dom["unknowns_per_launch"]}
     cpu = None if args.no_cpu else cpu_baseline(o, beff, w, args.m, args.cpu_sweeps)
-    shape = w["shape"]
     kind, prec = modes[0].split("-")
+    if kind == "batch":
+        w = wb
+    shape = w["shape"]
     line = {
         "metric": METRIC,
         "value": head["GBps"],
@@ -332,10 +341,13 @@ def main():
         "dtype": "f32+f64" if prec == "mixed" else "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.workload}: {shape[0]}x{shape[1]}x{shape[2]} Poisson, "
-                        f"{len(w['cuts'][0]) - 1}^3 blocks of "
-                        f"{shape[0] // (len(w['cuts'][0]) - 1)}^3, m={args.m}, "
-                        f"{kind} sweeps, {prec}",
+            "workload": (f"{args.workload}: {shape[0]}x{shape[1]}x{shape[2]} Poisson, "
+                         f"{len(w['cuts'][0]) - 1}^3 blocks of "
+                         f"{shape[0] // (len(w['cuts'][0]) - 1)}^3, m={args.m}, "
+                         f"{kind} sweeps, {prec}") if kind != "batch" else
+                        (f"{BATCH_WORKLOAD}: {shape[0]}x{shape[1]}x{shape[2]} Poisson, "
+                         f"{w['b'].shape[0]} right-hand sides, uneven blocks "
+                         f"{[len(c) - 1 for c in w['cuts']]}, {prec}"),
             "step": "one outer sweep",
             "unknowns": shape[0] * shape[1] * shape[2],
         },

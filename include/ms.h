@@ -92,9 +92,9 @@ typedef struct {
     void *stream;         /* hipStream_t used for all work; NULL = null stream */
     int32_t check_every;  /* sync: sweeps enqueued between host reads of the
                              convergence flag (0 = automatic) */
-    int32_t group_blocks; /* sync: blocks per launch; > 0 processes that many
-                             blocks at a time so their inner vectors stay
-                             cache resident (0 or -1 = all blocks at once) */
+    int32_t group_blocks; /* sync: blocks per launch.  0 = automatic: groups
+                             whose inner vectors fill the 256 MB on-package
+                             cache; -1 = all blocks at once; > 0 = that many */
     int32_t x_chunk;      /* x planes marched per workgroup (0 = automatic) */
     int32_t profile;      /* 1: time each kernel class with HIP events */
     int32_t use_graph;    /* sync: 1 = replay sweeps from a captured HIP graph

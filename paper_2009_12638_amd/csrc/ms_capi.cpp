@@ -2,9 +2,9 @@
 // scheduler for the synchronous two-stage multisplitting solve.
 //
 // Sweep schedule (synchronous mode).  Blocks are processed in groups of
-// consecutive blocks (by default one group holding every block; smaller
-// groups keep their inner vectors cache resident but give smaller launches);
-// every group reuses the same inner buffers.  For one
+// consecutive blocks whose inner vectors (r, d and two p buffers) fill the
+// 256 MB on-package cache, so the inner iterations of a group re-read them
+// from the cache; every group reuses the same inner buffers.  For one
 // group: residual (halo reads from x_old), then m x {stencil, update}; the
 // last update writes x_new = x_old + d into the second outer buffer, so all
 // groups of a sweep read only x_old (Section 3: X_i^(k) uses only sweep k-1
@@ -275,6 +275,12 @@ ms_status prof_begin(ms_handle *h, bool on) {
 
 // ---- solve pieces -------------------------------------------------------
 
+long long block_cells(const ms_handle *h, int b) {
+    const int bi = b / (h->gy * h->gz), bj = (b / h->gz) % h->gy, bk = b % h->gz;
+    return (long long)(h->cx[bi + 1] - h->cx[bi]) * (h->cy[bj + 1] - h->cy[bj]) *
+           (h->cz[bk + 1] - h->cz[bk]);
+}
+
 template <typename T>
 struct Bufs {
     T *r, *d, *p[2];
@@ -307,27 +313,35 @@ Batch batch_of(const ms_handle *h, int nrhs) {
     return bt;
 }
 
+// Consecutive blocks whose volume stays within cap_cells (at least one
+// block each).  Returns block ranges; tile ranges are filled by fill_tiles.
 std::vector<Group> make_groups(const ms_handle *h, long long cap_cells) {
     std::vector<Group> gs;
     int b = 0;
     while (b < h->nblocks) {
         Group g;
         g.b0 = b;
-        g.off = h->blocks_h[b].off;
         long long cells = 0;
         do {
-            const BlockInfo &B = h->blocks_h[b];
-            cells += (long long)B.bx * B.by * B.bz;
+            cells += (long long)(h->cx[b / (h->gy * h->gz) + 1] - h->cx[b / (h->gy * h->gz)]) *
+                     (h->cy[(b / h->gz) % h->gy + 1] - h->cy[(b / h->gz) % h->gy]) *
+                     (h->cz[b % h->gz + 1] - h->cz[b % h->gz]);
             b++;
-        } while (b < h->nblocks &&
-                 cells + (long long)h->blocks_h[b].bx * h->blocks_h[b].by * h->blocks_h[b].bz <=
-                     cap_cells);
+        } while (b < h->nblocks && cells + block_cells(h, b) <= cap_cells);
         g.b1 = b;
-        g.t0 = h->blocks_h[g.b0].tile0;
-        g.t1 = h->blocks_h[g.b1 - 1].tile0 + h->blocks_h[g.b1 - 1].ntiles;
+        g.t0 = g.t1 = 0;
+        g.off = 0;
         gs.push_back(g);
     }
     return gs;
+}
+
+void fill_tiles(const ms_handle *h, std::vector<Group> &gs) {
+    for (Group &g : gs) {
+        g.off = h->blocks_h[g.b0].off;
+        g.t0 = h->blocks_h[g.b0].tile0;
+        g.t1 = h->blocks_h[g.b1 - 1].tile0 + h->blocks_h[g.b1 - 1].ntiles;
+    }
 }
 
 // Enqueue one sweep of every right-hand side from xa into xb (or, final_only,
@@ -433,32 +447,38 @@ ms_status beff_norm(ms_handle *h, const double *b, hipStream_t st, double *out) 
     return beff_norms<T>(h, b, 1, st, out);
 }
 
-// Tile choice when the caller leaves it open: the largest rows-per-thread
-// and x chunk that still give at least kMinTiles workgroups per launch
-// (measured on 512^3 with 64^3 blocks: fewer, fatter tiles win as long as
-// every compute unit gets several workgroups).
+// Tile choice when the caller leaves it open, for launches over blocks
+// [b0, b1): the longest x chunk, then the most rows per thread, that still
+// give at least kMinTiles workgroups per launch (per right-hand side count
+// nrhs).  Measured on 512^3 with 64^3 blocks in cache-sized groups: about
+// 1024 workgroups per launch and chunks of 8-16 planes are best.
 constexpr long long kMinTiles = 1024;
 
-long long count_tiles(const ms_handle *h, int vz, int tx, int rows) {
+long long count_tiles(const ms_handle *h, int vz, int tx, int rows, int b0, int b1) {
     long long n = 0;
-    for (int bi = 0; bi < h->gx; bi++)
-        for (int bj = 0; bj < h->gy; bj++)
-            for (int bk = 0; bk < h->gz; bk++) {
-                const int bx = h->cx[bi + 1] - h->cx[bi], by = h->cy[bj + 1] - h->cy[bj],
-                          bz = h->cz[bk + 1] - h->cz[bk];
-                const long long slots = (long long)((by + rows - 1) / rows) * (bz / vz);
-                n += ((slots + ms::kThreads - 1) / ms::kThreads) * ((bx + tx - 1) / tx);
-            }
+    for (int b = b0; b < b1; b++) {
+        const int bi = b / (h->gy * h->gz), bj = (b / h->gz) % h->gy, bk = b % h->gz;
+        const int bx = h->cx[bi + 1] - h->cx[bi], by = h->cy[bj + 1] - h->cy[bj],
+                  bz = h->cz[bk + 1] - h->cz[bk];
+        const long long slots = (long long)((by + rows - 1) / rows) * (bz / vz);
+        n += ((slots + ms::kThreads - 1) / ms::kThreads) * ((bx + tx - 1) / tx);
+    }
     return n;
 }
 
-void auto_tiling(const ms_handle *h, int vz, int nrhs, int *tx, int *rows) {
-    for (int r : {4, 2, 1})
-        for (int t : {32, 16, 8, 4})
-            if (count_tiles(h, vz, t, r) * nrhs >= kMinTiles) { *tx = t; *rows = r; return; }
+void auto_tiling(const ms_handle *h, int vz, int nrhs, int b0, int b1, int *tx, int *rows) {
+    for (int t : {32, 16, 8, 4})
+        for (int r : {4, 2, 1})
+            if (count_tiles(h, vz, t, r, b0, b1) * nrhs >= kMinTiles) { *tx = t; *rows = r; return; }
     *tx = kTxMin;
     *rows = 1;
 }
+
+// Inner-vector working set of one launch group: the on-package cache
+// (256 MB) holds r, d and both p buffers of the group, so the m inner
+// iterations re-read them from the cache rather than from HBM (measured:
+// 64 blocks of 64^3 in FP32, 32 in FP64 are the fastest groups).
+constexpr long long kGroupBytes = 256ll << 20;
 
 // A HIP graph holding two sweeps (even then odd parity) of one solve
 // configuration, replayed instead of launching the kernels one by one.
@@ -509,12 +529,27 @@ ms_status solve_sync(ms_handle *h, const double *b, double *x, int nrhs, double 
                      const ms_opts &o, ms_stats *stats, hipStream_t st) {
     if (nrhs > h->rhs_cap) return fail(h, MS_ERR_ARG, "more right-hand sides than reserved");
     const int vz = std::min(h->vzmax, (int)(16 / sizeof(T)));
+    // blocks per launch: cache-sized groups by default (-1: all blocks at
+    // once, > 0: that many blocks)
+    long long cap_cells = kGroupBytes / (4 * (long long)sizeof(T) * nrhs);
+    if (o.group_blocks < 0) {
+        cap_cells = h->N;
+    } else if (o.group_blocks > 0) {
+        long long mx = 0;
+        for (int bb = 0; bb < h->nblocks; bb++) mx = std::max(mx, block_cells(h, bb));
+        cap_cells = mx * o.group_blocks;
+    }
+    std::vector<Group> groups = make_groups(h, cap_cells);
+    int gmax = 0;
+    for (size_t q = 0; q < groups.size(); q++)
+        if (groups[q].b1 - groups[q].b0 > groups[gmax].b1 - groups[gmax].b0) gmax = (int)q;
     int tx = 0, rows = 0;
-    auto_tiling(h, vz, nrhs, &tx, &rows);
+    auto_tiling(h, vz, nrhs, groups[gmax].b0, groups[gmax].b1, &tx, &rows);
     if (o.x_chunk > 0) tx = std::max(kTxMin, o.x_chunk);
     if (o.rows == 1 || o.rows == 2 || o.rows == 4) rows = o.rows;
     ms_status s = set_tiling(h, vz, tx, rows, st);
     if (s != MS_OK) return s;
+    fill_tiles(h, groups);
     std::vector<double> nbeff(nrhs, 0.0);
     s = beff_norms<T>(h, b, nrhs, st, nbeff.data());
     if (s != MS_OK) return s;
@@ -527,16 +562,6 @@ ms_status solve_sync(ms_handle *h, const double *b, double *x, int nrhs, double 
     }
     hipLaunchKernelGGL(k_mark_zero_rhs, dim3((nrhs + 63) / 64), dim3(64), 0, st, h->ctrl, nrhs);
     HIPCHK(h, hipGetLastError());
-    // blocks per launch: all of them unless the caller asks for cache-sized
-    // groups (small launches lose more to ramp-up and drain than the cache
-    // gives back)
-    long long cap_cells = h->N;
-    if (o.group_blocks > 0) {
-        long long mx = 0;
-        for (const BlockInfo &B : h->blocks_h) mx = std::max(mx, (long long)B.bx * B.by * B.bz);
-        cap_cells = mx * o.group_blocks;
-    }
-    const std::vector<Group> groups = make_groups(h, cap_cells);
     const Batch bt = batch_of(h, nrhs);
     const long long cells_per_sweep = h->N * (long long)m * nrhs;
     int batch = o.check_every > 0 ? o.check_every
@@ -666,7 +691,7 @@ ms_status solve_async(ms_handle *h, const double *b, double *x, double tol, int 
         return fail(h, MS_ERR_ARG, "asynchronous mode needs staleness >= 1");
     const int vz = std::min(h->vzmax, (int)(16 / sizeof(T)));
     int tx = 0, rows = 0;
-    auto_tiling(h, vz, 1, &tx, &rows);
+    auto_tiling(h, vz, 1, 0, h->nblocks, &tx, &rows);
     if (o.x_chunk > 0) tx = std::max(kTxMin, o.x_chunk);
     if (o.rows == 1 || o.rows == 2 || o.rows == 4) rows = o.rows;
     ms_status s = set_tiling(h, vz, tx, rows, st);
