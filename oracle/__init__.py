@@ -24,6 +24,12 @@ approach to solving linear systems using two-stage multisplitting":
   old, neighbour values); deterministic for a given delay table.
 * ``cg``: the conventional global Krylov solver the paper compares against
   (Section 4), here CG.
+* ``block_jacobi_ovl`` / ``ovl_sweep_some`` / ``overlap_cells``: overlapping
+  blocks (the block overlap of Section 3.2 and the multisplitting weights of
+  Section 2.3).  A block's region is its own cells plus slabs of depth o
+  across each face that has a neighbour (the cells a face halo of depth o
+  carries, giving the paper's o(2xy+2yz+2zx) extra unknowns); each block
+  solves on its region and every cell takes its owner's new value.
 """
 from __future__ import annotations
 
@@ -84,6 +90,17 @@ class Oracle:
         L.or_block_jacobi_async.restype = C.c_int
         L.or_cg.argtypes = [C.c_long] * 3 + [_dp, _dp, C.c_double, C.c_int, _dp, _ip]
         L.or_cg.restype = C.c_int
+        L.or_overlap_cells.argtypes = ([C.c_long] * 3 + [C.c_int] * 3 + [_ip] * 3 +
+                                       [C.c_int, C.c_int])
+        L.or_overlap_cells.restype = C.c_long
+        L.or_block_jacobi_ovl.argtypes = ([C.c_long] * 3 + [C.c_int] * 3 + [_ip] * 3 +
+                                          [C.c_int, _dp, _dp, C.c_double, C.c_int, C.c_double,
+                                           C.c_int, _dp, _ip, _lp])
+        L.or_block_jacobi_ovl.restype = C.c_int
+        L.or_ovl_sweep_some.argtypes = ([C.c_long] * 3 + [C.c_int] * 3 + [_ip] * 3 +
+                                        [C.c_int, _dp, _dp, C.c_int, _ip, C.c_int, C.c_double,
+                                         _dp])
+        L.or_ovl_sweep_some.restype = C.c_int
         L.or_num_threads.argtypes = []
         L.or_num_threads.restype = C.c_int
         self.L = L
@@ -164,6 +181,45 @@ class Oracle:
         st = self.L.or_block_sweep_some(nx, ny, nz, len(cx) - 1, len(cy) - 1, len(cz) - 1,
                                         pcx, pcy, pcz, self._d(beff), self._d(x), len(bl),
                                         pbl, m, inner_tol, self._d(out))
+        assert st == OK, st
+        return out
+
+    def overlap_cells(self, shape, cuts, overlap, block) -> int:
+        """Cells in block `block`'s region for overlap `overlap`."""
+        nx, ny, nz = shape
+        cx, pcx = self._i(cuts[0]); cy, pcy = self._i(cuts[1]); cz, pcz = self._i(cuts[2])
+        return int(self.L.or_overlap_cells(nx, ny, nz, len(cx) - 1, len(cy) - 1, len(cz) - 1,
+                                           pcx, pcy, pcz, int(overlap), int(block)))
+
+    def block_jacobi_ovl(self, beff, x0, cuts, overlap, tol, m, inner_tol=0.0,
+                         max_sweeps=100000):
+        """Synchronous block Jacobi on overlapping regions (FP64).
+
+        Returns (status, x, sweeps, inner_iters, history)."""
+        beff = np.ascontiguousarray(beff, dtype=np.float64)
+        x = np.array(x0, dtype=np.float64, order="C", copy=True)
+        nx, ny, nz = x.shape
+        cx, pcx = self._i(cuts[0]); cy, pcy = self._i(cuts[1]); cz, pcz = self._i(cuts[2])
+        hist = np.full(max_sweeps + 1, np.nan)
+        sw = C.c_int(0); inn = C.c_long(0)
+        st = self.L.or_block_jacobi_ovl(nx, ny, nz, len(cx) - 1, len(cy) - 1, len(cz) - 1,
+                                        pcx, pcy, pcz, int(overlap), self._d(beff), self._d(x),
+                                        tol, m, inner_tol, max_sweeps, self._d(hist),
+                                        C.byref(sw), C.byref(inn))
+        return st, x, sw.value, inn.value, hist[: sw.value + 1]
+
+    def ovl_sweep_some(self, beff, x, cuts, overlap, blocks, m, inner_tol=0.0):
+        """New owned values of the listed blocks after one overlapping sweep
+        from x (other cells = x)."""
+        beff = np.ascontiguousarray(beff, dtype=np.float64)
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        nx, ny, nz = x.shape
+        cx, pcx = self._i(cuts[0]); cy, pcy = self._i(cuts[1]); cz, pcz = self._i(cuts[2])
+        bl, pbl = self._i(blocks)
+        out = x.copy()
+        st = self.L.or_ovl_sweep_some(nx, ny, nz, len(cx) - 1, len(cy) - 1, len(cz) - 1,
+                                      pcx, pcy, pcz, int(overlap), self._d(beff), self._d(x),
+                                      len(bl), pbl, m, inner_tol, self._d(out))
         assert st == OK, st
         return out
 

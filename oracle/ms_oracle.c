@@ -693,3 +693,310 @@ int or_cg(long nx, long ny, long nz, const double *beff, double *x, double tol,
     if (iters_out) *iters_out = it;
     return status;
 }
+
+/* ------------------------------------------------------------------ */
+/* Overlapping blocks (Section 3.2, choice of parameters: the block     */
+/* overlap, and the multisplitting weights D_i of Section 2.3)          */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Reading of the paper: the region of block b for overlap o holds the
+ * block's own cells and, across each face that has a neighbouring block,
+ * the slab of depth o beyond that face (clipped to the interior): the cells
+ * a face halo of depth o carries.  Cells off the block's box along two or
+ * more axes (edge and corner regions) are not in it.  That is what gives
+ * o(2xy + 2yz + 2zx) extra unknowns for an x*y*z block with neighbours on
+ * every side, the count the paper states.
+ *
+ * Each block solves A_RR d = r_R on its region R (the principal submatrix
+ * of A: neighbours outside R are zero, i.e. a zero correction there), and
+ * the new value of every cell is the one computed by the block that owns
+ * it: the weights D_i of the multisplitting B = sum_i D_i M_i^{-1} N_i are
+ * the indicator of block i's own cells (restricted weighting).  With o = 0
+ * this is the block Jacobi iteration above.
+ */
+
+/* how far coordinate c lies outside [a, a + len) (0 when inside) */
+static long outside_by(long c, long a, long len)
+{
+    if (c < a) return a - c;
+    if (c >= a + len) return c - (a + len) + 1;
+    return 0;
+}
+
+/* 1 when interior cell (I,J,K) belongs to block b's region for overlap o */
+static int in_region(const part_t *P, int b, int o, long I, long J, long K)
+{
+    if (I < 0 || J < 0 || K < 0 || I >= P->nx || J >= P->ny || K >= P->nz) return 0;
+    int i0, j0, k0, bx, by, bz;
+    block_range(P, b, &i0, &j0, &k0, &bx, &by, &bz);
+    long dx = outside_by(I, i0, bx), dy = outside_by(J, j0, by), dz = outside_by(K, k0, bz);
+#if ORACLE_MUTANT == 11
+    /* planted mistake: the region is the whole box grown by o (edges and
+     * corners included) */
+    return dx <= o && dy <= o && dz <= o;
+#else
+    int nout = (dx > 0) + (dy > 0) + (dz > 0);
+    if (nout == 0) return 1;
+    if (nout > 1) return 0;
+    return dx + dy + dz <= o;
+#endif
+}
+
+typedef struct {
+    long n;          /* cells in the region */
+    long *cell;      /* region cell -> global index, in C order of the grid */
+    int *nbr;        /* region cell -> 6 region neighbours (-x,+x,-y,+y,-z,+z; -1 none) */
+    unsigned char *own;  /* region cell -> 1 when block b owns it */
+} region_t;
+
+static void region_free(region_t *R)
+{
+    free(R->cell); free(R->nbr); free(R->own);
+    R->cell = NULL; R->nbr = NULL; R->own = NULL; R->n = 0;
+}
+
+/* Enumerate block b's region (cells in C order) and its neighbour table. */
+static void region_build(const part_t *P, int b, int o, region_t *R)
+{
+    long nx = P->nx, ny = P->ny, nz = P->nz;
+    int i0, j0, k0, bx, by, bz;
+    block_range(P, b, &i0, &j0, &k0, &bx, &by, &bz);
+    /* a box that contains the region: the block grown by o, clipped */
+    long a0 = i0 - o < 0 ? 0 : i0 - o, a1 = i0 + bx + o > nx ? nx : i0 + bx + o;
+    long b0 = j0 - o < 0 ? 0 : j0 - o, b1 = j0 + by + o > ny ? ny : j0 + by + o;
+    long c0 = k0 - o < 0 ? 0 : k0 - o, c1 = k0 + bz + o > nz ? nz : k0 + bz + o;
+    long ex = a1 - a0, ey = b1 - b0, ez = c1 - c0;
+    long *map = (long *)malloc(sizeof(long) * (size_t)(ex * ey * ez));
+    long n = 0;
+    for (long I = a0; I < a1; I++)
+        for (long J = b0; J < b1; J++)
+            for (long K = c0; K < c1; K++) {
+                long q = ((I - a0) * ey + (J - b0)) * ez + (K - c0);
+                map[q] = in_region(P, b, o, I, J, K) ? n++ : -1;
+            }
+    R->n = n;
+    R->cell = (long *)malloc(sizeof(long) * (size_t)(n > 0 ? n : 1));
+    R->nbr = (int *)malloc(sizeof(int) * 6 * (size_t)(n > 0 ? n : 1));
+    R->own = (unsigned char *)malloc((size_t)(n > 0 ? n : 1));
+    for (long I = a0; I < a1; I++)
+        for (long J = b0; J < b1; J++)
+            for (long K = c0; K < c1; K++) {
+                long q = ((I - a0) * ey + (J - b0)) * ez + (K - c0);
+                long c = map[q];
+                if (c < 0) continue;
+                R->cell[c] = IDX(I, J, K);
+                R->own[c] = outside_by(I, i0, bx) == 0 && outside_by(J, j0, by) == 0 &&
+                            outside_by(K, k0, bz) == 0;
+                long nb[6] = {-1, -1, -1, -1, -1, -1};
+                if (I > a0) nb[0] = map[q - ey * ez];
+                if (I < a1 - 1) nb[1] = map[q + ey * ez];
+                if (J > b0) nb[2] = map[q - ez];
+                if (J < b1 - 1) nb[3] = map[q + ez];
+                if (K > c0) nb[4] = map[q - 1];
+                if (K < c1 - 1) nb[5] = map[q + 1];
+                for (int f = 0; f < 6; f++) R->nbr[6 * c + f] = (int)nb[f];
+            }
+    free(map);
+}
+
+/* q = A_RR p: 6 p minus the region neighbours, in the order -x,+x,-y,+y,-z,+z */
+static void region_apply(const region_t *R, const double *p, double *q)
+{
+    for (long c = 0; c < R->n; c++) {
+        double s = 6.0 * p[c];
+        for (int f = 0; f < 6; f++) {
+            int t = R->nbr[6 * c + f];
+            if (t >= 0) s -= p[t];
+        }
+        q[c] = s;
+    }
+}
+
+/* CG on A_RR d = r from d = 0 (the same recurrences, stops and guard as
+ * block_cg), on the region's cells. */
+static int region_cg(const region_t *R, double *r, double *d, double *p, double *q, int m,
+                     double inner_tol)
+{
+    long n = R->n;
+    for (long t = 0; t < n; t++) { d[t] = 0.0; p[t] = r[t]; }
+    double rho = dot(n, r, r);
+    double rho0 = rho;
+    if (rho == 0.0) return 0;
+    int it = 0;
+    while (it < m) {
+        region_apply(R, p, q);
+        double sigma = dot(n, p, q);
+        if (!(sigma > 0.0)) break;
+        double alpha = rho / sigma;
+        for (long t = 0; t < n; t++) {
+            d[t] += alpha * p[t];
+            r[t] -= alpha * q[t];
+        }
+        it++;
+        double rho_new = dot(n, r, r);
+        if (inner_tol > 0.0 && sqrt(rho_new) <= inner_tol * sqrt(rho0)) break;
+        double beta = rho_new / rho;
+        for (long t = 0; t < n; t++) p[t] = r[t] + beta * p[t];
+        rho = rho_new;
+    }
+    return it;
+}
+
+/* Cells in block b's region for overlap o (-1 on bad arguments). */
+long or_overlap_cells(long nx, long ny, long nz, int gx, int gy, int gz, const int *cx,
+                      const int *cy, const int *cz, int o, int b)
+{
+    part_t P = {nx, ny, nz, gx, gy, gz, cx, cy, cz};
+    if (o < 0 || b < 0 || b >= gx * gy * gz) return -1;
+    if (!check_cuts(cx, gx, nx) || !check_cuts(cy, gy, ny) || !check_cuts(cz, gz, nz))
+        return -1;
+    region_t R;
+    region_build(&P, b, o, &R);
+    long n = R.n;
+    region_free(&R);
+    return n;
+}
+
+/* Region residual r_R = b_eff - A x at the region's cells (global operator:
+ * values outside the region are the halo). */
+static void region_residual(const part_t *P, const region_t *R, const double *beff,
+                            const double *x, double *r)
+{
+    long nx = P->nx, ny = P->ny, nz = P->nz;
+    for (long c = 0; c < R->n; c++) {
+        long G = R->cell[c];
+        long K = G % nz, J = (G / nz) % ny, I = G / (ny * nz);
+        double s = 6.0 * x[G];
+        if (I > 0) s -= x[IDX(I - 1, J, K)];
+        if (I < nx - 1) s -= x[IDX(I + 1, J, K)];
+        if (J > 0) s -= x[IDX(I, J - 1, K)];
+        if (J < ny - 1) s -= x[IDX(I, J + 1, K)];
+        if (K > 0) s -= x[IDX(I, J, K - 1)];
+        if (K < nz - 1) s -= x[IDX(I, J, K + 1)];
+        r[c] = beff[G] - s;
+    }
+}
+
+/* Combine block corrections with the weights D_i: the owner's value. */
+static void region_combine(const region_t *R, const double *d, double *dg)
+{
+    for (long c = 0; c < R->n; c++) {
+#if ORACLE_MUTANT == 12
+        /* planted mistake: every block's correction added at every region
+         * cell (no weights) */
+        dg[R->cell[c]] += d[c];
+#else
+        if (R->own[c]) dg[R->cell[c]] = d[c];
+#endif
+    }
+}
+
+/*
+ * Synchronous block Jacobi with overlap o (o = 0: or_block_jacobi).  Same
+ * arguments, test, history and statuses as or_block_jacobi (FP64 only).
+ */
+int or_block_jacobi_ovl(long nx, long ny, long nz, int gx, int gy, int gz,
+                        const int *cx, const int *cy, const int *cz, int o,
+                        const double *beff, double *x, double tol, int m,
+                        double inner_tol, int max_sweeps, double *history,
+                        int *sweeps_out, long *inner_out)
+{
+    part_t P = {nx, ny, nz, gx, gy, gz, cx, cy, cz};
+    if (sweeps_out) *sweeps_out = 0;
+    if (inner_out) *inner_out = 0;
+    if (nx < 1 || ny < 1 || nz < 1 || m < 1 || max_sweeps < 0 || o < 0) return OR_ARG;
+    if (!check_cuts(cx, gx, nx) || !check_cuts(cy, gy, ny) || !check_cuts(cz, gz, nz))
+        return OR_ARG;
+    long n = nx * ny * nz;
+    int nb = gx * gy * gz;
+    double nbeff = or_norm2(n, beff);
+    if (!isfinite(nbeff)) return OR_NONFINITE;
+    if (nbeff == 0.0) {
+        memset(x, 0, sizeof(double) * (size_t)n);
+        if (history) history[0] = 0.0;
+        return OR_OK;
+    }
+    region_t *R = (region_t *)malloc(sizeof(region_t) * (size_t)nb);
+    double **dloc = (double **)malloc(sizeof(double *) * (size_t)nb);
+    long rmax = 1;
+    for (int b = 0; b < nb; b++) {
+        region_build(&P, b, o, &R[b]);
+        dloc[b] = (double *)malloc(sizeof(double) * (size_t)(R[b].n > 0 ? R[b].n : 1));
+        if (R[b].n > rmax) rmax = R[b].n;
+    }
+    double *r = (double *)malloc(sizeof(double) * (size_t)n);
+    double *dg = (double *)malloc(sizeof(double) * (size_t)n);
+    long inner_total = 0;
+    int status = OR_OK;
+    double res0 = -1.0;
+    int s = 0;
+    for (;;) {
+        /* global residual: every cell counted once, by its owner */
+        double res = blocked_residual_norm(&P, beff, x, r) / nbeff;
+        if (history) history[s] = res;
+        if (!isfinite(res)) { status = OR_NONFINITE; break; }
+        if (res0 < 0.0) res0 = res;
+        if (tol > 0.0 && res <= tol) break;
+        if (res > 1e6 * res0 && res0 > 0.0) { status = OR_DIVERGED; break; }
+        if (s == max_sweeps) { status = tol > 0.0 ? OR_NOT_CONVERGED : OR_OK; break; }
+        /* inner solves on the regions, all from this sweep's residual */
+#pragma omp parallel
+        {
+            double *lr = (double *)malloc(sizeof(double) * (size_t)rmax);
+            double *lp = (double *)malloc(sizeof(double) * (size_t)rmax);
+            double *lq = (double *)malloc(sizeof(double) * (size_t)rmax);
+#pragma omp for schedule(dynamic, 1) reduction(+ : inner_total)
+            for (int b = 0; b < nb; b++) {
+                for (long c = 0; c < R[b].n; c++) lr[c] = r[R[b].cell[c]];
+                inner_total += region_cg(&R[b], lr, dloc[b], lp, lq, m, inner_tol);
+            }
+            free(lr); free(lp); free(lq);
+        }
+        /* x^(k) = x^(k-1) + sum_i D_i (extended correction of block i) */
+        memset(dg, 0, sizeof(double) * (size_t)n);
+        for (int b = 0; b < nb; b++) region_combine(&R[b], dloc[b], dg);
+#pragma omp parallel for schedule(static)
+        for (long t = 0; t < n; t++) x[t] += dg[t];
+        s++;
+    }
+    for (int b = 0; b < nb; b++) { region_free(&R[b]); free(dloc[b]); }
+    free(R); free(dloc); free(r); free(dg);
+    if (sweeps_out) *sweeps_out = s;
+    if (inner_out) *inner_out = inner_total;
+    return status;
+}
+
+/*
+ * One synchronous sweep with overlap o restricted to a list of blocks: the
+ * owned cells of each listed block get x + d (d from m CG iterations on the
+ * block's region); other entries of xout are left untouched.
+ */
+int or_ovl_sweep_some(long nx, long ny, long nz, int gx, int gy, int gz,
+                      const int *cx, const int *cy, const int *cz, int o,
+                      const double *beff, const double *x, int nlist,
+                      const int *blocks, int m, double inner_tol, double *xout)
+{
+    part_t P = {nx, ny, nz, gx, gy, gz, cx, cy, cz};
+    if (o < 0) return OR_ARG;
+    if (!check_cuts(cx, gx, nx) || !check_cuts(cy, gy, ny) || !check_cuts(cz, gz, nz))
+        return OR_ARG;
+    int nb = gx * gy * gz;
+    for (int t = 0; t < nlist; t++)
+        if (blocks[t] < 0 || blocks[t] >= nb) return OR_ARG;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int t = 0; t < nlist; t++) {
+        region_t R;
+        region_build(&P, blocks[t], o, &R);
+        size_t sz = sizeof(double) * (size_t)(R.n > 0 ? R.n : 1);
+        double *lr = (double *)malloc(sz), *ld = (double *)malloc(sz);
+        double *lp = (double *)malloc(sz), *lq = (double *)malloc(sz);
+        region_residual(&P, &R, beff, x, lr);
+        region_cg(&R, lr, ld, lp, lq, m, inner_tol);
+        for (long c = 0; c < R.n; c++)
+            if (R.own[c]) xout[R.cell[c]] = x[R.cell[c]] + ld[c];
+        free(lr); free(ld); free(lp); free(lq);
+        region_free(&R);
+    }
+    return OR_OK;
+}

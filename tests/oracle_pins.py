@@ -293,6 +293,154 @@ def pin_block_sweep_some(o):
         assert np.array_equal(part.ravel()[sets[b]], x0.ravel()[sets[b]])
 
 
+# ----------------------------------------------------------------------
+# overlapping blocks (Section 3.2: block overlap; Section 2.3: weights D_i)
+# ----------------------------------------------------------------------
+
+GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden")
+
+
+def region_index_sets(shape, cuts, overlap):
+    """Brute-force regions: for each block, the flat indices of the cells that
+    are inside the block, or outside it along exactly one axis by at most
+    `overlap` (a face slab), and which of those the block owns."""
+    nx, ny, nz = shape
+    I, J, K = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    out = []
+    cx, cy, cz = cuts
+
+    def dist(c, a, b):
+        return np.where(c < a, a - c, np.where(c >= b, c - b + 1, 0))
+    for a in range(len(cx) - 1):
+        for b in range(len(cy) - 1):
+            for c in range(len(cz) - 1):
+                dx, dy, dz = dist(I, cx[a], cx[a + 1]), dist(J, cy[b], cy[b + 1]), dist(K, cz[c], cz[c + 1])
+                nout = (dx > 0).astype(int) + (dy > 0) + (dz > 0)
+                reg = (nout == 0) | ((nout == 1) & (dx + dy + dz <= overlap))
+                own = nout == 0
+                idx = np.flatnonzero(reg.ravel())
+                out.append((idx, own.ravel()[idx]))
+    return out
+
+
+def pin_overlap_counts(o):
+    """The paper's extra-unknown counts for 50^3 blocks with neighbours on
+    all sides (golden file), a corner block's count o(xy+yz+zx), and the
+    region sizes of a small uneven partition against brute force."""
+    rows = [tuple(int(v) for v in ln.split()) for ln in open(f"{GOLDEN}/overlap_counts.txt")
+            if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 3
+    cuts = [np.array([0, 50, 100, 150])] * 3
+    for ov, extra in rows:
+        assert o.overlap_cells((150, 150, 150), cuts, ov, 13) - 125000 == extra, (ov, extra)
+        assert o.overlap_cells((150, 150, 150), cuts, ov, 0) - 125000 == ov * 3 * 2500
+    shape = (9, 7, 8)
+    cuts = [np.array([0, 2, 6, 9]), np.array([0, 4, 7]), np.array([0, 3, 8])]
+    for ov in (0, 1, 2, 5):
+        sets = region_index_sets(shape, cuts, ov)
+        for b, (idx, _) in enumerate(sets):
+            assert o.overlap_cells(shape, cuts, ov, b) == len(idx), (ov, b)
+
+
+def pin_overlap_zero(o):
+    """Overlap 0 is block Jacobi itself, bit for bit."""
+    shape = (9, 7, 8)
+    cuts = [np.array([0, 2, 6, 9]), np.array([0, 4, 7]), np.array([0, 3, 8])]
+    rng = np.random.default_rng(16)
+    beff = rng.standard_normal(shape)
+    _, xa, sa, ia, ha = o.block_jacobi(beff, np.zeros(shape), cuts, tol=0.0, m=4, max_sweeps=7)
+    _, xb, sb, ib, hb = o.block_jacobi_ovl(beff, np.zeros(shape), cuts, 0, tol=0.0, m=4,
+                                           max_sweeps=7)
+    assert np.array_equal(xa, xb) and sa == sb and ia == ib
+    assert np.array_equal(ha, hb)
+
+
+def _ras_step(A, bf, x, sets):
+    """One restricted-weight sweep with exact region solves (dense)."""
+    r = bf - A @ x
+    xn = x.copy()
+    for idx, own in sets:
+        d = np.linalg.solve(A[np.ix_(idx, idx)], r[idx])
+        xn[idx[own]] = x[idx[own]] + d[own]
+    return xn
+
+
+def pin_overlap_dense_step(o):
+    """Sweeps with region solves run to convergence equal the dense
+    multisplitting step x + sum_i D_i R_i^T A_RR^{-1} R_i (b - A x), D_i the
+    indicator of block i's own cells (overlap 1 and 2, uneven blocks)."""
+    shape = (6, 5, 7)
+    cuts = [np.array([0, 3, 6]), np.array([0, 2, 5]), np.array([0, 4, 7])]
+    A = dense_laplacian(*shape)
+    rng = np.random.default_rng(17)
+    beff = rng.standard_normal(shape)
+    x0 = rng.standard_normal(shape)
+    for ov in (1, 2):
+        sets = region_index_sets(shape, cuts, ov)
+        xr = x0.ravel().copy()
+        for _ in range(3):
+            xr = _ras_step(A, beff.ravel(), xr, sets)
+        st, x, sw, _, _ = o.block_jacobi_ovl(beff, x0, cuts, ov, tol=0.0, m=300,
+                                             inner_tol=1e-15, max_sweeps=3)
+        assert st == 0 and sw == 3
+        assert rel(x.ravel(), xr) < 1e-11, (ov, rel(x.ravel(), xr))
+
+
+def pin_overlap_fixed_point(o):
+    """Overlapping sweeps reach the dense solution."""
+    shape = (8, 7, 6)
+    cuts = [np.array([0, 3, 8]), np.array([0, 4, 7]), np.array([0, 2, 6])]
+    rng = np.random.default_rng(18)
+    beff = rng.standard_normal(shape)
+    xstar = np.linalg.solve(dense_laplacian(*shape), beff.ravel()).reshape(shape)
+    for ov in (1, 3):
+        st, x, sw, _, _ = o.block_jacobi_ovl(beff, np.zeros(shape), cuts, ov, tol=1e-13, m=8,
+                                             max_sweeps=3000)
+        assert st == 0, st
+        assert rel(x, xstar) < 1e-11, (ov, rel(x, xstar))
+
+
+def pin_overlap_contraction(o):
+    """With exact region solves the residual contracts per sweep by the
+    spectral radius of the dense iteration matrix
+    I - sum_i D_i R_i^T A_RR^{-1} R_i A, and overlap lowers that radius
+    (the paper's observation that some overlap speeds convergence)."""
+    shape = (8, 8, 8)
+    cuts = [np.array([0, 4, 8])] * 3
+    A = dense_laplacian(*shape)
+    n = A.shape[0]
+    beff = np.random.default_rng(19).standard_normal(shape)
+    radii = {}
+    for ov in (0, 1):
+        B = np.zeros_like(A)
+        for idx, own in region_index_sets(shape, cuts, ov):
+            inv = np.linalg.inv(A[np.ix_(idx, idx)])
+            B[np.ix_(idx[own], idx)] += inv[own]
+        rho = np.max(np.abs(np.linalg.eigvals(np.eye(n) - B @ A)))
+        st, x, sw, _, hist = o.block_jacobi_ovl(beff, np.zeros(shape), cuts, ov, tol=0.0, m=60,
+                                                inner_tol=1e-15, max_sweeps=45)
+        ratio = (hist[45] / hist[30]) ** (1.0 / 15)
+        assert abs(ratio - rho) < 3e-3, (ov, ratio, rho)
+        radii[ov] = rho
+    assert radii[1] < radii[0] < 1.0, radii
+
+
+def pin_ovl_sweep_some(o):
+    """Per-block overlapping sweep equals the owned cells of a full sweep."""
+    shape = (8, 6, 10)
+    cuts = [np.array([0, 3, 8]), np.array([0, 6]), np.array([0, 4, 10])]
+    rng = np.random.default_rng(20)
+    beff = rng.standard_normal(shape)
+    x0 = rng.standard_normal(shape)
+    _, x1, _, _, _ = o.block_jacobi_ovl(beff, x0, cuts, 2, tol=0.0, m=4, max_sweeps=1)
+    part = o.ovl_sweep_some(beff, x0, cuts, 2, [1, 2], m=4)
+    sets = block_index_sets(shape, cuts)
+    for b in (1, 2):
+        assert np.array_equal(part.ravel()[sets[b]], x1.ravel()[sets[b]])
+    for b in (0, 3):
+        assert np.array_equal(part.ravel()[sets[b]], x0.ravel()[sets[b]])
+
+
 ALL_PINS = [
     pin_operator_dense,
     pin_operator_eigen,
@@ -308,6 +456,12 @@ ALL_PINS = [
     pin_mixed_reference,
     pin_sweep_semantics,
     pin_block_sweep_some,
+    pin_overlap_counts,
+    pin_overlap_zero,
+    pin_overlap_dense_step,
+    pin_overlap_fixed_point,
+    pin_overlap_contraction,
+    pin_ovl_sweep_some,
 ]
 
 # fast subset used against planted-mistake builds

@@ -2,8 +2,9 @@
 caught by at least one pin: a dropped stencil term, a wrong sign in the
 boundary lifting, inverted CG beta and alpha, a wrong sign in the residual
 update, a replace-instead-of-add outer update, a periodic instead of zero
-block boundary, a residual that skips neighbour blocks (no halo), and swapped
-boundary faces."""
+block boundary, a residual that skips neighbour blocks (no halo), swapped
+boundary faces, an overlap region grown into edges and corners, and overlap
+corrections added without the owner weights."""
 import os
 import tempfile
 
@@ -22,6 +23,8 @@ MUTANTS = {
     7: "outer residual without neighbour blocks",
     8: "-x and -y faces exchanged",
     10: "CG alpha inverted",
+    11: "overlap region includes edges and corners",
+    12: "overlap corrections added without weights",
 }
 
 
