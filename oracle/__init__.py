@@ -30,6 +30,11 @@ approach to solving linear systems using two-stage multisplitting":
   across each face that has a neighbour (the cells a face halo of depth o
   carries, giving the paper's o(2xy+2yz+2zx) extra unknowns); each block
   solves on its region and every cell takes its owner's new value.
+* ``multisplit`` / ``multisplit_sweep_some``: the same synchronous method with
+  any overlap and either inner solver: CG, or one GMRES(m) cycle (Sections
+  3.1 and 4: the experiments' inner solver was GMRES), Arnoldi with classical
+  Gram-Schmidt and Givens rotations, minimising the block residual over the
+  Krylov space.
 """
 from __future__ import annotations
 
@@ -101,6 +106,14 @@ class Oracle:
                                         [C.c_int, _dp, _dp, C.c_int, _ip, C.c_int, C.c_double,
                                          _dp])
         L.or_ovl_sweep_some.restype = C.c_int
+        L.or_multisplit.argtypes = ([C.c_long] * 3 + [C.c_int] * 3 + [_ip] * 3 +
+                                    [C.c_int, C.c_int, _dp, _dp, C.c_double, C.c_int,
+                                     C.c_double, C.c_int, _dp, _ip, _lp])
+        L.or_multisplit.restype = C.c_int
+        L.or_multisplit_sweep_some.argtypes = ([C.c_long] * 3 + [C.c_int] * 3 + [_ip] * 3 +
+                                               [C.c_int, C.c_int, _dp, _dp, C.c_int, _ip,
+                                                C.c_int, C.c_double, _dp])
+        L.or_multisplit_sweep_some.restype = C.c_int
         L.or_num_threads.argtypes = []
         L.or_num_threads.restype = C.c_int
         self.L = L
@@ -220,6 +233,41 @@ class Oracle:
         st = self.L.or_ovl_sweep_some(nx, ny, nz, len(cx) - 1, len(cy) - 1, len(cz) - 1,
                                       pcx, pcy, pcz, int(overlap), self._d(beff), self._d(x),
                                       len(bl), pbl, m, inner_tol, self._d(out))
+        assert st == OK, st
+        return out
+
+    INNER = {"cg": 0, "gmres": 1}
+
+    def multisplit(self, beff, x0, cuts, tol, m, overlap=0, inner="cg", inner_tol=0.0,
+                   max_sweeps=100000):
+        """Synchronous multisplitting, any overlap, CG or GMRES inner solves.
+
+        Returns (status, x, sweeps, inner_iters, history)."""
+        beff = np.ascontiguousarray(beff, dtype=np.float64)
+        x = np.array(x0, dtype=np.float64, order="C", copy=True)
+        nx, ny, nz = x.shape
+        cx, pcx = self._i(cuts[0]); cy, pcy = self._i(cuts[1]); cz, pcz = self._i(cuts[2])
+        hist = np.full(max_sweeps + 1, np.nan)
+        sw = C.c_int(0); inn = C.c_long(0)
+        st = self.L.or_multisplit(nx, ny, nz, len(cx) - 1, len(cy) - 1, len(cz) - 1,
+                                  pcx, pcy, pcz, int(overlap), self.INNER[inner], self._d(beff),
+                                  self._d(x), tol, m, inner_tol, max_sweeps, self._d(hist),
+                                  C.byref(sw), C.byref(inn))
+        return st, x, sw.value, inn.value, hist[: sw.value + 1]
+
+    def multisplit_sweep_some(self, beff, x, cuts, blocks, m, overlap=0, inner="cg",
+                              inner_tol=0.0):
+        """New owned values of the listed blocks after one sweep from x."""
+        beff = np.ascontiguousarray(beff, dtype=np.float64)
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        nx, ny, nz = x.shape
+        cx, pcx = self._i(cuts[0]); cy, pcy = self._i(cuts[1]); cz, pcz = self._i(cuts[2])
+        bl, pbl = self._i(blocks)
+        out = x.copy()
+        st = self.L.or_multisplit_sweep_some(nx, ny, nz, len(cx) - 1, len(cy) - 1, len(cz) - 1,
+                                             pcx, pcy, pcz, int(overlap), self.INNER[inner],
+                                             self._d(beff), self._d(x), len(bl), pbl, m,
+                                             inner_tol, self._d(out))
         assert st == OK, st
         return out
 

@@ -892,9 +892,22 @@ static void region_combine(const region_t *R, const double *d, double *dg)
     }
 }
 
+/* Forward declarations: the generic drivers below (any overlap, CG or
+ * GMRES inner solves). */
+int or_multisplit(long nx, long ny, long nz, int gx, int gy, int gz,
+                  const int *cx, const int *cy, const int *cz, int o, int inner,
+                  const double *beff, double *x, double tol, int m,
+                  double inner_tol, int max_sweeps, double *history,
+                  int *sweeps_out, long *inner_out);
+int or_multisplit_sweep_some(long nx, long ny, long nz, int gx, int gy, int gz,
+                             const int *cx, const int *cy, const int *cz, int o, int inner,
+                             const double *beff, const double *x, int nlist,
+                             const int *blocks, int m, double inner_tol, double *xout);
+
 /*
- * Synchronous block Jacobi with overlap o (o = 0: or_block_jacobi).  Same
- * arguments, test, history and statuses as or_block_jacobi (FP64 only).
+ * Synchronous block Jacobi with overlap o and CG inner solves (o = 0:
+ * or_block_jacobi).  Same arguments, test, history and statuses as
+ * or_block_jacobi (FP64 only).
  */
 int or_block_jacobi_ovl(long nx, long ny, long nz, int gx, int gy, int gz,
                         const int *cx, const int *cy, const int *cz, int o,
@@ -902,10 +915,141 @@ int or_block_jacobi_ovl(long nx, long ny, long nz, int gx, int gy, int gz,
                         double inner_tol, int max_sweeps, double *history,
                         int *sweeps_out, long *inner_out)
 {
+    return or_multisplit(nx, ny, nz, gx, gy, gz, cx, cy, cz, o, 0, beff, x, tol, m,
+                         inner_tol, max_sweeps, history, sweeps_out, inner_out);
+}
+
+/*
+ * One synchronous sweep with overlap o and CG inner solves restricted to a
+ * list of blocks: the owned cells of each listed block get x + d (d from m
+ * CG iterations on the block's region); other entries of xout are left
+ * untouched.
+ */
+int or_ovl_sweep_some(long nx, long ny, long nz, int gx, int gy, int gz,
+                      const int *cx, const int *cy, const int *cz, int o,
+                      const double *beff, const double *x, int nlist,
+                      const int *blocks, int m, double inner_tol, double *xout)
+{
+    return or_multisplit_sweep_some(nx, ny, nz, gx, gy, gz, cx, cy, cz, o, 0, beff, x, nlist,
+                                    blocks, m, inner_tol, xout);
+}
+
+/* ------------------------------------------------------------------ */
+/* Inner stage with GMRES (Sections 3.1 and 4: the experiments used     */
+/* GMRES as the inner Krylov solver; Section 3.2: a maximum number of   */
+/* inner iterations)                                                    */
+/* ------------------------------------------------------------------ */
+
+/*
+ * One GMRES(m) cycle on A_RR d = r from d = 0 (the region of a block; with
+ * overlap 0 the block itself).  Arnoldi builds an orthonormal basis
+ * v_0 = r/||r||, v_1, ... of the Krylov space span{r, A r, A^2 r, ...}: each
+ * new vector w = A v_j is orthogonalised against every earlier basis
+ * vector with coefficients taken from the same w (classical Gram-Schmidt)
+ * and normalised; the (k+1) x k Hessenberg matrix of coefficients is
+ * reduced to triangular form by Givens rotations as it grows, which also
+ * gives the least-squares residual |g_{k}|.  d = V y minimises
+ * ||r - A_RR d||_2 over the Krylov space, with y from the triangular solve.
+ * Stops after m steps, when |g_k| <= inner_tol * ||r|| (inner_tol > 0), or
+ * when the new vector vanishes (the Krylov space is invariant: exact).
+ * Returns the steps taken.
+ */
+static int region_gmres(const region_t *R, const double *r, double *d, int m,
+                        double inner_tol)
+{
+    long n = R->n;
+    for (long t = 0; t < n; t++) d[t] = 0.0;
+    double beta = sqrt(dot(n, r, r));
+    if (beta == 0.0) return 0;
+    double *V = (double *)malloc(sizeof(double) * (size_t)(n * (m + 1)));
+    double *w = (double *)malloc(sizeof(double) * (size_t)n);
+    double *H = (double *)calloc((size_t)((m + 1) * m), sizeof(double)); /* H[i*m + j] */
+    double *cs = (double *)malloc(sizeof(double) * (size_t)m);
+    double *sn = (double *)malloc(sizeof(double) * (size_t)m);
+    double *g = (double *)calloc((size_t)(m + 1), sizeof(double));
+    double *y = (double *)malloc(sizeof(double) * (size_t)m);
+    for (long t = 0; t < n; t++) V[t] = r[t] / beta;
+    g[0] = beta;
+    int k = 0;
+    for (int j = 0; j < m; j++) {
+        double *vj = V + (long)j * n;
+        region_apply(R, vj, w);
+        /* classical Gram-Schmidt: all coefficients from the same w */
+        for (int i = 0; i <= j; i++) {
+#if ORACLE_MUTANT == 14
+            /* planted mistake: the newest basis vector is left out */
+            if (i == j) { H[i * m + j] = 0.0; continue; }
+#endif
+            H[i * m + j] = dot(n, w, V + (long)i * n);
+        }
+        for (int i = 0; i <= j; i++) {
+            const double hij = H[i * m + j];
+            const double *vi = V + (long)i * n;
+            for (long t = 0; t < n; t++) w[t] -= hij * vi[t];
+        }
+        double hn = sqrt(dot(n, w, w));
+        H[(j + 1) * m + j] = hn;
+        /* earlier rotations applied to the new column */
+#if ORACLE_MUTANT != 13
+        for (int i = 0; i < j; i++) {
+            double a = H[i * m + j], b = H[(i + 1) * m + j];
+            H[i * m + j] = cs[i] * a + sn[i] * b;
+            H[(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+        }
+#endif
+        double a = H[j * m + j];
+        double den = sqrt(a * a + hn * hn);
+        if (!(den > 0.0)) break;                  /* nothing left to reduce */
+        cs[j] = a / den;
+        sn[j] = hn / den;
+        H[j * m + j] = den;
+        H[(j + 1) * m + j] = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        k = j + 1;
+        if (!(hn > 0.0)) break;                   /* invariant Krylov space: exact */
+        double *vn = V + (long)(j + 1) * n;
+        for (long t = 0; t < n; t++) vn[t] = w[t] / hn;
+        if (inner_tol > 0.0 && fabs(g[j + 1]) <= inner_tol * beta) break;
+    }
+    /* back substitution R y = g, then d = V y */
+    for (int i = k - 1; i >= 0; i--) {
+        double s = g[i];
+        for (int l = i + 1; l < k; l++) s -= H[i * m + l] * y[l];
+        y[i] = s / H[i * m + i];
+    }
+    for (int i = 0; i < k; i++) {
+        const double *vi = V + (long)i * n;
+        for (long t = 0; t < n; t++) d[t] += y[i] * vi[t];
+    }
+    free(V); free(w); free(H); free(cs); free(sn); free(g); free(y);
+    return k;
+}
+
+/* Inner solve on a region: 0 = CG, 1 = GMRES.  r is overwritten by CG. */
+static int region_inner(const region_t *R, int inner, double *r, double *d, double *p,
+                        double *q, int m, double inner_tol)
+{
+    if (inner == 1) return region_gmres(R, r, d, m, inner_tol);
+    return region_cg(R, r, d, p, q, m, inner_tol);
+}
+
+/*
+ * Synchronous two-stage multisplitting with overlap o (0 = plain blocks)
+ * and inner solver `inner` (0 = CG, 1 = GMRES).  Same test, history and
+ * statuses as or_block_jacobi (FP64).
+ */
+int or_multisplit(long nx, long ny, long nz, int gx, int gy, int gz,
+                  const int *cx, const int *cy, const int *cz, int o, int inner,
+                  const double *beff, double *x, double tol, int m,
+                  double inner_tol, int max_sweeps, double *history,
+                  int *sweeps_out, long *inner_out)
+{
     part_t P = {nx, ny, nz, gx, gy, gz, cx, cy, cz};
     if (sweeps_out) *sweeps_out = 0;
     if (inner_out) *inner_out = 0;
     if (nx < 1 || ny < 1 || nz < 1 || m < 1 || max_sweeps < 0 || o < 0) return OR_ARG;
+    if (inner != 0 && inner != 1) return OR_ARG;
     if (!check_cuts(cx, gx, nx) || !check_cuts(cy, gy, ny) || !check_cuts(cz, gz, nz))
         return OR_ARG;
     long n = nx * ny * nz;
@@ -949,7 +1093,7 @@ int or_block_jacobi_ovl(long nx, long ny, long nz, int gx, int gy, int gz,
 #pragma omp for schedule(dynamic, 1) reduction(+ : inner_total)
             for (int b = 0; b < nb; b++) {
                 for (long c = 0; c < R[b].n; c++) lr[c] = r[R[b].cell[c]];
-                inner_total += region_cg(&R[b], lr, dloc[b], lp, lq, m, inner_tol);
+                inner_total += region_inner(&R[b], inner, lr, dloc[b], lp, lq, m, inner_tol);
             }
             free(lr); free(lp); free(lq);
         }
@@ -967,18 +1111,16 @@ int or_block_jacobi_ovl(long nx, long ny, long nz, int gx, int gy, int gz,
     return status;
 }
 
-/*
- * One synchronous sweep with overlap o restricted to a list of blocks: the
- * owned cells of each listed block get x + d (d from m CG iterations on the
- * block's region); other entries of xout are left untouched.
- */
-int or_ovl_sweep_some(long nx, long ny, long nz, int gx, int gy, int gz,
-                      const int *cx, const int *cy, const int *cz, int o,
-                      const double *beff, const double *x, int nlist,
-                      const int *blocks, int m, double inner_tol, double *xout)
+/* One synchronous sweep (overlap o, inner solver `inner`) restricted to a
+ * list of blocks: the owned cells of each listed block get x + d; other
+ * entries of xout are left untouched. */
+int or_multisplit_sweep_some(long nx, long ny, long nz, int gx, int gy, int gz,
+                             const int *cx, const int *cy, const int *cz, int o, int inner,
+                             const double *beff, const double *x, int nlist,
+                             const int *blocks, int m, double inner_tol, double *xout)
 {
     part_t P = {nx, ny, nz, gx, gy, gz, cx, cy, cz};
-    if (o < 0) return OR_ARG;
+    if (o < 0 || (inner != 0 && inner != 1)) return OR_ARG;
     if (!check_cuts(cx, gx, nx) || !check_cuts(cy, gy, ny) || !check_cuts(cz, gz, nz))
         return OR_ARG;
     int nb = gx * gy * gz;
@@ -992,7 +1134,7 @@ int or_ovl_sweep_some(long nx, long ny, long nz, int gx, int gy, int gz,
         double *lr = (double *)malloc(sz), *ld = (double *)malloc(sz);
         double *lp = (double *)malloc(sz), *lq = (double *)malloc(sz);
         region_residual(&P, &R, beff, x, lr);
-        region_cg(&R, lr, ld, lp, lq, m, inner_tol);
+        region_inner(&R, inner, lr, ld, lp, lq, m, inner_tol);
         for (long c = 0; c < R.n; c++)
             if (R.own[c]) xout[R.cell[c]] = x[R.cell[c]] + ld[c];
         free(lr); free(ld); free(lp); free(lq);

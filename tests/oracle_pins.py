@@ -293,6 +293,24 @@ def pin_block_sweep_some(o):
         assert np.array_equal(part.ravel()[sets[b]], x0.ravel()[sets[b]])
 
 
+def pin_single_block_is_global_cg(o):
+    """A partition into one block: one sweep of m inner iterations from x = 0
+    is m iterations of the global Krylov solve (the same CG recurrences on
+    the same operator and right-hand side, the conventional solver the paper
+    compares against), bit for bit; a second sweep is CG restarted from the
+    new residual."""
+    shape = (7, 6, 9)
+    rng = np.random.default_rng(21)
+    beff = rng.standard_normal(shape)
+    one = [np.array([0, n]) for n in shape]
+    for m in (1, 5, 23):
+        _, xb, sw, inner, _ = o.block_jacobi(beff, np.zeros(shape), one, tol=0.0, m=m,
+                                             max_sweeps=1)
+        st, xc, it, _ = o.cg(beff, np.zeros(shape), tol=0.0, max_iters=m)
+        assert sw == 1 and inner == m and it == m
+        assert np.array_equal(xb, xc), m
+
+
 # ----------------------------------------------------------------------
 # overlapping blocks (Section 3.2: block overlap; Section 2.3: weights D_i)
 # ----------------------------------------------------------------------
@@ -441,6 +459,108 @@ def pin_ovl_sweep_some(o):
         assert np.array_equal(part.ravel()[sets[b]], x0.ravel()[sets[b]])
 
 
+# ----------------------------------------------------------------------
+# GMRES inner solves (Sections 3.1 and 4: the paper's inner solver)
+# ----------------------------------------------------------------------
+
+def _krylov_min_residual(Ab, r, k):
+    """argmin ||r - Ab d|| over span{r, Ab r, ..., Ab^{k-1} r}: orthonormal
+    basis by QR of the power basis, then dense least squares."""
+    K = np.empty((len(r), k))
+    v = r.copy()
+    for i in range(k):
+        K[:, i] = v
+        v = Ab @ v
+    Q, _ = np.linalg.qr(K)
+    y, *_ = np.linalg.lstsq(Ab @ Q, r, rcond=None)
+    return Q @ y
+
+
+def pin_gmres_minimal_residual(o):
+    """One sweep with GMRES(m) inner solves: every block's (or region's)
+    correction minimises its residual over the Krylov space of dimension m
+    (dense least squares), combined with the owner weights; overlap 0 and 1,
+    uneven blocks."""
+    shape = (6, 5, 7)
+    cuts = [np.array([0, 3, 6]), np.array([0, 2, 5]), np.array([0, 4, 7])]
+    A = dense_laplacian(*shape)
+    rng = np.random.default_rng(22)
+    beff = rng.standard_normal(shape)
+    x0 = rng.standard_normal(shape)
+    r = beff.ravel() - A @ x0.ravel()
+    for ov in (0, 1):
+        for m in (1, 3):
+            want = x0.ravel().copy()
+            for idx, own in region_index_sets(shape, cuts, ov):
+                d = _krylov_min_residual(A[np.ix_(idx, idx)], r[idx], m)
+                want[idx[own]] += d[own]
+            st, x, sw, inner, _ = o.multisplit(beff, x0, cuts, tol=0.0, m=m, overlap=ov,
+                                               inner="gmres", max_sweeps=1)
+            assert st == 0 and sw == 1 and inner == 8 * m
+            assert rel(x.ravel(), want) < 1e-11, (ov, m, rel(x.ravel(), want))
+
+
+def pin_gmres_exact_block_jacobi(o):
+    """2x2x2 blocks: A_ii has 4 distinct eigenvalues, so GMRES(4) solves each
+    block exactly and the sweep is Section 3's block formula with dense
+    inverses (the same pin as for CG)."""
+    shape = (4, 6, 4)
+    rng = np.random.default_rng(23)
+    beff = rng.standard_normal(shape)
+    cuts = [np.arange(0, n + 1, 2) for n in shape]
+    A = dense_laplacian(*shape)
+    sets = block_index_sets(shape, cuts)
+    K = 5
+    st, x, sw, _, _ = o.multisplit(beff, np.zeros(shape), cuts, tol=0.0, m=4, inner="gmres",
+                                   max_sweeps=K)
+    assert st == 0 and sw == K
+    xr = np.zeros(A.shape[0])
+    bf = beff.ravel()
+    for _ in range(K):
+        xn = xr.copy()
+        for S in sets:
+            rhs = bf[S] - A[S] @ xr + A[np.ix_(S, S)] @ xr[S]
+            xn[S] = np.linalg.solve(A[np.ix_(S, S)], rhs)
+        xr = xn
+    assert rel(x.ravel(), xr) < 1e-12, rel(x.ravel(), xr)
+
+
+def pin_gmres_fixed_point(o):
+    """GMRES inner solves (with and without overlap) reach the dense solution;
+    CG inner solves through the same driver are block_jacobi bit for bit."""
+    shape = (8, 7, 6)
+    cuts = [np.array([0, 3, 8]), np.array([0, 4, 7]), np.array([0, 2, 6])]
+    rng = np.random.default_rng(24)
+    beff = rng.standard_normal(shape)
+    xstar = np.linalg.solve(dense_laplacian(*shape), beff.ravel()).reshape(shape)
+    for ov in (0, 2):
+        st, x, sw, _, _ = o.multisplit(beff, np.zeros(shape), cuts, tol=1e-13, m=6, overlap=ov,
+                                       inner="gmres", max_sweeps=3000)
+        assert st == 0, st
+        assert rel(x, xstar) < 1e-11, (ov, rel(x, xstar))
+    _, xa, _, _, _ = o.block_jacobi(beff, np.zeros(shape), cuts, tol=0.0, m=4, max_sweeps=6)
+    _, xb, _, _, _ = o.multisplit(beff, np.zeros(shape), cuts, tol=0.0, m=4, max_sweeps=6)
+    assert np.array_equal(xa, xb)
+
+
+def pin_gmres_sweep_some(o):
+    """Per-block GMRES sweep equals the owned cells of a full sweep."""
+    shape = (8, 6, 10)
+    cuts = [np.array([0, 3, 8]), np.array([0, 6]), np.array([0, 4, 10])]
+    rng = np.random.default_rng(25)
+    beff = rng.standard_normal(shape)
+    x0 = rng.standard_normal(shape)
+    for ov in (0, 2):
+        _, x1, _, _, _ = o.multisplit(beff, x0, cuts, tol=0.0, m=5, overlap=ov, inner="gmres",
+                                      max_sweeps=1)
+        part = o.multisplit_sweep_some(beff, x0, cuts, [0, 3], m=5, overlap=ov, inner="gmres")
+        sets = block_index_sets(shape, cuts)
+        for b in (0, 3):
+            assert np.array_equal(part.ravel()[sets[b]], x1.ravel()[sets[b]])
+        for b in (1, 2):
+            assert np.array_equal(part.ravel()[sets[b]], x0.ravel()[sets[b]])
+
+
 ALL_PINS = [
     pin_operator_dense,
     pin_operator_eigen,
@@ -456,12 +576,17 @@ ALL_PINS = [
     pin_mixed_reference,
     pin_sweep_semantics,
     pin_block_sweep_some,
+    pin_single_block_is_global_cg,
     pin_overlap_counts,
     pin_overlap_zero,
     pin_overlap_dense_step,
     pin_overlap_fixed_point,
     pin_overlap_contraction,
     pin_ovl_sweep_some,
+    pin_gmres_minimal_residual,
+    pin_gmres_exact_block_jacobi,
+    pin_gmres_fixed_point,
+    pin_gmres_sweep_some,
 ]
 
 # fast subset used against planted-mistake builds

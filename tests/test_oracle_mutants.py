@@ -4,7 +4,9 @@ boundary lifting, inverted CG beta and alpha, a wrong sign in the residual
 update, a replace-instead-of-add outer update, a periodic instead of zero
 block boundary, a residual that skips neighbour blocks (no halo), swapped
 boundary faces, an overlap region grown into edges and corners, and overlap
-corrections added without the owner weights."""
+corrections added without the owner weights, GMRES least squares without
+the earlier Givens rotations, and a Gram-Schmidt step that skips the newest
+basis vector."""
 import os
 import tempfile
 
@@ -25,6 +27,8 @@ MUTANTS = {
     10: "CG alpha inverted",
     11: "overlap region includes edges and corners",
     12: "overlap corrections added without weights",
+    13: "GMRES without the earlier Givens rotations",
+    14: "GMRES Gram-Schmidt skips the newest vector",
 }
 
 
