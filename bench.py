@@ -77,11 +77,30 @@ def model_sweep_bytes(m: int, mixed: bool) -> int:
 CG_BYTES = {"stencil": 24, "update": 40}   # FP64 global CG, per unknown per iteration
 
 
-def per_kernel(prof, N, byte_lists, extra=None):
+def region_cells(shape, cuts, overlap: int) -> int:
+    """Cells of the inner-solve boxes with overlap (each block grown by the
+    overlap across faces that have a neighbour, clipped to the grid); the
+    grid size when overlap is 0."""
+    per_axis = []
+    for n, c in zip(shape, cuts):
+        c = [int(v) for v in c]
+        per_axis.append([c[t + 1] - c[t] + min(overlap, c[t]) + min(overlap, n - c[t + 1])
+                         for t in range(len(c) - 1)])
+    total = 0
+    for a in per_axis[0]:
+        for b in per_axis[1]:
+            for e in per_axis[2]:
+                total += a * b * e
+    return total
+
+
+def per_kernel(prof, N, byte_lists, extra=None, cells=None):
     """Per kernel class: launches, average duration, compulsory GB/s and the
-    unknowns one launch processes (launches cover groups of blocks)."""
+    unknowns one launch processes (launches cover groups of blocks).  cells:
+    per class, the cells a pass touches (N unless overlap regions are on)."""
     out = {}
     for name, lst in byte_lists.items():
+        N = (cells or {}).get(name, N)
         launches = prof.kernel_launches.get(name, 0)
         ms_tot = prof.kernel_ms.get(name, 0.0)
         if launches == 0 or ms_tot <= 0:
@@ -107,6 +126,10 @@ def run_mode(args, torch, ms, w, mode: str, oracle_check):
     b = torch.from_numpy(w["b"]).to("cuda")
     nrhs = b.shape[0] if kind == "batch" else 1
     h = ms.ms_create(shape, cuts=[list(map(int, c)) for c in cuts], faces=None)
+    ov = args.overlap if kind in ("sync", "batch") else 0
+    if ov:
+        ms.ms_set_overlap(h, ov)
+    NR = region_cells(shape, cuts, ov)   # cells the residual and inner kernels touch
     x = torch.zeros_like(b)
     tuned = {}
     if kind == "batch":
@@ -137,6 +160,9 @@ def run_mode(args, torch, ms, w, mode: str, oracle_check):
     log(f"{mode}: {args.steps} steps in {sec:.3f} s")
     res = {"mode": mode, "steps": args.steps, "seconds": round(sec, 4),
            "ms_per_step": round(1e3 * sec / args.steps, 4), "nrhs": nrhs, "inner_iters": m}
+    if ov:
+        res["overlap"] = ov
+        res["region_cells"] = NR
     if tuned:
         res["autotuned"] = {k: tuned[k] for k in ("rows", "x_chunk", "inner_iters")}
     if kind == "cg":
@@ -144,7 +170,9 @@ def run_mode(args, torch, ms, w, mode: str, oracle_check):
         res["GBps"] = round(bpu * N * args.steps / sec / 1e9, 1)
         res["bytes_per_unknown_step"] = bpu
     else:
-        res["GBps"] = round(sweep_bytes(m, T) * N * nrhs * args.steps / sec / 1e9, 1)
+        fin = dict(kernel_bytes(m, T))["final"]
+        sweep_total = (sweep_bytes(m, T) - fin) * NR + fin * N
+        res["GBps"] = round(sweep_total * nrhs * args.steps / sec / 1e9, 1)
         res["bytes_per_unknown_step"] = sweep_bytes(m, T)
         res["model_GBps"] = round(model_sweep_bytes(m, T == 4) * N * nrhs * args.steps / sec / 1e9, 1)
         res["unknown_iters_per_s"] = N * nrhs * m * args.steps / sec
@@ -156,7 +184,10 @@ def run_mode(args, torch, ms, w, mode: str, oracle_check):
             lists = {}
             for name, by in kernel_bytes(m, T):
                 lists.setdefault(name, []).append(by)
-            res["kernels"] = per_kernel(prof, N * nrhs, lists, extra={"resid": 16 * N * nrhs})
+            cells = {"resid": NR * nrhs, "stencil": NR * nrhs, "update": NR * nrhs,
+                     "final": N * nrhs}
+            res["kernels"] = per_kernel(prof, N * nrhs, lists, extra={"resid": 16 * NR * nrhs},
+                                        cells=cells)
         else:
             res["kernels"] = per_kernel(prof, N, {k: [v] for k, v in CG_BYTES.items()})
     if args.full_solve:
@@ -204,6 +235,47 @@ def run_mode(args, torch, ms, w, mode: str, oracle_check):
     return res
 
 
+def overlap_study(args, torch, ms, inputs):
+    """Sweeps and time to the workload's tolerance for several overlap depths
+    (synchronous, mixed precision): the paper's overlap experiment on this
+    GPU."""
+    w = inputs.workload(args.study_workload)
+    shape, cuts = w["shape"], w["cuts"]
+    b = torch.from_numpy(w["b"]).to("cuda")
+    h = ms.ms_create(shape, cuts=[list(map(int, c)) for c in cuts], faces=None)
+    out = {"workload": args.study_workload, "tol": w["tol"], "inner_iters": args.m,
+           "precision": "mixed", "runs": []}
+    for ov in [int(v) for v in args.overlap_study.split(",")]:
+        ms.ms_set_overlap(h, ov)
+        x = torch.zeros_like(b)
+        ms.ms_solve(h, b, x, 0.0, args.m, "sync", max_sweeps=2, precision="mixed")  # warm
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        total = 0
+        while True:
+            fs = ms.ms_solve(h, b, x, w["tol"], args.m, "sync", precision="mixed",
+                             max_sweeps=args.chunk, raise_on_error=False)
+            total += fs.sweeps
+            if fs.status == ms.MS_OK:
+                break
+            if fs.status != ms.MS_ERR_NOT_CONVERGED or total > 200000:
+                raise RuntimeError(f"overlap {ov}: solve failed with status {fs.status}")
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        rel, _ = ms.ms_residual(h, b, x)
+        out["runs"].append({"overlap": ov, "sweeps_to_tol": total, "seconds": round(sec, 3),
+                            "ms_per_sweep": round(1e3 * sec / max(total, 1), 4),
+                            "region_cells": region_cells(shape, cuts, ov),
+                            "final_rel_residual": rel})
+        log(f"overlap {ov}: {total} sweeps, {sec:.2f} s, residual {rel:.3e}")
+        del x
+    ms.ms_destroy(h)
+    del b
+    torch.cuda.empty_cache()
+    return out
+
+
 def measured_traffic(kernel: str, unknowns_per_launch: int):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a
@@ -225,6 +297,37 @@ def measured_traffic(kernel: str, unknowns_per_launch: int):
     return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
 
 
+def copy_peak(torch, gib: int = 1, reps: int = 5) -> float:
+    """Measured device-to-device copy bandwidth (read + write bytes / time)
+    over `reps` copies of `gib` GiB: the practical streaming ceiling beside
+    the 8 TB/s data-sheet peak."""
+    n = (gib << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbps = 2 * 8 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return round(gbps, 1)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(o, beff, w, m: int, sweeps: int):
     import numpy as np
     shape, cuts = w["shape"], w["cuts"]
@@ -238,6 +341,7 @@ def cpu_baseline(o, beff, w, m: int, sweeps: int):
         "unit": "GB/s",
         "cores": o.num_threads(),
         "kind": "oracle",
+        "cpu_model": cpu_model(),
         "sample": f"{sweeps} FP64 synchronous sweeps of the full {shape[0]}^3 workload "
                   f"(m={m}): {sec:.2f} s, {1e3 * sec / sweeps:.0f} ms per sweep",
         "ms_per_sweep": round(1e3 * sec / sweeps, 1),
@@ -258,6 +362,12 @@ def main():
     ap.add_argument("--chunk", type=int, default=400, help="sweeps per call in --full-solve")
     ap.add_argument("--autotune", action="store_true",
                     help="batched modes: pick tile shape and m with the autotuner first")
+    ap.add_argument("--overlap", type=int, default=0,
+                    help="overlap depth of the blocks in sync and batch modes")
+    ap.add_argument("--overlap-study", default="",
+                    help="comma list of overlap depths: solve the study workload to "
+                         "tolerance for each (sync, mixed)")
+    ap.add_argument("--study-workload", default="poisson256")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for hardware counters)")
     args = ap.parse_args()
@@ -310,14 +420,20 @@ def main():
         else:
             results[mo] = run_mode(args, torch, ms, w, mo,
                                    oracle_check if args.full_solve else None)
+    study = overlap_study(args, torch, ms, inputs) if args.overlap_study else None
+    log("copy probe: device copy bandwidth")
+    copy_gbps = copy_peak(torch)
     head = results[modes[0]]
     roof = None
     if "kernels" in head and head["kernels"]:
         dom_name, dom = max(head["kernels"].items(), key=lambda kv: kv[1]["total_ms"])
-        tb = measured_traffic(f"{dom_name}:{head['mode']}", dom["unknowns_per_launch"])
+        tb = (measured_traffic(f"{dom_name}:{head['mode']}", dom["unknowns_per_launch"])
+              if not head.get("overlap") else None)
         roof = {"bound": "hbm", "kernel": f"k_{dom_name} ({head['mode']})",
                 "achieved": dom["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(dom["GBps"] / HBM_PEAK_GBPS, 4),
+                "copy_GBps": copy_gbps,
+                "frac_of_copy": round(dom["GBps"] / copy_gbps, 4),
                 "traffic": None if tb is None else round(tb / (dom["avg_us"] * 1e-6) / 1e9, 1),
                 "algorithmic_bytes_per_launch": dom["bytes_per_launch"],
                 "traffic_bytes_per_launch": None if tb is None else int(tb),
@@ -355,6 +471,10 @@ def main():
         "cpu_baseline": cpu,
         "modes": results,
     }
+    if args.overlap:
+        line["config"]["overlap"] = args.overlap
+    if study:
+        line["overlap_study"] = study
     print(json.dumps(line), flush=True)
 
 

@@ -55,6 +55,9 @@ typedef enum {
 } ms_status;
 
 typedef enum { MS_SYNC = 0, MS_ASYNC = 1 } ms_mode;
+/* Inner solver of every block (Section 3.1: the framework takes CG or
+ * GMRES; the paper's experiments used GMRES). */
+typedef enum { MS_INNER_CG = 0, MS_INNER_GMRES = 1 } ms_inner;
 typedef enum { MS_FP64 = 0, MS_MIXED = 1 } ms_precision;
 
 /* Interior grid size (points per axis, each >= 1). */
@@ -102,16 +105,22 @@ typedef struct {
     int32_t rows;         /* y rows each thread owns: 1, 2 or 4 (0 = automatic) */
     int32_t workers;      /* async: persistent workgroups, each sweeping one block
                              at a time (0 = automatic) */
+    int32_t inner_solver; /* ms_inner (default MS_INNER_CG).  MS_INNER_GMRES:
+                             sync only, needs ms_reserve_krylov */
 } ms_opts;
 
 /* Kernel classes reported by the profile counters of ms_stats. */
 enum {
     MS_K_RESID = 0,   /* outer residual r = b_eff - A x with halo reads   */
-    MS_K_STENCIL = 1, /* inner CG: p = r + beta p; sigma = p.A_ii p       */
+    MS_K_STENCIL = 1, /* inner CG: p = r + beta p; sigma = p.A_ii p.
+                         GMRES: w = A_ii v_j and its dots with the basis */
     MS_K_UPDATE = 2,  /* inner CG: d += alpha p; r -= alpha A_ii p; r.r   */
-    MS_K_FINAL = 3,   /* last inner step fused with x_new = x + d         */
+    MS_K_FINAL = 3,   /* last inner step fused with x_new = x + d
+                         (GMRES: x_new = x + V y)                        */
     MS_K_CHECK = 4,   /* global residual sum and convergence test          */
     MS_K_OTHER = 5,
+    MS_K_ORTH = 6,    /* GMRES: Gram-Schmidt orthogonalisation + norm     */
+    MS_K_HESS = 7,    /* GMRES: per-block Hessenberg, Givens and solve     */
     MS_K_COUNT = 8
 };
 
@@ -146,6 +155,27 @@ ms_status ms_create(const ms_grid *grid, const ms_blocks *blocks,
 /* Replace the boundary data (same layout as ms_create). */
 ms_status ms_set_bc(ms_handle *h, const ms_bc *bc);
 
+/* Overlapping blocks (Section 3.2: the block overlap parameter; Section 2.3:
+ * the weights D_i of the multisplitting B = sum_i D_i M_i^-1 N_i).  With
+ * overlap o >= 1 the inner solve of block i runs on its region: the block's
+ * own cells plus, across each face that has a neighbouring block, the slab
+ * of depth o beyond that face (clipped to the grid) -- o(2xy+2yz+2zx) extra
+ * unknowns for an x*y*z block with neighbours on all sides.  Edge and corner
+ * cells next to the block are not in the region.  The inner CG solves the
+ * region's principal submatrix of A (zero correction outside the region)
+ * from the residual b_eff - A x at the region's cells, and every cell takes
+ * the correction of the block that owns it (D_i = indicator of block i's
+ * own cells).  The global residual counts each cell once.  o = 0 restores
+ * plain block Jacobi.
+ * Applies to later ms_solve (MS_SYNC only; MS_ASYNC returns
+ * MS_ERR_UNSUPPORTED while o > 0) and ms_solve_batch calls.  Allocates when
+ * the regions need larger inner buffers than the handle holds (never
+ * shrinks them).  Vector z accesses need o to be a multiple of the vector
+ * width, so an odd o runs scalar z accesses.
+ * Errors: MS_ERR_ARG (o < 0 or larger than the grid), MS_ERR_NOMEM (the
+ * handle keeps its previous overlap), MS_ERR_HIP. */
+ms_status ms_set_overlap(ms_handle *h, int32_t overlap);
+
 /* Solve A x = b_eff by two-stage multisplitting (Section 3, Listing 1):
  * each outer sweep computes r = b_eff - A x with neighbour-block values read
  * straight from x (the halo exchange), tests ||r|| / ||b_eff|| <= tol, runs
@@ -179,6 +209,23 @@ ms_status ms_solve(ms_handle *h, const double *b, double *x, double tol,
  * working).  Errors: MS_ERR_ARG (nrhs outside [1, 4096]), MS_ERR_NOMEM (the
  * handle keeps its previous capacity). */
 ms_status ms_reserve(ms_handle *h, int32_t nrhs);
+
+/* GMRES inner solves (Sections 3.1 and 4: the experiments' inner solver;
+ * Section 3.2: a maximum number of inner iterations).  With
+ * opts->inner_solver = MS_INNER_GMRES each block runs one GMRES(m) cycle
+ * per sweep, m = inner_iters, from a zero correction on its residual: an
+ * Arnoldi basis built with classical Gram-Schmidt, the correction that
+ * minimises the block residual over the Krylov space (Givens rotations of
+ * the Hessenberg matrix), early stop when that least-squares residual is
+ * <= inner_tol * ||r_i|| or the space becomes invariant.  Works with
+ * overlap and with several right-hand sides; synchronous mode only.
+ * This call allocates the m+1 basis vectors and per-block state for
+ * inner_iters up to max_inner (1..128) for the handle's current right-hand
+ * side capacity and overlap; call it again after ms_reserve or
+ * ms_set_overlap enlarge those (a GMRES solve otherwise returns
+ * MS_ERR_ARG).  Memory: (max_inner+1) * 8 bytes per unknown and
+ * right-hand side.  Errors: MS_ERR_ARG, MS_ERR_NOMEM. */
+ms_status ms_reserve_krylov(ms_handle *h, int32_t max_inner);
 
 /* Synchronous solve of nrhs independent right-hand sides with the same grid,
  * blocks and boundary data in the same kernel launches (each launch covers

@@ -29,6 +29,7 @@ COMMON = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
 
 SOURCES = [
     ("ms_kernels.hip", []),
+    ("ms_gmres.hip", []),
     ("ms_capi.cpp", ["-x", "hip"]),
 ]
 

@@ -53,7 +53,11 @@ struct ms_handle {
     long long nx = 0, ny = 0, nz = 0, N = 0;
     int gx = 0, gy = 0, gz = 0, nblocks = 0;
     std::vector<int> cx, cy, cz;
-    int vzmax = 1;              // widest vector every z cut and nz allow
+    int vzmax = 1;              // widest vector the z cuts, nz and the overlap allow
+    int vzbase = 1;             // widest vector the z cuts and nz allow
+    int overlap = 0;            // block overlap depth (0: plain block Jacobi)
+    long long inner_n = 0;      // inner-vector elements per right-hand side
+    long long inner_cap = 0;    // ... that the inner buffers hold (>= inner_n)
     // current tiling
     int cur_vz = 0, cur_tx = 0, cur_rows = 0, ntiles = 0;
     std::vector<BlockInfo> blocks_h;
@@ -80,6 +84,13 @@ struct ms_handle {
     int num_cu = 0;
     // right-hand sides the per-RHS buffers hold (ms_reserve grows it)
     int rhs_cap = 1;
+    // GMRES inner solves (ms_reserve_krylov): basis vectors, tile partials
+    // and per-block records, sized for kry_M steps, kry_inner inner
+    // elements, kry_rhs right-hand sides and kry_tiles tiles
+    int kry_M = 0, kry_rhs = 0;
+    long long kry_inner = 0, kry_tiles = 0;
+    void *V = nullptr;
+    double *gpart = nullptr, *gm = nullptr;
     // replayed sweep pairs
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -137,6 +148,28 @@ bool dev_range_ok(const void *p, size_t bytes) {
     return (const char *)p + bytes <= (const char *)base + size;
 }
 
+// Inner-solve box of block b: the block, grown by the overlap depth across
+// every face that has a neighbour (clipped to the grid), with the block's
+// own cells recorded inside it.  The region proper is the box minus its
+// edge and corner parts (cells outside the own box along two or more axes).
+void region_box(const ms_handle *h, int b, BlockInfo &B) {
+    const int bi = b / (h->gy * h->gz), bj = (b / h->gz) % h->gy, bk = b % h->gz;
+    const int o = h->overlap;
+    const int c0[3] = {h->cx[bi], h->cy[bj], h->cz[bk]};
+    const int c1[3] = {h->cx[bi + 1], h->cy[bj + 1], h->cz[bk + 1]};
+    const long long n[3] = {h->nx, h->ny, h->nz};
+    int lo[3], ext[3];
+    for (int a = 0; a < 3; a++) {
+        lo[a] = std::min(o, c0[a]);
+        const int hi = (int)std::min<long long>(o, n[a] - c1[a]);
+        ext[a] = c1[a] - c0[a] + lo[a] + hi;
+    }
+    B.i0 = c0[0] - lo[0]; B.j0 = c0[1] - lo[1]; B.k0 = c0[2] - lo[2];
+    B.bx = ext[0]; B.by = ext[1]; B.bz = ext[2];
+    B.oi = lo[0]; B.oj = lo[1]; B.ok = lo[2];
+    B.obx = c1[0] - c0[0]; B.oby = c1[1] - c0[1]; B.obz = c1[2] - c0[2];
+}
+
 // Build the tile table for vector width vz, x chunk tx and rows per thread.
 ms_status set_tiling(ms_handle *h, int vz, int tx, int rows, hipStream_t st) {
     if (h->cur_vz == vz && h->cur_tx == tx && h->cur_rows == rows) return MS_OK;
@@ -149,10 +182,7 @@ ms_status set_tiling(ms_handle *h, int vz, int tx, int rows, hipStream_t st) {
             for (int bk = 0; bk < h->gz; bk++) {
                 const int b = (bi * h->gy + bj) * h->gz + bk;
                 BlockInfo &B = h->blocks_h[b];
-                B.i0 = h->cx[bi]; B.j0 = h->cy[bj]; B.k0 = h->cz[bk];
-                B.bx = h->cx[bi + 1] - B.i0;
-                B.by = h->cy[bj + 1] - B.j0;
-                B.bz = h->cz[bk + 1] - B.k0;
+                region_box(h, b, B);
                 B.off = off;
                 const long long P = (long long)B.by * B.bz;
                 const long long slots = (long long)((B.by + rows - 1) / rows) * (B.bz / vz);
@@ -186,6 +216,7 @@ Geom geom(const ms_handle *h) {
     g.tx = h->cur_tx;
     g.rows = h->cur_rows;
     g.nblocks = h->nblocks;
+    g.ovl = h->overlap > 0 ? 1 : 0;
     return g;
 }
 
@@ -220,7 +251,7 @@ void free_all(ms_handle *h) {
     void *ps[] = {h->blocks_d, h->tile_block_d, h->x1, h->r, h->d, h->p0, h->p1, h->part64,
                   h->partT, h->psig, h->prhoA, h->prhoB, h->active, h->ctrl, h->history_d,
                   h->scal_d, h->cg_block_d, h->cg_tiles_d, h->version_d, h->claim_d,
-                  h->nbr_d, h->finished_d, h->board_d};
+                  h->nbr_d, h->finished_d, h->board_d, h->V, h->gpart, h->gm};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     for (int t = 0; t < 6; t++)
@@ -275,10 +306,11 @@ ms_status prof_begin(ms_handle *h, bool on) {
 
 // ---- solve pieces -------------------------------------------------------
 
+// Inner-vector cells of block b (its region's box).
 long long block_cells(const ms_handle *h, int b) {
-    const int bi = b / (h->gy * h->gz), bj = (b / h->gz) % h->gy, bk = b % h->gz;
-    return (long long)(h->cx[bi + 1] - h->cx[bi]) * (h->cy[bj + 1] - h->cy[bj]) *
-           (h->cz[bk + 1] - h->cz[bk]);
+    BlockInfo B;
+    region_box(h, b, B);
+    return (long long)B.bx * B.by * B.bz;
 }
 
 template <typename T>
@@ -294,7 +326,9 @@ Bufs<T> bufs(ms_handle *h) {
     B.d = (T *)h->d;
     B.p[0] = (T *)h->p0;
     B.p[1] = (T *)h->p1;
-    B.pT = sizeof(T) == sizeof(double) ? (T *)h->part64 : (T *)h->partT;
+    // FP64 without overlap shares the FP64 partials; with overlap the
+    // region sums (inner CG) and own-cell sums (global residual) differ
+    B.pT = sizeof(T) == sizeof(double) && h->overlap == 0 ? (T *)h->part64 : (T *)h->partT;
     B.psig = (T *)h->psig;
     B.prA = (T *)h->prhoA;
     B.prB = (T *)h->prhoB;
@@ -302,7 +336,8 @@ Bufs<T> bufs(ms_handle *h) {
 }
 
 // Strides of the per-right-hand-side arrays (a right-hand side owns N
-// elements of every vector buffer, tiles_cap partial slots and nblocks flags).
+// elements of b, x and the second outer buffer, inner_n of every inner
+// vector, tiles_cap partial slots and nblocks flags).
 Batch batch_of(const ms_handle *h, int nrhs) {
     Batch bt;
     bt.nt = 0;
@@ -310,6 +345,7 @@ Batch batch_of(const ms_handle *h, int nrhs) {
     bt.vs = h->N;
     bt.ps = h->tiles_cap;
     bt.bs = h->nblocks;
+    bt.is = h->inner_n;
     return bt;
 }
 
@@ -323,9 +359,7 @@ std::vector<Group> make_groups(const ms_handle *h, long long cap_cells) {
         g.b0 = b;
         long long cells = 0;
         do {
-            cells += (long long)(h->cx[b / (h->gy * h->gz) + 1] - h->cx[b / (h->gy * h->gz)]) *
-                     (h->cy[(b / h->gz) % h->gy + 1] - h->cy[(b / h->gz) % h->gy]) *
-                     (h->cz[b % h->gz + 1] - h->cz[b % h->gz]);
+            cells += block_cells(h, b);
             b++;
         } while (b < h->nblocks && cells + block_cells(h, b) <= cap_cells);
         g.b1 = b;
@@ -344,12 +378,72 @@ void fill_tiles(const ms_handle *h, std::vector<Group> &gs) {
     }
 }
 
+ms::GmArgs gm_args(const ms_handle *h) {
+    ms::GmArgs a;
+    a.gm = h->gm;
+    a.gpart = h->gpart;
+    a.kvs = h->kry_inner * h->kry_rhs;
+    a.M = h->kry_M;
+    a.gstride = h->kry_M + 2;
+    a.nblocks = h->nblocks;
+    a.rec_stride = ms::gm_record_doubles(h->kry_M);
+    return a;
+}
+
+// One sweep with GMRES(m) inner solves: per group, the residual (written as
+// the first, unscaled Krylov vector), m Arnoldi steps of four launches, the
+// per-block triangular solves and x_new = x_old + V y on own cells.
+template <typename T>
+ms_status enqueue_sweep_gmres(ms_handle *h, const std::vector<Group> &groups, const double *b,
+                              const double *xa, double *xb, double tol, int m, double inner_tol,
+                              bool final_only, Batch bt, hipStream_t st) {
+    const Geom g = geom(h);
+    const int vz = h->cur_vz;
+    Bufs<T> B = bufs<T>(h);
+    const Faces F = faces(h);
+    T *V = (T *)h->V;
+    const ms::GmArgs a = gm_args(h);
+    for (const Group &G : groups) {
+        {
+            Prof p(h, st, MS_K_RESID);
+            HIPCHK(h, ms::launch_resid<T>(g, vz, G.t0, G.t1, G.off, b, xa, F,
+                                          final_only ? nullptr : V, h->part64, B.pT, h->ctrl,
+                                          bt, st));
+        }
+        if (final_only) continue;
+        {
+            Prof p(h, st, MS_K_HESS);
+            HIPCHK(h, ms::launch_gm_init<T>(g, G.b0, G.b1, B.pT, bt, a, h->ctrl, st));
+        }
+        static const int cls[4] = {MS_K_STENCIL, MS_K_HESS, MS_K_ORTH, MS_K_HESS};
+        for (int j = 0; j < m; j++)
+            for (int part = 0; part < 4; part++) {
+                Prof p(h, st, cls[part]);
+                HIPCHK(h, ms::launch_gm_step<T>(g, vz, G.t0, G.t1, G.b0, G.b1, G.off, V, j,
+                                                inner_tol, bt, a, h->ctrl, st, part));
+            }
+        for (int part = 0; part < 2; part++) {
+            Prof p(h, st, part ? MS_K_FINAL : MS_K_HESS);
+            HIPCHK(h, ms::launch_gm_finish<T>(g, vz, G.t0, G.t1, G.b0, G.b1, G.off, V, xa, xb, bt,
+                                              a, h->ctrl, st, part));
+        }
+    }
+    {
+        Prof p(h, st, MS_K_CHECK);
+        HIPCHK(h, ms::launch_check(h->part64, h->ntiles, tol, final_only ? 1 : 0, h->history_d,
+                                   kHistoryCap, h->ctrl, bt, st));
+    }
+    return MS_OK;
+}
+
 // Enqueue one sweep of every right-hand side from xa into xb (or, final_only,
-// just the residual check of xa).
+// just the residual check of xa).  inner: ms_inner.
 template <typename T>
 ms_status enqueue_sweep(ms_handle *h, const std::vector<Group> &groups, const double *b,
                         const double *xa, double *xb, double tol, int m, double inner_tol,
-                        bool final_only, Batch bt, hipStream_t st) {
+                        int inner, bool final_only, Batch bt, hipStream_t st) {
+    if (inner == MS_INNER_GMRES)
+        return enqueue_sweep_gmres<T>(h, groups, b, xa, xb, tol, m, inner_tol, final_only, bt, st);
     const Geom g = geom(h);
     const int vz = h->cur_vz;
     Bufs<T> B = bufs<T>(h);
@@ -457,13 +551,18 @@ constexpr long long kMinTiles = 1024;
 long long count_tiles(const ms_handle *h, int vz, int tx, int rows, int b0, int b1) {
     long long n = 0;
     for (int b = b0; b < b1; b++) {
-        const int bi = b / (h->gy * h->gz), bj = (b / h->gz) % h->gy, bk = b % h->gz;
-        const int bx = h->cx[bi + 1] - h->cx[bi], by = h->cy[bj + 1] - h->cy[bj],
-                  bz = h->cz[bk + 1] - h->cz[bk];
-        const long long slots = (long long)((by + rows - 1) / rows) * (bz / vz);
-        n += ((slots + ms::kThreads - 1) / ms::kThreads) * ((bx + tx - 1) / tx);
+        BlockInfo B;
+        region_box(h, b, B);
+        const long long slots = (long long)((B.by + rows - 1) / rows) * (B.bz / vz);
+        n += ((slots + ms::kThreads - 1) / ms::kThreads) * ((B.bx + tx - 1) / tx);
     }
     return n;
+}
+
+// Tile-table capacity: the narrowest vector, one row per thread and the
+// smallest x chunk give the most tiles.
+long long tile_capacity(const ms_handle *h) {
+    return count_tiles(h, 1, kTxMin, 1, 0, h->nblocks);
 }
 
 void auto_tiling(const ms_handle *h, int vz, int nrhs, int b0, int b1, int *tx, int *rows) {
@@ -487,7 +586,7 @@ struct GraphKey {
     double *x;
     double tol, inner_tol;
     long long cap_cells;
-    int m, tsize, vz, tx, rows, nrhs;
+    int m, tsize, vz, tx, rows, nrhs, overlap, inner;
 };
 
 void drop_graph(ms_handle *h) {
@@ -500,15 +599,16 @@ void drop_graph(ms_handle *h) {
 template <typename T>
 ms_status sweep_pair_graph(ms_handle *h, const GraphKey &key, const std::vector<Group> &groups,
                            const double *b, double *const X[2], double tol, int m,
-                           double inner_tol, Batch bt) {
+                           double inner_tol, int inner, Batch bt) {
     if (h->graph_exec && memcmp(&h->graph_key, &key, sizeof(GraphKey)) == 0) return MS_OK;
     drop_graph(h);
     if (!h->cap_stream) HIPCHK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-    ms_status s = enqueue_sweep<T>(h, groups, b, X[0], X[1], tol, m, inner_tol, false, bt,
+    ms_status s = enqueue_sweep<T>(h, groups, b, X[0], X[1], tol, m, inner_tol, inner, false, bt,
                                    h->cap_stream);
     if (s == MS_OK)
-        s = enqueue_sweep<T>(h, groups, b, X[1], X[0], tol, m, inner_tol, false, bt, h->cap_stream);
+        s = enqueue_sweep<T>(h, groups, b, X[1], X[0], tol, m, inner_tol, inner, false, bt,
+                             h->cap_stream);
     hipGraph_t gr = nullptr;
     const hipError_t e = hipStreamEndCapture(h->cap_stream, &gr);
     if (s != MS_OK) {
@@ -528,12 +628,18 @@ template <typename T>
 ms_status solve_sync(ms_handle *h, const double *b, double *x, int nrhs, double tol, int m,
                      const ms_opts &o, ms_stats *stats, hipStream_t st) {
     if (nrhs > h->rhs_cap) return fail(h, MS_ERR_ARG, "more right-hand sides than reserved");
+    const bool gmres = o.inner_solver == MS_INNER_GMRES;
+    if (gmres && (m > h->kry_M || nrhs > h->kry_rhs || h->inner_n > h->kry_inner ||
+                  h->tiles_cap > h->kry_tiles))
+        return fail(h, MS_ERR_ARG,
+                    "GMRES inner solves need ms_reserve_krylov(h, >= inner_iters) after the "
+                    "last ms_reserve / ms_set_overlap");
     const int vz = std::min(h->vzmax, (int)(16 / sizeof(T)));
     // blocks per launch: cache-sized groups by default (-1: all blocks at
     // once, > 0: that many blocks)
     long long cap_cells = kGroupBytes / (4 * (long long)sizeof(T) * nrhs);
     if (o.group_blocks < 0) {
-        cap_cells = h->N;
+        cap_cells = h->inner_n;
     } else if (o.group_blocks > 0) {
         long long mx = 0;
         for (int bb = 0; bb < h->nblocks; bb++) mx = std::max(mx, block_cells(h, bb));
@@ -547,6 +653,20 @@ ms_status solve_sync(ms_handle *h, const double *b, double *x, int nrhs, double 
     auto_tiling(h, vz, nrhs, groups[gmax].b0, groups[gmax].b1, &tx, &rows);
     if (o.x_chunk > 0) tx = std::max(kTxMin, o.x_chunk);
     if (o.rows == 1 || o.rows == 2 || o.rows == 4) rows = o.rows;
+    if (gmres) {
+        // GMRES kernels keep a tile's w in registers: one row per thread and
+        // at most gm_max_planes() planes
+        rows = 1;
+        if (o.x_chunk <= 0) {
+            tx = kTxMin;
+            for (int t = ms::gm_max_planes(); t > kTxMin; t /= 2)
+                if (count_tiles(h, vz, t, 1, groups[gmax].b0, groups[gmax].b1) * nrhs >= kMinTiles) {
+                    tx = t;
+                    break;
+                }
+        }
+        tx = std::min(tx, ms::gm_max_planes());
+    }
     ms_status s = set_tiling(h, vz, tx, rows, st);
     if (s != MS_OK) return s;
     fill_tiles(h, groups);
@@ -577,7 +697,9 @@ ms_status solve_sync(ms_handle *h, const double *b, double *x, int nrhs, double 
         key.b = b; key.x = x; key.tol = tol; key.inner_tol = o.inner_tol; key.cap_cells = cap_cells;
         key.m = m; key.tsize = (int)sizeof(T); key.vz = vz; key.tx = tx; key.rows = rows;
         key.nrhs = nrhs;
-        s = sweep_pair_graph<T>(h, key, groups, b, X, tol, m, o.inner_tol, bt);
+        key.overlap = h->overlap;
+        key.inner = o.inner_solver;
+        s = sweep_pair_graph<T>(h, key, groups, b, X, tol, m, o.inner_tol, o.inner_solver, bt);
         if (s != MS_OK) return s;
     }
     std::vector<Ctrl> c(nrhs);
@@ -590,12 +712,12 @@ ms_status solve_sync(ms_handle *h, const double *b, double *x, int nrhs, double 
         }
         for (; q < nb; q++, next++) {
             s = enqueue_sweep<T>(h, groups, b, X[next % 2], X[(next + 1) % 2], tol, m, o.inner_tol,
-                                 false, bt, st);
+                                 o.inner_solver, false, bt, st);
             if (s != MS_OK) return s;
         }
         if (next == o.max_sweeps) {
-            s = enqueue_sweep<T>(h, groups, b, X[next % 2], nullptr, tol, m, o.inner_tol, true, bt,
-                                 st);
+            s = enqueue_sweep<T>(h, groups, b, X[next % 2], nullptr, tol, m, o.inner_tol,
+                                 o.inner_solver, true, bt, st);
             if (s != MS_OK) return s;
         }
         HIPCHK(h, hipMemcpyAsync(c.data(), h->ctrl, sizeof(Ctrl) * nrhs, hipMemcpyDeviceToHost, st));
@@ -655,11 +777,12 @@ ms_status solve_sync(ms_handle *h, const double *b, double *x, int nrhs, double 
 ms_status residual_norms(ms_handle *h, const double *b, const double *x, hipStream_t st,
                          double *nbeff, double *absres) {
     const Geom g = geom(h);
+    double *pT = (double *)h->partT;   // region sums (unused here)
     HIPCHK(h, ms::launch_resid<double>(g, h->cur_vz, 0, h->ntiles, 0, b, nullptr, faces(h),
-                                       nullptr, h->part64, h->part64, nullptr, ms::single_rhs(), st));
+                                       nullptr, h->part64, pT, nullptr, ms::single_rhs(), st));
     HIPCHK(h, ms::launch_sum(h->part64, h->ntiles, h->scal_d, st));
     HIPCHK(h, ms::launch_resid<double>(g, h->cur_vz, 0, h->ntiles, 0, b, x, faces(h), nullptr,
-                                       h->part64, h->part64, nullptr, ms::single_rhs(), st));
+                                       h->part64, pT, nullptr, ms::single_rhs(), st));
     HIPCHK(h, ms::launch_sum(h->part64, h->ntiles, h->scal_d + 1, st));
     double ss[2] = {0.0, 0.0};
     HIPCHK(h, hipMemcpyAsync(ss, h->scal_d, sizeof(ss), hipMemcpyDeviceToHost, st));
@@ -689,6 +812,10 @@ ms_status solve_async(ms_handle *h, const double *b, double *x, double tol, int 
                       const ms_opts &o, ms_stats *stats, hipStream_t st) {
     if (o.staleness < 1)
         return fail(h, MS_ERR_ARG, "asynchronous mode needs staleness >= 1");
+    if (h->overlap > 0)
+        return fail(h, MS_ERR_UNSUPPORTED, "overlapping blocks are synchronous only");
+    if (o.inner_solver != MS_INNER_CG)
+        return fail(h, MS_ERR_UNSUPPORTED, "GMRES inner solves are synchronous only");
     const int vz = std::min(h->vzmax, (int)(16 / sizeof(T)));
     int tx = 0, rows = 0;
     auto_tiling(h, vz, 1, 0, h->nblocks, &tx, &rows);
@@ -816,6 +943,8 @@ ms_status set_cg_tiling(ms_handle *h, int vz, hipStream_t st) {
     const long long slots = ((h->ny + rows - 1) / rows) * (h->nz / vz);
     B.nplane = (int)((slots + ms::kThreads - 1) / ms::kThreads);
     B.ntiles = B.nplane * (int)((h->nx + tx - 1) / tx);
+    B.oi = B.oj = B.ok = 0;
+    B.obx = B.bx; B.oby = B.by; B.obz = B.bz;
     B.pad_ = 0;
     if (B.ntiles > h->cg_cap) return fail(h, MS_ERR_ARG, "global CG tiling exceeds its table");
     std::vector<int> tb(B.ntiles, 0);
@@ -856,6 +985,7 @@ ms_status solve_cg(ms_handle *h, const double *b, double *x, double tol, int max
     g1.tx = h->cg_tx;
     g1.rows = h->cg_rows;
     g1.nblocks = 1;
+    g1.ovl = 0;
     const int nt = h->cg_ntiles;
     double *r = (double *)h->r, *P[2] = {(double *)h->p0, (double *)h->p1};
     double *psig = (double *)h->psig, *prho = (double *)h->prhoA, *scal = h->scal_d;
@@ -939,6 +1069,7 @@ void ms_default_opts(ms_opts *o) {
     o->use_graph = 1;
     o->rows = 0;
     o->workers = 0;
+    o->inner_solver = MS_INNER_CG;
 }
 
 const char *ms_status_string(ms_status s) {
@@ -1003,20 +1134,14 @@ ms_status ms_create(const ms_grid *grid, const ms_blocks *blocks, const ms_bc *b
         for (int c : tmp.cz) ok = ok && (c % w == 0);
         if (ok) { tmp.vzmax = w; break; }
     }
+    tmp.vzbase = tmp.vzmax;
+    tmp.inner_n = tmp.inner_cap = tmp.N;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return fail(nullptr, MS_ERR_HIP, std::string("no HIP device: ") + hipGetErrorString(e));
     ms_handle *h = new ms_handle(std::move(tmp));
     // tile table capacity: narrowest vector, smallest x chunk
-    long long cap = 0;
-    for (int bi = 0; bi < h->gx; bi++)
-        for (int bj = 0; bj < h->gy; bj++)
-            for (int bk = 0; bk < h->gz; bk++) {
-                const long long P = (long long)(h->cy[bj + 1] - h->cy[bj]) * (h->cz[bk + 1] - h->cz[bk]);
-                const long long np = (P + ms::kThreads - 1) / ms::kThreads;
-                const long long nxc = (h->cx[bi + 1] - h->cx[bi] + kTxMin - 1) / kTxMin;
-                cap += np * nxc;
-            }
+    const long long cap = tile_capacity(h);
     // the global-CG tiling (one block = the grid) needs at most as many tiles
     const long long cg_cap = ((h->ny * h->nz + ms::kThreads - 1) / ms::kThreads) *
                              ((h->nx + kTxMin - 1) / kTxMin);
@@ -1124,6 +1249,8 @@ static ms_status check_solve(ms_handle *h, const double *b, double *x, long long
         return fail(h, MS_ERR_ARG, "tol or inner_tol invalid");
     if (o.precision != MS_FP64 && o.precision != MS_MIXED)
         return fail(h, MS_ERR_ARG, "unknown precision");
+    if (o.inner_solver != MS_INNER_CG && o.inner_solver != MS_INNER_GMRES)
+        return fail(h, MS_ERR_ARG, "unknown inner solver");
     return MS_OK;
 }
 
@@ -1165,11 +1292,12 @@ ms_status ms_reserve(ms_handle *h, int32_t nrhs) {
     if (nrhs < 1 || nrhs > 4096) return fail(h, MS_ERR_ARG, "nrhs must be in [1, 4096]");
     if (nrhs <= h->rhs_cap) return MS_OK;
     const size_t vb = sizeof(double) * (size_t)h->N * nrhs;
+    const size_t ib = sizeof(double) * (size_t)h->inner_cap * nrhs;
     const size_t tb = sizeof(double) * (size_t)h->tiles_cap * nrhs;
     void **slots[] = {(void **)&h->x1, &h->r, &h->d, &h->p0, &h->p1, (void **)&h->part64,
                       &h->partT, &h->psig, &h->prhoA, &h->prhoB, (void **)&h->active,
                       (void **)&h->ctrl, (void **)&h->history_d};
-    const size_t sizes[] = {vb, vb, vb, vb, vb, tb, tb, tb, tb, tb,
+    const size_t sizes[] = {vb, ib, ib, ib, ib, tb, tb, tb, tb, tb,
                             sizeof(int) * (size_t)h->nblocks * nrhs, sizeof(Ctrl) * (size_t)nrhs,
                             sizeof(double) * (size_t)kHistoryCap * nrhs};
     constexpr int n = sizeof(sizes) / sizeof(sizes[0]);
@@ -1189,6 +1317,96 @@ ms_status ms_reserve(ms_handle *h, int32_t nrhs) {
         *slots[i] = fresh[i];
     }
     h->rhs_cap = nrhs;
+    return MS_OK;
+}
+
+ms_status ms_set_overlap(ms_handle *h, int32_t overlap) {
+    if (!h) return fail(nullptr, MS_ERR_ARG, "handle is NULL");
+    if (overlap < 0) return fail(h, MS_ERR_ARG, "overlap must be >= 0");
+    if (overlap > std::max(h->nx, std::max(h->ny, h->nz)))
+        return fail(h, MS_ERR_ARG, "overlap exceeds the grid");
+    if (overlap == h->overlap) return MS_OK;
+    // sizes under the new overlap
+    const int old = h->overlap;
+    h->overlap = overlap;
+    long long inner = 0;
+    for (int b = 0; b < h->nblocks; b++) inner += block_cells(h, b);
+    const long long cap = std::max(tile_capacity(h), (long long)h->cg_cap);
+    h->overlap = old;
+    if (cap > (1ll << 30)) return fail(h, MS_ERR_ARG, "too many tiles");
+    // grow the inner vectors and the per-tile arrays when they are too small
+    const size_t R = (size_t)h->rhs_cap;
+    const bool gi = inner > h->inner_cap, gt = cap > h->tiles_cap;
+    void **slots[] = {&h->r, &h->d, &h->p0, &h->p1, (void **)&h->tile_block_d,
+                      (void **)&h->part64, &h->partT, &h->psig, &h->prhoA, &h->prhoB};
+    const size_t ib = sizeof(double) * (size_t)inner * R, tb = sizeof(double) * (size_t)cap * R;
+    const size_t sizes[] = {ib, ib, ib, ib, sizeof(int) * (size_t)cap, tb, tb, tb, tb, tb};
+    const bool grow[] = {gi, gi, gi, gi, gt, gt, gt, gt, gt, gt};
+    constexpr int n = sizeof(sizes) / sizeof(sizes[0]);
+    void *fresh[n] = {};
+    for (int i = 0; i < n; i++) {
+        if (!grow[i]) continue;
+        const hipError_t e = hipMalloc(&fresh[i], sizes[i]);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            for (int j = 0; j < i; j++)
+                if (fresh[j]) (void)hipFree(fresh[j]);
+            return fail(h, e == hipErrorOutOfMemory ? MS_ERR_NOMEM : MS_ERR_HIP,
+                        std::string("ms_set_overlap: ") + hipGetErrorString(e));
+        }
+    }
+    drop_graph(h);
+    for (int i = 0; i < n; i++) {
+        if (!grow[i]) continue;
+        (void)hipFree(*slots[i]);
+        *slots[i] = fresh[i];
+    }
+    if (gi) h->inner_cap = inner;
+    if (gt) h->tiles_cap = (int)cap;
+    h->overlap = overlap;
+    h->inner_n = inner;
+    // the vector width must also divide the overlap (so it divides every
+    // region's z offset and extent)
+    h->vzmax = 1;
+    for (int w : {4, 2})
+        if (h->vzbase % w == 0 && overlap % w == 0) { h->vzmax = w; break; }
+    h->cur_vz = 0;
+    return set_tiling(h, std::min(h->vzmax, 2), 16, 1, nullptr);
+}
+
+ms_status ms_reserve_krylov(ms_handle *h, int32_t max_inner) {
+    if (!h) return fail(nullptr, MS_ERR_ARG, "handle is NULL");
+    if (max_inner < 1 || max_inner > 128) return fail(h, MS_ERR_ARG, "max_inner must be in [1, 128]");
+    const int M = std::max((int)max_inner, h->kry_M);
+    if (M == h->kry_M && h->kry_inner >= h->inner_cap && h->kry_rhs >= h->rhs_cap &&
+        h->kry_tiles >= h->tiles_cap)
+        return MS_OK;
+    const size_t R = (size_t)h->rhs_cap;
+    const size_t sizes[3] = {
+        sizeof(double) * (size_t)(M + 1) * (size_t)h->inner_cap * R,
+        sizeof(double) * (size_t)h->tiles_cap * R * (size_t)(M + 2),
+        sizeof(double) * (size_t)h->nblocks * R * (size_t)ms::gm_record_doubles(M)};
+    void *fresh[3] = {};
+    for (int i = 0; i < 3; i++) {
+        const hipError_t e = hipMalloc(&fresh[i], sizes[i]);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            for (int j = 0; j < i; j++) (void)hipFree(fresh[j]);
+            return fail(h, e == hipErrorOutOfMemory ? MS_ERR_NOMEM : MS_ERR_HIP,
+                        std::string("ms_reserve_krylov: ") + hipGetErrorString(e));
+        }
+    }
+    drop_graph(h);
+    if (h->V) (void)hipFree(h->V);
+    if (h->gpart) (void)hipFree(h->gpart);
+    if (h->gm) (void)hipFree(h->gm);
+    h->V = fresh[0];
+    h->gpart = (double *)fresh[1];
+    h->gm = (double *)fresh[2];
+    h->kry_M = M;
+    h->kry_inner = h->inner_cap;
+    h->kry_rhs = h->rhs_cap;
+    h->kry_tiles = h->tiles_cap;
     return MS_OK;
 }
 

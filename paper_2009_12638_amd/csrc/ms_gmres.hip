@@ -1,0 +1,480 @@
+// GMRES inner solves of the synchronous multisplitting sweep (Sections 3.1
+// and 4: the experiments' inner Krylov solver was GMRES; Section 3.2: a
+// maximum number of inner iterations).  One GMRES(m) cycle per block and
+// sweep, from a zero correction on the block's residual (or its overlap
+// region's).
+//
+// Krylov vectors are stored unscaled: u_0 = r, u_{j+1} = A v_j minus its
+// projections, with v_i = u_i / s_i and s_i = ||u_i|| kept per block, so
+// no pass is spent normalising.  One Arnoldi step j is four launches:
+//   k_gm_apply  w = A v_j on every tile (7-point stencil, zero outside the
+//               block's box, masked outside an overlap region), stored as
+//               u_{j+1}; per-tile partials of (w, u_i), i <= j, from the w
+//               values still in registers;
+//   k_gm_coef   per block: h_ij = (w, u_i) / s_i in a fixed tile order;
+//   k_gm_orth   u_{j+1} = w - sum_i (h_ij / s_i) u_i (classical
+//               Gram-Schmidt: all coefficients from the same w), per-tile
+//               partials of its squared norm;
+//   k_gm_norm   per block: h_{j+1,j} = s_{j+1}; the Givens rotations of
+//               the Hessenberg column and the least-squares residual.
+// After m steps (or an early stop) k_gm_solve back-substitutes y per block
+// and k_gm_final writes x_new = x_old + sum_i (y_i / s_i) u_i on the
+// block's own cells.  The Hessenberg arithmetic is FP64; vectors and tile
+// partials are in the inner type T (FP32 in mixed precision).
+#include "ms_internal.h"
+#include "ms_device.h"
+
+#include <math.h>
+
+namespace ms {
+
+namespace {
+
+// x planes one workgroup marches (the tile's w values stay in registers)
+constexpr int kGmPlanes = 8;
+
+// Fields of one (right-hand side, block) GMRES record, in doubles.
+struct GmRec {
+    int M;
+    __device__ int s() const { return 0; }                  // M+1 scales s_i
+    __device__ int coef() const { return M + 1; }           // M+1 coefficients h_ij / s_i
+    __device__ int g() const { return 2 * (M + 1); }        // M+1 rotated right-hand side
+    __device__ int y() const { return 3 * (M + 1); }        // M   solution coefficients / s_i
+    __device__ int cs() const { return 4 * M + 3; }         // M   rotation cosines
+    __device__ int sn() const { return 5 * M + 3; }         // M   rotation sines
+    __device__ int R() const { return 6 * M + 3; }          // (M+1) x M, row i at i*M
+    __device__ int beta() const { return 6 * M + 3 + (M + 1) * M; }
+    __device__ int steps() const { return beta() + 1; }
+    __device__ int active() const { return beta() + 2; }
+};
+
+__device__ __forceinline__ double *rec(double *gm, const GmArgs &a, int k, int b) {
+    return gm + ((long long)k * a.nblocks + b) * a.rec_stride;
+}
+
+// The whole block's tile partials of slot `slot`, in tile order (FP64).
+template <typename T>
+__device__ __forceinline__ double block_sum(const T *part, long long stride, int slot,
+                                            int tile0, int ntiles) {
+    double s = 0.0;
+    for (int t = 0; t < ntiles; t++) s += (double)part[(long long)(tile0 + t) * stride + slot];
+    return s;
+}
+
+// w = A_box u (zero outside the box; overlap: zero outside the region)
+// times inv_s, on one tile of one-row threads; w kept in wv and stored.
+template <typename T, int VZ, bool OVL>
+__device__ __forceinline__ void tile_gm_apply(const Tile &t, long long goff,
+                                              const T *__restrict__ u, T *__restrict__ w,
+                                              T inv_s, T (&wv)[kGmPlanes][VZ]) {
+    const int bz = t.B.bz, by = t.B.by, bx = t.B.bx;
+    const long long P = (long long)by * bz;
+    const long long base = (t.B.off - goff) + (long long)t.j0 * bz + t.k;
+    const bool live = t.nrows > 0;
+    const bool zm_in = t.zc > 0, zp_in = t.zc < t.tpr - 1;
+    const bool zm_sh = zm_in && t.lane > 0, zp_sh = zp_in && t.lane < 63;
+    const bool ym_ld = live && t.j0 > 0;
+    const bool yp_ld = live && t.j0 + 1 < by;
+    const bool ym_sh = t.lane >= t.tpr, yp_sh = t.lane + t.tpr < 64;
+    T pm[VZ], pc[VZ], pp[VZ];
+#pragma unroll
+    for (int v = 0; v < VZ; v++) { pm[v] = T(0); pc[v] = T(0); pp[v] = T(0); }
+    if (live) {
+        if (t.xbeg > 0) vload<T, VZ>(u + base + (long long)(t.xbeg - 1) * P, pm);
+        vload<T, VZ>(u + base + (long long)t.xbeg * P, pc);
+    }
+#pragma unroll
+    for (int q = 0; q < kGmPlanes; q++) {
+#pragma unroll
+        for (int v = 0; v < VZ; v++) wv[q][v] = T(0);
+        const int i = t.xbeg + q;
+        if (i >= t.xend) continue;   // uniform over the workgroup
+        const long long o = base + (long long)i * P;
+        T ym[VZ], yp[VZ], ysu[VZ], ysd[VZ];
+#pragma unroll
+        for (int v = 0; v < VZ; v++) {
+            ym[v] = T(0);
+            yp[v] = T(0);
+            ysu[v] = __shfl_up(pc[v], t.tpr, 64);
+            ysd[v] = __shfl_down(pc[v], t.tpr, 64);
+        }
+        if (live && i + 1 < bx) vload<T, VZ>(u + o + P, pp);
+        if (ym_ld) {
+            if (ym_sh) {
+#pragma unroll
+                for (int v = 0; v < VZ; v++) ym[v] = ysu[v];
+            } else {
+                vload<T, VZ>(u + o - bz, ym);
+            }
+        }
+        if (yp_ld) {
+            if (yp_sh) {
+#pragma unroll
+                for (int v = 0; v < VZ; v++) yp[v] = ysd[v];
+            } else {
+                vload<T, VZ>(u + o + bz, yp);
+            }
+        }
+        const T sl = from_left(pc[VZ - 1]);
+        const T sr = from_right(pc[0]);
+        if (live) {
+            T zm = T(0), zp = T(0);
+            if (zm_in) zm = zm_sh ? sl : u[o - 1];
+            if (zp_in) zp = zp_sh ? sr : u[o + VZ];
+#pragma unroll
+            for (int v = 0; v < VZ; v++) {
+                const T left = v == 0 ? zm : pc[v - 1];
+                const T right = v == VZ - 1 ? zp : pc[v + 1];
+                T qv = (T(6) * pc[v] - pm[v] - pp[v] - ym[v] - yp[v] - left - right) * inv_s;
+                if (OVL && axes_out(t.B, i, t.j0, t.k + v) > 1) qv = T(0);
+                wv[q][v] = qv;
+            }
+            vstore<T, VZ>(w + o, wv[q]);
+        }
+#pragma unroll
+        for (int v = 0; v < VZ; v++) { pm[v] = pc[v]; pc[v] = pp[v]; pp[v] = T(0); }
+    }
+}
+
+}  // namespace
+
+// Start of a block's GMRES cycle: beta = ||r|| from the residual kernel's
+// region partials; one thread per (right-hand side, block of the group).
+template <typename T>
+__global__ void k_gm_init(const BlockInfo *blocks, int b0, int nb, const T *pT, Batch bt,
+                          GmArgs a, Ctrl *ctrl) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nb * bt.nrhs) return;
+    const int k = q / nb, b = b0 + q % nb;
+    if (ctrl[k].done) return;
+    const BlockInfo &B = blocks[b];
+    const GmRec R{a.M};
+    double *st = rec(a.gm, a, k, b);
+    const double beta = sqrt(block_sum(pT + (long long)k * bt.ps, 1, 0, B.tile0, B.ntiles));
+    st[R.s()] = beta;
+    st[R.g()] = beta;
+    st[R.beta()] = beta;
+    st[R.steps()] = 0.0;
+    st[R.active()] = beta > 0.0 ? 1.0 : 0.0;   // a zero residual has nothing to solve
+}
+
+// Arnoldi step j, part 1: u_{j+1} = A v_j and partials of (u_{j+1}, u_i).
+template <typename T, int VZ, bool OVL>
+__global__ __launch_bounds__(kThreads) void k_gm_apply(Geom g, int t0, long long goff, T *V,
+                                                       int j, Batch bt, GmArgs a, Ctrl *ctrl) {
+    const int w = xcd_tile(blockIdx.x, gridDim.x);
+    const int k = w / bt.nt;
+    if (ctrl[k].done) return;
+    const int tile = t0 + (w - k * bt.nt);
+    const Tile t = decode_tile<VZ, 1>(g, tile, threadIdx.x);
+    const GmRec R{a.M};
+    const double *st = rec(a.gm, a, k, t.b);
+    if (st[R.active()] == 0.0) return;   // uniform over the workgroup
+    const long long ko = (long long)k * bt.is;
+    const T *uj = V + (long long)j * a.kvs + ko;
+    T *un = V + (long long)(j + 1) * a.kvs + ko;
+    T wv[kGmPlanes][VZ];
+    tile_gm_apply<T, VZ, OVL>(t, goff, uj, un, T(1.0 / st[R.s() + j]), wv);
+    double *part = a.gpart + ((long long)k * bt.ps + tile) * a.gstride;
+    const int bz = t.B.bz;
+    const long long P = (long long)t.B.by * bz;
+    const long long base = (t.B.off - goff) + (long long)t.j0 * bz + t.k;
+    for (int i = 0; i <= j; i++) {
+        const T *ui = V + (long long)i * a.kvs + ko;
+        T acc = T(0);
+        if (t.nrows > 0) {
+#pragma unroll
+            for (int q = 0; q < kGmPlanes; q++) {
+                if (t.xbeg + q >= t.xend) continue;
+                T uv[VZ];
+                vload<T, VZ>(ui + base + (long long)(t.xbeg + q) * P, uv);
+#pragma unroll
+                for (int v = 0; v < VZ; v++) acc += wv[q][v] * uv[v];
+            }
+        }
+        const T s = wg_allsum<T, kThreads>(acc);
+        if (threadIdx.x == 0) part[i] = (double)s;
+    }
+}
+
+// Arnoldi step j, part 2 (per block): h_ij = (w, u_i) / s_i, i <= j.
+template <typename T>
+__global__ void k_gm_coef(const BlockInfo *blocks, int b0, int nb, int j, Batch bt, GmArgs a,
+                          Ctrl *ctrl) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nb * bt.nrhs) return;
+    const int k = q / nb, b = b0 + q % nb;
+    if (ctrl[k].done) return;
+    const GmRec R{a.M};
+    double *st = rec(a.gm, a, k, b);
+    if (st[R.active()] == 0.0) return;
+    const BlockInfo &B = blocks[b];
+    const double *part = a.gpart + (long long)k * bt.ps * a.gstride;
+    for (int i = 0; i <= j; i++) {
+        const double h = block_sum(part, a.gstride, i, B.tile0, B.ntiles) / st[R.s() + i];
+        st[R.R() + i * a.M + j] = h;
+        st[R.coef() + i] = h / st[R.s() + i];
+    }
+}
+
+// Arnoldi step j, part 3: u_{j+1} = w - sum_i (h_ij / s_i) u_i and
+// partials of its squared norm.
+template <typename T, int VZ>
+__global__ __launch_bounds__(kThreads) void k_gm_orth(Geom g, int t0, long long goff, T *V, int j,
+                                                      Batch bt, GmArgs a, Ctrl *ctrl) {
+    const int w = xcd_tile(blockIdx.x, gridDim.x);
+    const int k = w / bt.nt;
+    if (ctrl[k].done) return;
+    const int tile = t0 + (w - k * bt.nt);
+    const Tile t = decode_tile<VZ, 1>(g, tile, threadIdx.x);
+    const GmRec R{a.M};
+    const double *st = rec(a.gm, a, k, t.b);
+    if (st[R.active()] == 0.0) return;
+    const long long ko = (long long)k * bt.is;
+    T *un = V + (long long)(j + 1) * a.kvs + ko;
+    const int bz = t.B.bz;
+    const long long P = (long long)t.B.by * bz;
+    const long long base = (t.B.off - goff) + (long long)t.j0 * bz + t.k;
+    T wv[kGmPlanes][VZ];
+    const bool live = t.nrows > 0;
+#pragma unroll
+    for (int q = 0; q < kGmPlanes; q++) {
+#pragma unroll
+        for (int v = 0; v < VZ; v++) wv[q][v] = T(0);
+        if (live && t.xbeg + q < t.xend) vload<T, VZ>(un + base + (long long)(t.xbeg + q) * P, wv[q]);
+    }
+    for (int i = 0; i <= j; i++) {
+        const T c = (T)st[R.coef() + i];
+        const T *ui = V + (long long)i * a.kvs + ko;
+        if (!live) continue;
+#pragma unroll
+        for (int q = 0; q < kGmPlanes; q++) {
+            if (t.xbeg + q >= t.xend) continue;
+            T uv[VZ];
+            vload<T, VZ>(ui + base + (long long)(t.xbeg + q) * P, uv);
+#pragma unroll
+            for (int v = 0; v < VZ; v++) wv[q][v] = wv[q][v] - c * uv[v];
+        }
+    }
+    T acc = T(0);
+    if (live) {
+#pragma unroll
+        for (int q = 0; q < kGmPlanes; q++) {
+            if (t.xbeg + q >= t.xend) continue;
+            vstore<T, VZ>(un + base + (long long)(t.xbeg + q) * P, wv[q]);
+#pragma unroll
+            for (int v = 0; v < VZ; v++) acc += wv[q][v] * wv[q][v];
+        }
+    }
+    const T s = wg_allsum<T, kThreads>(acc);
+    if (threadIdx.x == 0) a.gpart[((long long)k * bt.ps + tile) * a.gstride + a.M + 1] = (double)s;
+}
+
+// Arnoldi step j, part 4 (per block): h_{j+1,j} = ||u_{j+1}||, Givens
+// rotations of column j, least-squares residual and the stopping rules
+// (m steps, inner_tol, an invariant Krylov space).
+__global__ void k_gm_norm(const BlockInfo *blocks, int b0, int nb, int j, double inner_tol,
+                          Batch bt, GmArgs a, Ctrl *ctrl) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nb * bt.nrhs) return;
+    const int k = q / nb, b = b0 + q % nb;
+    if (ctrl[k].done) return;
+    const GmRec R{a.M};
+    double *st = rec(a.gm, a, k, b);
+    if (st[R.active()] == 0.0) return;
+    const BlockInfo &B = blocks[b];
+    const int M = a.M;
+    const double *part = a.gpart + (long long)k * bt.ps * a.gstride;
+    const double hn = sqrt(block_sum(part, a.gstride, M + 1, B.tile0, B.ntiles));
+    double *H = st + R.R();
+    for (int i = 0; i < j; i++) {
+        const double x0 = H[i * M + j], x1 = H[(i + 1) * M + j];
+        const double c = st[R.cs() + i], s = st[R.sn() + i];
+        H[i * M + j] = c * x0 + s * x1;
+        H[(i + 1) * M + j] = -s * x0 + c * x1;
+    }
+    const double d = H[j * M + j];
+    const double den = sqrt(d * d + hn * hn);
+    if (!(den > 0.0)) {          // nothing left to reduce
+        st[R.active()] = 0.0;
+        return;
+    }
+    const double c = d / den, s = hn / den;
+    st[R.cs() + j] = c;
+    st[R.sn() + j] = s;
+    H[j * M + j] = den;
+    const double gj = st[R.g() + j];
+    st[R.g() + j + 1] = -s * gj;
+    st[R.g() + j] = c * gj;
+    st[R.steps()] = (double)(j + 1);
+    atomicAdd(&ctrl[k].inner_iters, 1ull);
+    if (!(hn > 0.0)) {
+        st[R.active()] = 0.0;   // invariant Krylov space: the block is solved
+        return;
+    }
+    st[R.s() + j + 1] = hn;
+    if (inner_tol > 0.0 && fabs(st[R.g() + j + 1]) <= inner_tol * st[R.beta()])
+        st[R.active()] = 0.0;
+}
+
+// End of the cycle (per block): y from the triangular system, stored as
+// y_i / s_i, the coefficient of u_i in the correction.
+__global__ void k_gm_solve(int b0, int nb, Batch bt, GmArgs a, Ctrl *ctrl) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nb * bt.nrhs) return;
+    const int k = q / nb, b = b0 + q % nb;
+    if (ctrl[k].done) return;
+    const GmRec R{a.M};
+    double *st = rec(a.gm, a, k, b);
+    const int n = (int)st[R.steps()];
+    const int M = a.M;
+    const double *H = st + R.R();
+    double *y = st + R.y();
+    for (int i = n - 1; i >= 0; i--) {
+        double s = st[R.g() + i];
+        for (int l = i + 1; l < n; l++) s -= H[i * M + l] * y[l];
+        y[i] = s / H[i * M + i];
+    }
+    for (int i = 0; i < n; i++) y[i] /= st[R.s() + i];
+}
+
+// x_new = x_old + sum_i (y_i / s_i) u_i on the block's own cells (every own
+// cell is written, also for blocks that took no step).
+template <typename T, int VZ, bool OVL>
+__global__ __launch_bounds__(kThreads) void k_gm_final(Geom g, int t0, long long goff,
+                                                       const T *V, const double *xa, double *xb,
+                                                       Batch bt, GmArgs a, Ctrl *ctrl) {
+    const int w = xcd_tile(blockIdx.x, gridDim.x);
+    const int k = w / bt.nt;
+    if (ctrl[k].done) return;
+    const int tile = t0 + (w - k * bt.nt);
+    const Tile t = decode_tile<VZ, 1>(g, tile, threadIdx.x);
+    if (t.nrows == 0) return;
+    const GmRec R{a.M};
+    const double *st = rec(a.gm, a, k, t.b);
+    const int n = (int)st[R.steps()];
+    xa += k * bt.vs;
+    xb += k * bt.vs;
+    const long long ko = (long long)k * bt.is;
+    const int bz = t.B.bz;
+    const long long P = (long long)t.B.by * bz;
+    const long long base = (t.B.off - goff) + (long long)t.j0 * bz + t.k;
+    const long long J = t.B.j0 + t.j0, K = t.B.k0 + t.k;
+    for (int i = t.xbeg; i < t.xend; i++) {
+        if (OVL && axes_out(t.B, i, t.j0, t.k) != 0) continue;
+        const long long gI = ((long long)(t.B.i0 + i) * g.ny + J) * g.nz + K;
+        const long long o = base + (long long)i * P;
+        double xv[VZ];
+        vload<double, VZ>(xa + gI, xv);
+        for (int l = 0; l < n; l++) {
+            const double c = st[R.y() + l];
+            T uv[VZ];
+            vload<T, VZ>(V + (long long)l * a.kvs + ko + o, uv);
+#pragma unroll
+            for (int v = 0; v < VZ; v++) xv[v] += c * (double)uv[v];
+        }
+        vstore<double, VZ>(xb + gI, xv);
+    }
+}
+
+// ----------------------------------------------------------------------
+// launchers
+// ----------------------------------------------------------------------
+
+#define GM_CASE(vz_, ...)                     \
+    case vz_: {                               \
+        constexpr int VZ = vz_;               \
+        __VA_ARGS__;                          \
+        break;                                \
+    }
+#define GM_DISPATCH(vz, ...)                                                        \
+    switch (vz) {                                                                   \
+        GM_CASE(1, __VA_ARGS__) GM_CASE(2, __VA_ARGS__) GM_CASE(4, __VA_ARGS__)     \
+        default: return hipErrorInvalidValue;                                       \
+    }
+
+static inline dim3 small_grid(int nb, int nrhs) {
+    return dim3((unsigned)((nb * nrhs + 63) / 64));
+}
+
+static inline dim3 gm_batch_grid(int t0, int t1, Batch &bt) {
+    bt.nt = t1 - t0;
+    return dim3((unsigned)((long long)bt.nt * bt.nrhs));
+}
+
+template <typename T>
+hipError_t launch_gm_init(const Geom &g, int b0, int b1, const T *pT, Batch bt, GmArgs a,
+                          Ctrl *ctrl, hipStream_t st) {
+    if (b1 <= b0) return hipSuccess;
+    hipLaunchKernelGGL(k_gm_init<T>, small_grid(b1 - b0, bt.nrhs), dim3(64), 0, st, g.blocks,
+                       b0, b1 - b0, pT, bt, a, ctrl);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gm_step(const Geom &g, int vz, int t0, int t1, int b0, int b1, long long goff,
+                          T *V, int j, double inner_tol, Batch bt, GmArgs a, Ctrl *ctrl,
+                          hipStream_t st, int part) {
+    if (t1 <= t0) return hipSuccess;
+    if (g.rows != 1 || g.tx > kGmPlanes) return hipErrorInvalidValue;
+    if (part == 0) {
+        const dim3 grid = gm_batch_grid(t0, t1, bt);
+        if (g.ovl) {
+            GM_DISPATCH(vz, hipLaunchKernelGGL((k_gm_apply<T, VZ, true>), grid, dim3(kThreads),
+                                               0, st, g, t0, goff, V, j, bt, a, ctrl));
+        } else {
+            GM_DISPATCH(vz, hipLaunchKernelGGL((k_gm_apply<T, VZ, false>), grid, dim3(kThreads),
+                                               0, st, g, t0, goff, V, j, bt, a, ctrl));
+        }
+    } else if (part == 1) {
+        hipLaunchKernelGGL(k_gm_coef<T>, small_grid(b1 - b0, bt.nrhs), dim3(64), 0, st, g.blocks,
+                           b0, b1 - b0, j, bt, a, ctrl);
+    } else if (part == 2) {
+        const dim3 grid = gm_batch_grid(t0, t1, bt);
+        GM_DISPATCH(vz, hipLaunchKernelGGL((k_gm_orth<T, VZ>), grid, dim3(kThreads), 0, st, g,
+                                           t0, goff, V, j, bt, a, ctrl));
+    } else {
+        hipLaunchKernelGGL(k_gm_norm, small_grid(b1 - b0, bt.nrhs), dim3(64), 0, st, g.blocks, b0,
+                           b1 - b0, j, inner_tol, bt, a, ctrl);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gm_finish(const Geom &g, int vz, int t0, int t1, int b0, int b1,
+                            long long goff, const T *V, const double *xa, double *xb, Batch bt,
+                            GmArgs a, Ctrl *ctrl, hipStream_t st, int part) {
+    if (t1 <= t0) return hipSuccess;
+    if (g.rows != 1 || g.tx > kGmPlanes) return hipErrorInvalidValue;
+    if (part == 0) {
+        hipLaunchKernelGGL(k_gm_solve, small_grid(b1 - b0, bt.nrhs), dim3(64), 0, st, b0,
+                           b1 - b0, bt, a, ctrl);
+    } else {
+        const dim3 grid = gm_batch_grid(t0, t1, bt);
+        if (g.ovl) {
+            GM_DISPATCH(vz, hipLaunchKernelGGL((k_gm_final<T, VZ, true>), grid, dim3(kThreads),
+                                               0, st, g, t0, goff, V, xa, xb, bt, a, ctrl));
+        } else {
+            GM_DISPATCH(vz, hipLaunchKernelGGL((k_gm_final<T, VZ, false>), grid, dim3(kThreads),
+                                               0, st, g, t0, goff, V, xa, xb, bt, a, ctrl));
+        }
+    }
+    return hipGetLastError();
+}
+
+int gm_record_doubles(int M) { return 6 * M + 3 + (M + 1) * M + 4; }
+int gm_max_planes() { return kGmPlanes; }
+
+#define GM_INST(T)                                                                            \
+    template hipError_t launch_gm_init<T>(const Geom &, int, int, const T *, Batch, GmArgs,   \
+                                          Ctrl *, hipStream_t);                               \
+    template hipError_t launch_gm_step<T>(const Geom &, int, int, int, int, int, long long,   \
+                                          T *, int, double, Batch, GmArgs, Ctrl *,            \
+                                          hipStream_t, int);                                  \
+    template hipError_t launch_gm_finish<T>(const Geom &, int, int, int, int, int, long long, \
+                                            const T *, const double *, double *, Batch,      \
+                                            GmArgs, Ctrl *, hipStream_t, int);
+GM_INST(double)
+GM_INST(float)
+
+}  // namespace ms

@@ -10,6 +10,11 @@ constexpr int kThreads = 256;       // threads per workgroup in the tiled kernel
 constexpr int kAsyncThreads = 512;  // threads per persistent asynchronous worker
 
 // One block of the partition (Section 3: the unknowns X_i of one block).
+// The box [i0, i0+bx) x [j0, j0+by) x [k0, k0+bz) is the block's inner-solve
+// domain: the block itself, or with overlap the bounding box of its region
+// (the block plus slabs of depth o across faces that have a neighbour).
+// The block's own cells are the sub-box at offset (oi, oj, ok) of extents
+// (obx, oby, obz); without overlap that is the whole box.
 struct BlockInfo {
     int i0, j0, k0;   // origin in the global interior grid
     int bx, by, bz;   // extents
@@ -17,6 +22,8 @@ struct BlockInfo {
     int tile0;        // first tile (workgroup) number of this block
     int ntiles;       // tiles of this block = nplane * nxchunk
     int nplane;       // tiles across one y-z plane
+    int oi, oj, ok;   // own cells: offset inside the box
+    int obx, oby, obz;  // own cells: extents
     int pad_;
 };
 
@@ -46,6 +53,7 @@ struct Geom {
     int tx;                  // x planes per tile
     int rows;                // rows (y) per thread: 1, 2 or 4
     int nblocks;
+    int ovl;                 // 1: blocks are overlap regions (mask edges, write own cells)
 };
 
 struct Faces {
@@ -58,12 +66,27 @@ struct Faces {
 struct Batch {
     int nt;          // tiles per right-hand side in this launch (set by the launcher)
     int nrhs;        // right-hand sides
-    long long vs;    // element stride between right-hand sides' vectors
+    long long vs;    // element stride between right-hand sides' vectors (b, x)
     long long ps;    // stride of per-tile partial arrays
     long long bs;    // stride of per-block arrays
+    long long is;    // element stride between right-hand sides' inner vectors
 };
 
-inline Batch single_rhs() { return Batch{0, 1, 0, 0, 0}; }
+inline Batch single_rhs() { return Batch{0, 1, 0, 0, 0, 0}; }
+
+// GMRES inner solves: per (right-hand side, block) records of the
+// Hessenberg/Givens state (doubles), per (right-hand side, tile) partial
+// sums, and the Krylov vectors (vector i of right-hand side k starts at
+// V + i * kvs + k * Batch::is).
+struct GmArgs {
+    double *gm;          // records, rec_stride doubles each
+    double *gpart;       // tile partials, gstride slots each
+    long long kvs;       // elements between consecutive Krylov vectors
+    int M;               // inner iterations the records are laid out for
+    int gstride;         // M + 2: dots with u_0..u_M, then the norm slot
+    int nblocks;
+    int rec_stride;
+};
 
 // Shared state of an asynchronous solve (one entry per block).
 struct AsyncState {
@@ -139,5 +162,26 @@ hipError_t launch_apply(long long nx, long long ny, long long nz, const double *
 
 // Fixed-order sum of n doubles into *out (device).
 hipError_t launch_sum(const double *v, int n, double *out, hipStream_t st);
+
+// ---- GMRES inner solves (ms_gmres.hip) ----------------------------------
+// Tiles must be one row per thread and at most gm_max_planes() x planes.
+// init: beta = ||r|| per block of [b0, b1) from the residual's region
+// partials pT.  step part 0..3 of Arnoldi step j: apply + dots, per-block
+// coefficients, orthogonalisation + norm partials, per-block norm and
+// Givens rotation.  finish part 0: per-block triangular solve; part 1:
+// x_new = x_old + correction on own cells.
+template <typename T>
+hipError_t launch_gm_init(const Geom &g, int b0, int b1, const T *pT, Batch bt, GmArgs a,
+                          Ctrl *ctrl, hipStream_t st);
+template <typename T>
+hipError_t launch_gm_step(const Geom &g, int vz, int t0, int t1, int b0, int b1, long long goff,
+                          T *V, int j, double inner_tol, Batch bt, GmArgs a, Ctrl *ctrl,
+                          hipStream_t st, int part);
+template <typename T>
+hipError_t launch_gm_finish(const Geom &g, int vz, int t0, int t1, int b0, int b1,
+                            long long goff, const T *V, const double *xa, double *xb, Batch bt,
+                            GmArgs a, Ctrl *ctrl, hipStream_t st, int part);
+int gm_record_doubles(int M);
+int gm_max_planes();
 
 }  // namespace ms

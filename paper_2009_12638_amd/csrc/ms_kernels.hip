@@ -17,138 +17,11 @@
 // block's tile slots in tile order, so every reduction has a fixed order and
 // synchronous results are bitwise reproducible run to run.
 #include "ms_internal.h"
+#include "ms_device.h"
 
 #include <math.h>
 
 namespace ms {
-
-// ----------------------------------------------------------------------
-// small helpers
-// ----------------------------------------------------------------------
-
-template <typename T, int N>
-struct alignas(sizeof(T) * N) VecT {
-    T v[N];
-};
-
-// N consecutive values starting at p (p aligned to sizeof(T)*N).
-template <typename T, int N>
-__device__ __forceinline__ void vload(const T *__restrict__ p, T (&o)[N]) {
-    constexpr int C = (sizeof(T) * N <= 16) ? N : (int)(16 / sizeof(T));
-#pragma unroll
-    for (int c = 0; c < N; c += C) {
-        VecT<T, C> t = *reinterpret_cast<const VecT<T, C> *>(p + c);
-#pragma unroll
-        for (int v = 0; v < C; v++) o[c + v] = t.v[v];
-    }
-}
-
-template <typename T, int N>
-__device__ __forceinline__ void vstore(T *__restrict__ p, const T (&o)[N]) {
-    constexpr int C = (sizeof(T) * N <= 16) ? N : (int)(16 / sizeof(T));
-#pragma unroll
-    for (int c = 0; c < N; c += C) {
-        VecT<T, C> t;
-#pragma unroll
-        for (int v = 0; v < C; v++) t.v[v] = o[c + v];
-        *reinterpret_cast<VecT<T, C> *>(p + c) = t;
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// Sum over the NT threads of the workgroup, returned to every thread.
-// Fixed shape: lanes by butterfly, then the wavefront sums in order.
-template <typename T, int NT>
-__device__ __forceinline__ T wg_allsum(T v) {
-    __shared__ T sh[NT / 64 + 1];
-    v = wave_sum(v);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        T s = T(0);
-#pragma unroll
-        for (int w = 0; w < NT / 64; w++) s += sh[w];
-        sh[NT / 64] = s;
-    }
-    __syncthreads();
-    const T s = sh[NT / 64];
-    __syncthreads();   // sh may be reused by the next call
-    return s;
-}
-
-// Sum of a block's tile partials in tile order (every thread computes it).
-template <typename T>
-__device__ __forceinline__ T tiles_sum(const T *__restrict__ part, int t0, int n) {
-    T s = T(0);
-    for (int t = 0; t < n; t++) s += part[t0 + t];
-    return s;
-}
-
-// Thread geometry inside a tile.  A thread owns R consecutive rows (y) of
-// VZ consecutive z cells; tpr = bz / VZ threads cover one z row, so lanes
-// next to each other hold z neighbours and one wavefront covers whole rows
-// whenever tpr divides 64.  Row groups of R rows are numbered g, the
-// thread's slot in the block plane is q = g * tpr + zc.
-struct Tile {
-    int b;             // block number
-    BlockInfo B;
-    bool live;         // thread owns cells
-    int j0;            // first row of the thread's row group
-    int nrows;         // rows owned (R, fewer in a partial last group, 0 if idle)
-    int k;             // first z of the thread's cells
-    int zc, tpr;       // z chunk of the thread, chunks per row
-    int xbeg, xend;    // planes marched
-    bool first;        // first tile of its block
-    int lane;
-};
-
-// ltid: thread index inside the 256-thread tile.
-template <int VZ, int R>
-__device__ __forceinline__ Tile decode_tile(const Geom &g, int tile, int ltid) {
-    Tile t;
-    t.b = g.tile_block[tile];
-    t.B = g.blocks[t.b];
-    const int local = tile - t.B.tile0;
-    const int pt = local % t.B.nplane;
-    const int xc = local / t.B.nplane;
-    t.tpr = t.B.bz / VZ;
-    const int ng = (t.B.by + R - 1) / R;
-    const int q = pt * kThreads + ltid;
-    t.live = q < ng * t.tpr;
-    const int qq = t.live ? q : 0;
-    t.zc = qq % t.tpr;
-    t.j0 = (qq / t.tpr) * R;
-    t.k = t.zc * VZ;
-    t.nrows = t.live ? min(R, t.B.by - t.j0) : 0;
-    t.xbeg = xc * g.tx;
-    t.xend = min(t.B.bx, t.xbeg + g.tx);
-    t.first = (local == 0);
-    t.lane = ltid & 63;
-    return t;
-}
-
-template <typename T>
-__device__ __forceinline__ T from_left(T v) { return __shfl_up(v, 1, 64); }
-template <typename T>
-__device__ __forceinline__ T from_right(T v) { return __shfl_down(v, 1, 64); }
-
-// Workgroups of a launch are dispatched to the XCDs in turn (workgroup w to
-// XCD w % 8).  Hand each XCD one contiguous range of tiles instead, so the
-// tiles of a block and of its z and y neighbours share that XCD's L2 and
-// the halo rows and planes they exchange are L2 hits.  A bijection on
-// [0, n) for any n; correctness does not depend on the dispatch order.
-constexpr int kXcds = 8;
-__device__ __forceinline__ int xcd_tile(int w, int n) {
-    const int q = n / kXcds, rem = n % kXcds;
-    const int c = w % kXcds, k = w / kXcds;
-    return c * q + min(c, rem) + k;
-}
 
 // ----------------------------------------------------------------------
 // tile bodies
@@ -158,7 +31,9 @@ __device__ __forceinline__ int xcd_tile(int w, int n) {
 // B_i - sum_j A_ij X_j of a block, with neighbour-block values read straight
 // from x: the halo exchange of Listing 1).  x == nullptr means x = 0.
 // Adds r.r in FP64 to acc64 and in T to accT; stores r packed when STORE.
-template <typename T, int VZ, int R, bool STORE>
+// OVL (overlap regions): r is zero outside the region; acc64 counts the
+// block's own cells only (every cell of the grid once), accT the region.
+template <typename T, int VZ, int R, bool STORE, bool OVL = false>
 __device__ __forceinline__ void tile_resid(const Geom &g, const Tile &t, long long goff,
                                            const double *__restrict__ b, const double *x,
                                            const Faces &F, T *__restrict__ r, double &acc64,
@@ -267,8 +142,14 @@ __device__ __forceinline__ void tile_resid(const Geom &g, const Tile &t, long lo
                 const double up = rr == 0 ? ym[v] : xc[rr - 1][v];
                 const double down = (rr == R - 1 || rr + 1 == t.nrows) ? yp[v] : xc[rr + 1][v];
                 const double ax = 6.0 * xc[rr][v] - xm[rr][v] - xp[rr][v] - up - down - left - right;
-                const double rv = bb[v] - ax;
-                acc64 += rv * rv;
+                double rv = bb[v] - ax;
+                if (OVL) {
+                    const int n = axes_out(t.B, i, t.j0 + rr, t.k + v);
+                    if (n > 1) rv = 0.0;
+                    if (n == 0) acc64 += rv * rv;
+                } else {
+                    acc64 += rv * rv;
+                }
                 out[v] = (T)rv;
                 accT += out[v] * out[v];
             }
@@ -384,8 +265,9 @@ __device__ __forceinline__ T tile_stencil(const Tile &t, long long goff,
 }
 
 // Inner CG phase 2 on one tile: d += alpha p (d taken as 0 when !have_d);
-// r -= alpha A_ii p; returns the thread's part of r.r.
-template <typename T, typename TD, int VZ, int R>
+// r -= alpha A_ii p; returns the thread's part of r.r.  OVL: A_ii p is taken
+// as zero outside the region, so r (and d, p) stay zero there.
+template <typename T, typename TD, int VZ, int R, bool OVL = false>
 __device__ __forceinline__ T tile_update(const Tile &t, long long goff, T *__restrict__ r,
                                          const T *__restrict__ p, TD *__restrict__ d, T alpha,
                                          bool have_d) {
@@ -464,7 +346,8 @@ __device__ __forceinline__ T tile_update(const Tile &t, long long goff, T *__res
                 const T right = v == VZ - 1 ? zp : pc[rr][v + 1];
                 const T up = rr == 0 ? ym[v] : pc[rr - 1][v];
                 const T down = (rr == R - 1 || rr + 1 == t.nrows) ? yp[v] : pc[rr + 1][v];
-                const T q = T(6) * pc[rr][v] - pm[rr][v] - pp[rr][v] - up - down - left - right;
+                T q = T(6) * pc[rr][v] - pm[rr][v] - pp[rr][v] - up - down - left - right;
+                if (OVL && axes_out(t.B, i, t.j0 + rr, t.k + v) > 1) q = T(0);
                 dd[v] = dd[v] + alpha * pc[rr][v];
                 rv[v] = rv[v] - alpha * q;
                 acc += rv[v] * rv[v];
@@ -482,7 +365,11 @@ __device__ __forceinline__ T tile_update(const Tile &t, long long goff, T *__res
 
 // Outer update on one tile (Section 3: X_i^(k) = X_i^(k-1) + correction):
 // xb = xa + d (when have_d) + alpha p (when use_p), in FP64.  xb may equal xa.
-template <typename T, int VZ, int R>
+// OVL: only the block's own cells are written (each cell takes its owner's
+// correction: the multisplitting weights D_i of Section 2.3 are 0/1); the
+// vector width divides the own box's z offset and extent, so a z vector is
+// wholly own or wholly not.
+template <typename T, int VZ, int R, bool OVL = false>
 __device__ __forceinline__ void tile_final(const Geom &g, const Tile &t, long long goff,
                                            const T *p, const T *d, T alpha, bool have_d,
                                            bool use_p, const double *xa, double *xb) {
@@ -494,6 +381,7 @@ __device__ __forceinline__ void tile_final(const Geom &g, const Tile &t, long lo
 #pragma unroll
         for (int rr = 0; rr < R; rr++) {
             if (rr >= t.nrows) continue;
+            if (OVL && axes_out(t.B, i, t.j0 + rr, t.k) != 0) continue;
             const long long o = base + (long long)i * P + (long long)rr * bz;
             const long long gI = ((long long)(t.B.i0 + i) * g.ny + J0 + rr) * g.nz + K;
             double xo[VZ];
@@ -519,7 +407,7 @@ __device__ __forceinline__ void tile_final(const Geom &g, const Tile &t, long lo
 // synchronous phase kernels: one tile per workgroup
 // ----------------------------------------------------------------------
 
-template <typename T, int VZ, int R, bool STORE>
+template <typename T, int VZ, int R, bool STORE, bool OVL>
 __global__ __launch_bounds__(kThreads) void k_resid(Geom g, int t0, long long goff,
                                                     const double *__restrict__ b,
                                                     const double *__restrict__ x, Faces F,
@@ -533,15 +421,16 @@ __global__ __launch_bounds__(kThreads) void k_resid(Geom g, int t0, long long go
     const int tile = t0 + (w - k * bt.nt);
     if (b) b += k * bt.vs;
     if (x) x += k * bt.vs;
-    if (r) r += k * bt.vs;
+    if (r) r += k * bt.is;
     p64 += (long long)k * bt.ps;
     pT += (long long)k * bt.ps;
     const Tile t = decode_tile<VZ, R>(g, tile, threadIdx.x);
     double acc64 = 0.0;
     T accT = T(0);
-    tile_resid<T, VZ, R, STORE>(g, t, goff, b, x, F, r, acc64, accT);
+    tile_resid<T, VZ, R, STORE, OVL>(g, t, goff, b, x, F, r, acc64, accT);
     const double s64 = wg_allsum<double, kThreads>(acc64);
-    if (sizeof(T) == sizeof(double)) {
+    // FP64 without overlap: the region and own sums coincide (pT == p64)
+    if (sizeof(T) == sizeof(double) && !OVL) {
         if (threadIdx.x == 0) p64[tile] = s64;
     } else {
         const T sT = wg_allsum<T, kThreads>(accT);
@@ -563,9 +452,9 @@ __global__ __launch_bounds__(kThreads) void k_stencil(Geom g, int t0, long long 
     const int k = w / bt.nt;
     if (ctrl[k].done) return;
     const int tile = t0 + (w - k * bt.nt);
-    r += k * bt.vs;
-    pold += k * bt.vs;
-    pnew += k * bt.vs;
+    r += k * bt.is;
+    pold += k * bt.is;
+    pnew += k * bt.is;
     psig += (long long)k * bt.ps;
     prho_cur += (long long)k * bt.ps;
     prho_prev += (long long)k * bt.ps;
@@ -595,7 +484,7 @@ __global__ __launch_bounds__(kThreads) void k_stencil(Geom g, int t0, long long 
     if (threadIdx.x == 0) psig[tile] = s;
 }
 
-template <typename T, int VZ, int R, bool LAST>
+template <typename T, int VZ, int R, bool LAST, bool OVL>
 __global__ __launch_bounds__(kThreads) void k_update(Geom g, int t0, long long goff,
                                                      T *__restrict__ r,
                                                      const T *__restrict__ p,
@@ -611,9 +500,9 @@ __global__ __launch_bounds__(kThreads) void k_update(Geom g, int t0, long long g
     ctrl += k;
     if (ctrl->done) return;
     const int tile = t0 + (w - k * bt.nt);
-    r += k * bt.vs;
-    p += k * bt.vs;
-    d += k * bt.vs;
+    r += k * bt.is;
+    p += k * bt.is;
+    d += k * bt.is;
     psig += (long long)k * bt.ps;
     prho_cur += (long long)k * bt.ps;
     prho_next += (long long)k * bt.ps;
@@ -639,7 +528,7 @@ __global__ __launch_bounds__(kThreads) void k_update(Geom g, int t0, long long g
         // x_new = x_old + d + alpha p, for every block (inactive ones too);
         // x_new is a separate buffer, so every block's residual of this sweep
         // saw only x_old (Section 3: X_i^(k) from sweep k-1 values)
-        tile_final<T, VZ, R>(g, t, goff, p, d, alpha, iter > 0, act, xa, xb);
+        tile_final<T, VZ, R, OVL>(g, t, goff, p, d, alpha, iter > 0, act, xa, xb);
         return;
     }
     if (!act) {
@@ -658,7 +547,7 @@ __global__ __launch_bounds__(kThreads) void k_update(Geom g, int t0, long long g
         }
         return;
     }
-    const T acc = tile_update<T, T, VZ, R>(t, goff, r, p, d, alpha, iter > 0);
+    const T acc = tile_update<T, T, VZ, R, OVL>(t, goff, r, p, d, alpha, iter > 0);
     const T s = wg_allsum<T, kThreads>(acc);
     if (threadIdx.x == 0) prho_next[tile] = s;
 }
@@ -1031,15 +920,16 @@ hipError_t launch_resid(const Geom &g, int vz, int t0, int t1, long long goff,
                         T *pT, const Ctrl *ctrl, Batch bt, hipStream_t st) {
     if (t1 <= t0) return hipSuccess;
     const dim3 grid = batch_grid(t0, t1, bt);
+#define MS_RESID(STORE, OVL)                                                               \
+    MS_DISPATCH(vz, g.rows, hipLaunchKernelGGL((k_resid<T, VZ, RR, STORE, OVL>), grid,      \
+                                               dim3(kThreads), 0, st, g, t0, goff, b, x,   \
+                                               faces, r, p64, pT, ctrl, bt))
     if (r) {
-        MS_DISPATCH(vz, g.rows, hipLaunchKernelGGL((k_resid<T, VZ, RR, true>), grid,
-                                                   dim3(kThreads), 0, st, g, t0, goff, b, x,
-                                                   faces, r, p64, pT, ctrl, bt));
+        if (g.ovl) { MS_RESID(true, true); } else { MS_RESID(true, false); }
     } else {
-        MS_DISPATCH(vz, g.rows, hipLaunchKernelGGL((k_resid<T, VZ, RR, false>), grid,
-                                                   dim3(kThreads), 0, st, g, t0, goff, b, x,
-                                                   faces, r, p64, pT, ctrl, bt));
+        if (g.ovl) { MS_RESID(false, true); } else { MS_RESID(false, false); }
     }
+#undef MS_RESID
     return hipGetLastError();
 }
 
@@ -1064,17 +954,17 @@ hipError_t launch_update(const Geom &g, int vz, int t0, int t1, long long goff, 
                          Ctrl *ctrl, Batch bt, hipStream_t st) {
     if (t1 <= t0) return hipSuccess;
     const dim3 grid = batch_grid(t0, t1, bt);
+#define MS_UPDATE(LAST, OVL)                                                                \
+    MS_DISPATCH(vz, g.rows, hipLaunchKernelGGL((k_update<T, VZ, RR, LAST, OVL>), grid,       \
+                                               dim3(kThreads), 0, st, g, t0, goff, r, p, d, \
+                                               psig, prho_cur, prho_next, active, iter, xa, \
+                                               xb, ctrl, bt))
     if (last) {
-        MS_DISPATCH(vz, g.rows, hipLaunchKernelGGL((k_update<T, VZ, RR, true>), grid,
-                                                   dim3(kThreads), 0, st, g, t0, goff, r, p, d,
-                                                   psig, prho_cur, prho_next, active, iter, xa,
-                                                   xb, ctrl, bt));
+        if (g.ovl) { MS_UPDATE(true, true); } else { MS_UPDATE(true, false); }
     } else {
-        MS_DISPATCH(vz, g.rows, hipLaunchKernelGGL((k_update<T, VZ, RR, false>), grid,
-                                                   dim3(kThreads), 0, st, g, t0, goff, r, p, d,
-                                                   psig, prho_cur, prho_next, active, iter, xa,
-                                                   xb, ctrl, bt));
+        if (g.ovl) { MS_UPDATE(false, true); } else { MS_UPDATE(false, false); }
     }
+#undef MS_UPDATE
     return hipGetLastError();
 }
 

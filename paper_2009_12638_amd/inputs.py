@@ -173,6 +173,11 @@ def workload(name: str):
     uneven384   384x320x448 Poisson, per-axis block edges drawn from
                 {32, 48, 64, 96} (seeds 40, 41, 42), 16 right-hand sides
                 f_k ~ N(0,1) (seed 400+k), zero Dirichlet; b is [16, nx, ny, nz]
+    diff128     128^3, 4^3 blocks of 32^3: source f ~ N(0,1) (seed 50), faces
+                g ~ U(-1,1) (seed 51), target u_t = smooth_field (seed 52);
+                returns f (not h^2 f) under "f"; directions from diff_direction;
+                adjoint_tol 1e-11: the adjoint solution is ~360x its right-hand
+                side in norm, which puts its FP64 residual floor near 1e-12
     """
     if name == "laplace32":
         n = 32
@@ -194,4 +199,27 @@ def workload(name: str):
         for k in range(nrhs):
             b[k] = poisson_randn(shape, 400 + k)
         return dict(shape=shape, cuts=cuts, b=b, faces=[None] * 6, m=10, tol=1e-8)
+    if name == "diff128":
+        n = 128
+        rng = np.random.default_rng(50)
+        return dict(shape=(n, n, n), cuts=[uniform_cuts(n, 4)] * 3,
+                    f=rng.standard_normal((n, n, n)), faces=random_faces(n, n, n, 51),
+                    ut=smooth_field((n, n, n), 52), m=10, tol=1e-13, adjoint_tol=1e-11)
     raise KeyError(name)
+
+
+def diff_direction(shape, j: int):
+    """Seeded direction j (seed 53 + j) in (source, faces) space for
+    directional derivatives.  The source part is N(0,1) / h^2 per cell, so
+    that the change it makes to the right-hand side h^2 f is N(0,1) per cell,
+    like the face part (N(0,1) per face node).  Kinds by j mod 4: 0 and 2 both
+    parts, 1 source only, 3 faces only."""
+    rng = np.random.default_rng(53 + j)
+    h = spacing(shape[0])
+    df = rng.standard_normal(shape) / (h * h)
+    dg = [rng.standard_normal(s) for s in face_shapes(*shape)]
+    if j % 4 == 1:
+        dg = [np.zeros_like(a) for a in dg]
+    elif j % 4 == 3:
+        df = np.zeros_like(df)
+    return df, dg

@@ -19,7 +19,8 @@ MS_OK, MS_ERR_ARG, MS_ERR_HIP, MS_ERR_NOMEM = 0, 1, 2, 3
 MS_ERR_NOT_CONVERGED, MS_ERR_NONFINITE, MS_ERR_DIVERGED, MS_ERR_UNSUPPORTED = 4, 5, 6, 7
 MS_SYNC, MS_ASYNC = 0, 1
 MS_FP64, MS_MIXED = 0, 1
-KERNEL_CLASSES = ["resid", "stencil", "update", "final", "check", "other", "-", "-"]
+MS_INNER_CG, MS_INNER_GMRES = 0, 1
+KERNEL_CLASSES = ["resid", "stencil", "update", "final", "check", "other", "orth", "hess"]
 
 
 class MsError(RuntimeError):
@@ -49,7 +50,7 @@ class ms_opts(C.Structure):
                 ("stream", C.c_void_p), ("check_every", C.c_int32),
                 ("group_blocks", C.c_int32), ("x_chunk", C.c_int32),
                 ("profile", C.c_int32), ("use_graph", C.c_int32), ("rows", C.c_int32),
-                ("workers", C.c_int32)]
+                ("workers", C.c_int32), ("inner_solver", C.c_int32)]
 
 
 class ms_stats(C.Structure):
@@ -80,6 +81,10 @@ def lib() -> C.CDLL:
         L.ms_create.restype = C.c_int
         L.ms_set_bc.argtypes = [H, C.POINTER(ms_bc)]
         L.ms_set_bc.restype = C.c_int
+        L.ms_set_overlap.argtypes = [H, C.c_int32]
+        L.ms_set_overlap.restype = C.c_int
+        L.ms_reserve_krylov.argtypes = [H, C.c_int32]
+        L.ms_reserve_krylov.restype = C.c_int
         L.ms_solve.argtypes = [H, C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_int,
                                C.POINTER(ms_opts), C.POINTER(ms_stats)]
         L.ms_solve.restype = C.c_int
@@ -221,6 +226,17 @@ def ms_set_bc(h: Handle, faces) -> None:
     _check(h, lib().ms_set_bc(h.raw, C.byref(bc)))
 
 
+def ms_set_overlap(h: Handle, overlap: int) -> None:
+    """Overlap depth of the blocks' inner-solve regions (0: plain blocks)."""
+    _check(h, lib().ms_set_overlap(h.raw, int(overlap)))
+
+
+def ms_reserve_krylov(h: Handle, max_inner: int) -> None:
+    """Allocate the GMRES basis for inner_iters up to max_inner (call again
+    after ms_reserve / ms_set_overlap enlarge the handle)."""
+    _check(h, lib().ms_reserve_krylov(h.raw, int(max_inner)))
+
+
 @dataclass
 class Stats:
     status: int
@@ -237,7 +253,7 @@ class Stats:
 
 def _opts(precision="fp64", max_sweeps=100000, inner_tol=0.0, staleness=2, stream=None,
           check_every=0, group_blocks=0, x_chunk=0, profile=False, use_graph=True,
-          rows=0, workers=0) -> ms_opts:
+          rows=0, workers=0, inner="cg") -> ms_opts:
     o = ms_default_opts()
     o.max_sweeps = int(max_sweeps)
     o.inner_tol = float(inner_tol)
@@ -252,6 +268,8 @@ def _opts(precision="fp64", max_sweeps=100000, inner_tol=0.0, staleness=2, strea
     o.use_graph = 1 if use_graph else 0
     o.rows = int(rows)
     o.workers = int(workers)
+    o.inner_solver = {"cg": MS_INNER_CG, "gmres": MS_INNER_GMRES}[inner] \
+        if isinstance(inner, str) else int(inner)
     return o
 
 
@@ -260,8 +278,8 @@ def _stats_of(st: int, s: ms_stats, hist) -> Stats:
                  rel_residual=s.rel_residual, seconds=s.seconds,
                  max_staleness_seen=s.max_staleness_seen, relaunches=s.relaunches,
                  history=list(hist[: s.history_len]) if hist is not None else [],
-                 kernel_ms={KERNEL_CLASSES[i]: s.kernel_ms[i] for i in range(6)},
-                 kernel_launches={KERNEL_CLASSES[i]: s.kernel_launches[i] for i in range(6)})
+                 kernel_ms={KERNEL_CLASSES[i]: s.kernel_ms[i] for i in range(8)},
+                 kernel_launches={KERNEL_CLASSES[i]: s.kernel_launches[i] for i in range(8)})
 
 
 def ms_solve(h: Handle, b, x, tol: float, inner_iters: int, mode="sync", history=0,

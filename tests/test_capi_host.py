@@ -38,6 +38,8 @@ def test_struct_sizes_match_c_layout():
     assert C.sizeof(ms.ms_grid) == 24
     assert C.sizeof(ms.ms_blocks) == 12 + 4 + 24
     assert C.sizeof(ms.ms_bc) == 48
+    # max_sweeps, pad, inner_tol, staleness, precision, stream, five int32
+    # options, rows, workers, inner_solver
     assert C.sizeof(ms.ms_opts) == 4 + 4 + 8 + 4 + 4 + 8 + 4 * 5 + 4 + 4 + 4
     assert C.sizeof(ms.ms_stats) == 4 + 4 + 8 + 8 + 8 + 4 + 4 + 4 + 4 + 8 + 4 + 4 + 64 + 64
 
@@ -51,7 +53,7 @@ def test_status_strings(L):
 def test_default_opts(L):
     o = ms.ms_default_opts()
     assert o.max_sweeps == 100000 and o.staleness == 2 and o.precision == 0
-    assert o.use_graph == 1
+    assert o.use_graph == 1 and o.inner_solver == ms.MS_INNER_CG
 
 
 @pytest.mark.parametrize("shape,blocks,cuts,why", [

@@ -39,17 +39,22 @@ def sampled_blocks(g):
     return sorted(picks)
 
 
-@pytest.mark.parametrize("name,precision", [("poisson256", "fp64"), ("bumps512", "fp64"),
-                                            ("bumps512", "mixed")])
-def test_sampled_block_sweep(orc, name, precision):
+@pytest.mark.parametrize("name,precision,ov", [("poisson256", "fp64", 0), ("bumps512", "fp64", 0),
+                                               ("bumps512", "mixed", 0), ("bumps512", "fp64", 1),
+                                               ("bumps512", "mixed", 4)])
+def test_sampled_block_sweep(orc, name, precision, ov):
+    """ov > 0: overlapping blocks (regions of depth ov); the oracle's
+    per-block sweep then solves on each sampled block's region."""
     torch = torch_cuda()
     w = workload(name)
     shape, cuts = w["shape"], w["cuts"]
     g = len(cuts[0]) - 1
     h = ms.ms_create(shape, cuts=[list(map(int, c)) for c in cuts], faces=None)
+    if ov:
+        ms.ms_set_overlap(h, ov)
     b = dev(w["b"])
     x = torch.zeros(shape, dtype=torch.float64, device="cuda")
-    say("fullsize", name, precision, "2 sweeps")
+    say("fullsize", name, precision, "overlap", ov, "2 sweeps")
     ms.ms_solve(h, b, x, 0.0, w["m"], "sync", max_sweeps=2, precision=precision)
     x2 = host(x)
     say("fullsize", name, precision, "1 more sweep")
@@ -60,7 +65,10 @@ def test_sampled_block_sweep(orc, name, precision):
     torch.cuda.empty_cache()
     beff = orc.lift_bc(w["b"], [None] * 6)
     blocks = sampled_blocks(g)
-    xo = orc.block_sweep_some(beff, x2, cuts, blocks, m=w["m"])
+    if ov:
+        xo = orc.ovl_sweep_some(beff, x2, cuts, ov, blocks, m=w["m"])
+    else:
+        xo = orc.block_sweep_some(beff, x2, cuts, blocks, m=w["m"])
     cx, cy, cz = cuts
     worst = 0.0
     for blk in blocks:
@@ -75,7 +83,7 @@ def test_sampled_block_sweep(orc, name, precision):
     assert np.isfinite(x3).all()
     moved = np.abs(x3 - x2).reshape(g, shape[0] // g, g, shape[1] // g, g, shape[2] // g)
     assert (moved.max(axis=(1, 3, 5)) > 0).all()
-    print(f"{name} {precision}: worst block correction error {worst:.2e}")
+    print(f"{name} {precision} overlap {ov}: worst block correction error {worst:.2e}")
 
 
 def test_uneven384_batch_sampled_blocks(orc):

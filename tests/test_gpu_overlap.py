@@ -1,0 +1,194 @@
+"""GPU parity of overlapping blocks (Section 3.2: block overlap; Section 2.3:
+the multisplitting weights) through the C ABI against the CPU oracle.  Each
+block's inner solve runs on its region (the block plus face slabs of depth
+o); every cell takes its owner's correction.  FP64 iterates after the same
+number of sweeps match the oracle to 1e-10; mixed precision reaches the FP64
+answer within 1e-6."""
+import numpy as np
+import pytest
+
+from paper_2009_12638_amd import inputs, ms
+from gpu_util import dev, host, make, rel, say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-10     # same bar and reasoning as the non-overlapping path
+TOL_MIXED = 1e-6
+HIST_ATOL = 1e-12
+
+
+def _pair(orc, shape, cuts, b, faces, ov, m, K, precision="fp64", **kw):
+    torch = torch_cuda()
+    h, _ = make(ms, shape, cuts, faces)
+    ms.ms_set_overlap(h, ov)
+    x = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    say("overlap solve", shape, "o", ov, "m", m, "K", K, precision, kw)
+    st = ms.ms_solve(h, dev(b), x, 0.0, m, "sync", max_sweeps=K, precision=precision,
+                     history=K + 1, **kw)
+    beff = orc.lift_bc(b, faces)
+    ost, xo, sw, inner, hist = orc.block_jacobi_ovl(beff, np.zeros(shape), cuts, ov, tol=0.0,
+                                                    m=m, max_sweeps=K)
+    assert ost == 0 and sw == K
+    ms.ms_destroy(h)
+    return st, host(x), xo, hist, inner
+
+
+CASES = [
+    # shape, cuts, overlap, m, K
+    ((40, 36, 44), ([0, 14, 40], [0, 10, 36], [0, 20, 44]), 1, 7, 20),   # odd o: scalar z
+    ((40, 36, 44), ([0, 14, 40], [0, 10, 36], [0, 20, 44]), 2, 7, 20),   # 16-byte z accesses
+    ((32, 24, 48), ([0, 8, 16, 32], [0, 12, 24], [0, 16, 32, 48]), 4, 5, 15),
+    ((33, 30, 26), ([0, 11, 33], [0, 16, 30], [0, 13, 26]), 5, 5, 12),
+    ((8, 6, 4), ([0, 1, 2, 3, 4, 5, 6, 7, 8], [0, 2, 4, 6], [0, 2, 4]), 3, 3, 8),  # o > block
+]
+
+
+@pytest.mark.parametrize("shape,cuts,ov,m,K", CASES)
+def test_overlap_fp64_matched(orc, shape, cuts, ov, m, K):
+    rng = np.random.default_rng(300 + ov)
+    b = rng.standard_normal(shape) / 100
+    faces = inputs.random_faces(*shape, seed=301)
+    st, xg, xo, hist, inner = _pair(orc, shape, cuts, b, faces, ov, m, K)
+    assert st.status == 0 and st.sweeps == K
+    assert rel(xg, xo) <= TOL_FP64, rel(xg, xo)
+    assert st.inner_iters == inner
+    np.testing.assert_allclose(st.history, hist, rtol=1e-9, atol=HIST_ATOL)
+
+
+@pytest.mark.parametrize("kw", [dict(rows=2), dict(rows=4, x_chunk=4), dict(group_blocks=1),
+                                dict(group_blocks=-1), dict(use_graph=False)])
+def test_overlap_schedule_options(orc, kw):
+    shape, cuts = (40, 36, 44), ([0, 14, 40], [0, 10, 36], [0, 20, 44])
+    rng = np.random.default_rng(302)
+    b = rng.standard_normal(shape) / 100
+    faces = inputs.random_faces(*shape, seed=303)
+    st, xg, xo, _, _ = _pair(orc, shape, cuts, b, faces, 2, 6, 14, **kw)
+    assert st.status == 0 and st.sweeps == 14
+    assert rel(xg, xo) <= TOL_FP64, (kw, rel(xg, xo))
+
+
+def test_overlap_to_tolerance(orc):
+    """The GPU's stopping rule with overlap stops where the oracle's does."""
+    torch = torch_cuda()
+    shape, cuts = (48, 40, 36), ([0, 16, 32, 48], [0, 20, 40], [0, 12, 24, 36])
+    b = inputs.poisson_randn(shape, 304)
+    beff = orc.lift_bc(b, [None] * 6)
+    ost, xo, K, _, _ = orc.block_jacobi_ovl(beff, np.zeros(shape), cuts, 1, tol=1e-8, m=8)
+    assert ost == 0
+    h, _ = make(ms, shape, cuts, [None] * 6)
+    ms.ms_set_overlap(h, 1)
+    x = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    say("overlap to tol")
+    st = ms.ms_solve(h, dev(b), x, 1e-8, 8, "sync")
+    assert st.status == 0 and st.sweeps == K and st.rel_residual <= 1e-8
+    assert rel(host(x), xo) <= TOL_FP64
+    # the library's residual (each cell counted once) agrees with the oracle's:
+    # at a relative residual of 1e-8 rounding in b - Ax leaves ~eps / 1e-8
+    # relative difference (3e-10 seen), while counting the overlap cells of
+    # the regions too would be off by several percent
+    r_rel, r_abs = ms.ms_residual(h, dev(b), x)
+    assert abs(r_abs - orc.residual(beff, host(x))) <= 1e-6 * r_abs
+    ms.ms_destroy(h)
+
+
+@pytest.mark.parametrize("ov", [1, 4])
+def test_overlap_mixed_refines_to_fp64(orc, ov):
+    torch = torch_cuda()
+    shape, cuts = (48, 40, 36), ([0, 16, 32, 48], [0, 20, 40], [0, 12, 24, 36])
+    b = inputs.poisson_randn(shape, 305)
+    faces = inputs.random_faces(*shape, seed=306)
+    beff = orc.lift_bc(b, faces)
+    ost, xo, K, _, _ = orc.block_jacobi_ovl(beff, np.zeros(shape), cuts, ov, tol=1e-8, m=8)
+    h, _ = make(ms, shape, cuts, faces)
+    ms.ms_set_overlap(h, ov)
+    x = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    say("overlap mixed", ov)
+    st = ms.ms_solve(h, dev(b), x, 1e-8, 8, "sync", precision="mixed")
+    assert st.status == 0 and st.rel_residual <= 1e-8
+    assert rel(host(x), xo) <= TOL_MIXED, rel(host(x), xo)
+    assert abs(st.sweeps - K) <= max(3, K // 20), (st.sweeps, K)
+    ms.ms_destroy(h)
+
+
+def test_overlap_cuts_sweeps(orc):
+    """Overlap lowers the sweeps to tolerance (the paper's observation; the
+    oracle gives 527 sweeps at o = 0 and 219 at o = 1 here, deeper overlap
+    helping less with 5 inner iterations), and the GPU's counts equal the
+    oracle's for each overlap."""
+    torch = torch_cuda()
+    n = 48
+    shape, cuts = (n, n, n), [inputs.uniform_cuts(n, 4)] * 3
+    b = inputs.poisson_randn(shape, 307)
+    beff = orc.lift_bc(b, [None] * 6)
+    h, _ = make(ms, shape, cuts, [None] * 6)
+    counts = {}
+    for ov in (0, 1, 2, 4):
+        ms.ms_set_overlap(h, ov)
+        x = torch.zeros(shape, dtype=torch.float64, device="cuda")
+        say("overlap sweeps", ov)
+        st = ms.ms_solve(h, dev(b), x, 1e-6, 5, "sync")
+        ost, _, K, _, _ = orc.block_jacobi_ovl(beff, np.zeros(shape), cuts, ov, tol=1e-6, m=5)
+        assert st.sweeps == K, (ov, st.sweeps, K)
+        counts[ov] = K
+    ms.ms_destroy(h)
+    assert all(counts[0] > counts[ov] for ov in (1, 2, 4)), counts
+
+
+def test_overlap_back_to_zero_is_plain(orc):
+    """Setting overlap and then 0 again gives the plain block-Jacobi iterate
+    bit for bit."""
+    torch = torch_cuda()
+    shape, cuts = (40, 36, 44), ([0, 14, 40], [0, 10, 36], [0, 20, 44])
+    rng = np.random.default_rng(308)
+    b = dev(rng.standard_normal(shape))
+    h, _ = make(ms, shape, cuts, [None] * 6)
+    xa = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    say("overlap reset")
+    ms.ms_solve(h, b, xa, 0.0, 6, "sync", max_sweeps=9)
+    ms.ms_set_overlap(h, 3)
+    xt = torch.zeros_like(xa)
+    ms.ms_solve(h, b, xt, 0.0, 6, "sync", max_sweeps=9)
+    ms.ms_set_overlap(h, 0)
+    xb = torch.zeros_like(xa)
+    ms.ms_solve(h, b, xb, 0.0, 6, "sync", max_sweeps=9)
+    ms.ms_destroy(h)
+    assert torch.equal(xa, xb)
+    assert not torch.equal(xa, xt)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_overlap_batch_matches_single(precision):
+    torch = torch_cuda()
+    shape, cuts = (32, 24, 48), ([0, 8, 16, 32], [0, 12, 24], [0, 16, 32, 48])
+    rng = np.random.default_rng(309)
+    B = dev(rng.standard_normal((3,) + shape))
+    h, _ = make(ms, shape, cuts, [None] * 6)
+    ms.ms_reserve(h, 3)
+    ms.ms_set_overlap(h, 2)
+    X = torch.zeros_like(B)
+    say("overlap batch", precision)
+    ms.ms_solve_batch(h, B, X, 0.0, 5, max_sweeps=11, precision=precision)
+    for k in range(3):
+        x = torch.zeros(shape, dtype=torch.float64, device="cuda")
+        ms.ms_solve(h, B[k].contiguous(), x, 0.0, 5, "sync", max_sweeps=11, precision=precision)
+        assert torch.equal(x, X[k]), k
+    ms.ms_destroy(h)
+
+
+def test_overlap_errors():
+    torch = torch_cuda()
+    shape = (16, 16, 16)
+    h, _ = make(ms, shape, [inputs.uniform_cuts(16, 2)] * 3, [None] * 6)
+    with pytest.raises(ms.MsError) as e:
+        ms.ms_set_overlap(h, -1)
+    assert e.value.status == ms.MS_ERR_ARG
+    with pytest.raises(ms.MsError) as e:
+        ms.ms_set_overlap(h, 17)
+    assert e.value.status == ms.MS_ERR_ARG
+    ms.ms_set_overlap(h, 2)
+    b = torch.ones(shape, dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+    with pytest.raises(ms.MsError) as e:
+        ms.ms_solve(h, b, x, 1e-6, 5, "async")
+    assert e.value.status == ms.MS_ERR_UNSUPPORTED
+    ms.ms_destroy(h)
