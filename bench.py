@@ -36,7 +36,7 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_2009_12638_amd", "csrc", "ms_kernels.h
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_bumps512_sync_mixed.json")
 HBM_PEAK_GBPS = 8000.0
 ALL_MODES = ["sync-mixed", "sync-fp64", "async-mixed", "async-fp64", "cg-fp64",
-             "batch-mixed", "batch-fp64"]
+             "batch-mixed", "batch-fp64", "gmres-mixed", "gmres-fp64"]
 BATCH_WORKLOAD = "uneven384"   # batched modes: 16 right-hand sides, uneven blocks
 
 
@@ -64,8 +64,26 @@ def kernel_bytes(m: int, T: int):
     return out
 
 
-def sweep_bytes(m: int, T: int) -> int:
-    return sum(b for _, b in kernel_bytes(m, T))
+def kernel_bytes_gmres(m: int, T: int):
+    """Compulsory bytes per unknown of each launch of a synchronous sweep
+    with GMRES(m) inner solves (per-block Hessenberg kernels move no vector):
+
+    resid   : read x, b, write u_0
+    stencil : Arnoldi step j, w = A v_j: read u_j, write w, read u_0..u_{j-1}
+              for the dots (u_j counted once)
+    orth    : read w and u_0..u_j, write u_{j+1}
+    final   : read x_old and u_0..u_{m-1}, write x_new
+    """
+    out = [("resid", 16 + T)]
+    for j in range(m):
+        out.append(("stencil", (j + 2) * T))
+        out.append(("orth", (j + 3) * T))
+    out.append(("final", 16 + m * T))
+    return out
+
+
+def sweep_bytes(m: int, T: int, gmres: bool = False) -> int:
+    return sum(b for _, b in (kernel_bytes_gmres if gmres else kernel_bytes)(m, T))
 
 
 def model_sweep_bytes(m: int, mixed: bool) -> int:
@@ -126,9 +144,11 @@ def run_mode(args, torch, ms, w, mode: str, oracle_check):
     b = torch.from_numpy(w["b"]).to("cuda")
     nrhs = b.shape[0] if kind == "batch" else 1
     h = ms.ms_create(shape, cuts=[list(map(int, c)) for c in cuts], faces=None)
-    ov = args.overlap if kind in ("sync", "batch") else 0
+    ov = args.overlap if kind in ("sync", "batch", "gmres") else 0
     if ov:
         ms.ms_set_overlap(h, ov)
+    if kind == "gmres":
+        ms.ms_reserve_krylov(h, m)
     NR = region_cells(shape, cuts, ov)   # cells the residual and inner kernels touch
     x = torch.zeros_like(b)
     tuned = {}
@@ -147,6 +167,9 @@ def run_mode(args, torch, ms, w, mode: str, oracle_check):
         if kind == "batch":
             return ms.ms_solve_batch(h, b, x, 0.0, m, max_sweeps=k, precision=precision,
                                      **tile_kw, **kw)[0]
+        if kind == "gmres":
+            return ms.ms_solve(h, b, x, 0.0, m, "sync", max_sweeps=k, precision=precision,
+                               inner="gmres", **kw)
         return ms.ms_solve(h, b, x, 0.0, m, kind, max_sweeps=k, precision=precision, **kw)
 
     log(f"{mode}: warmup {args.warmup}")
@@ -170,22 +193,23 @@ def run_mode(args, torch, ms, w, mode: str, oracle_check):
         res["GBps"] = round(bpu * N * args.steps / sec / 1e9, 1)
         res["bytes_per_unknown_step"] = bpu
     else:
-        fin = dict(kernel_bytes(m, T))["final"]
-        sweep_total = (sweep_bytes(m, T) - fin) * NR + fin * N
+        gm = kind == "gmres"
+        fin = dict((kernel_bytes_gmres if gm else kernel_bytes)(m, T))["final"]
+        sweep_total = (sweep_bytes(m, T, gm) - fin) * NR + fin * N
         res["GBps"] = round(sweep_total * nrhs * args.steps / sec / 1e9, 1)
-        res["bytes_per_unknown_step"] = sweep_bytes(m, T)
+        res["bytes_per_unknown_step"] = sweep_bytes(m, T, gm)
         res["model_GBps"] = round(model_sweep_bytes(m, T == 4) * N * nrhs * args.steps / sec / 1e9, 1)
         res["unknown_iters_per_s"] = N * nrhs * m * args.steps / sec
     if kind == "async":
         res["max_staleness_seen"] = st.max_staleness_seen
-    if kind in ("sync", "cg", "batch"):
+    if kind in ("sync", "cg", "batch", "gmres"):
         prof = step(max(2, min(args.steps, 5)), profile=True)
-        if kind in ("sync", "batch"):
+        if kind in ("sync", "batch", "gmres"):
             lists = {}
-            for name, by in kernel_bytes(m, T):
+            for name, by in (kernel_bytes_gmres if kind == "gmres" else kernel_bytes)(m, T):
                 lists.setdefault(name, []).append(by)
             cells = {"resid": NR * nrhs, "stencil": NR * nrhs, "update": NR * nrhs,
-                     "final": N * nrhs}
+                     "orth": NR * nrhs, "final": N * nrhs}
             res["kernels"] = per_kernel(prof, N * nrhs, lists, extra={"resid": 16 * NR * nrhs},
                                         cells=cells)
         else:
@@ -207,9 +231,11 @@ def run_mode(args, torch, ms, w, mode: str, oracle_check):
             # in chunks so progress is printed; a sweep resumed from x is the
             # same sweep (the whole outer state is x)
             total = 0
+            extra = {"inner": "gmres"} if kind == "gmres" else {}
             while True:
-                fs = ms.ms_solve(h, b, x, w["tol"], m, kind, precision=precision,
-                                 max_sweeps=args.chunk, raise_on_error=False)
+                fs = ms.ms_solve(h, b, x, w["tol"], m, "sync" if kind == "gmres" else kind,
+                                 precision=precision, max_sweeps=args.chunk,
+                                 raise_on_error=False, **extra)
                 total += fs.sweeps
                 if fs.status == ms.MS_OK:
                     break

@@ -86,6 +86,43 @@ def test_sampled_block_sweep(orc, name, precision, ov):
     print(f"{name} {precision} overlap {ov}: worst block correction error {worst:.2e}")
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_bumps512_gmres_sampled_blocks(orc, precision):
+    """GMRES(10) inner solves at 512^3 (the paper's inner solver): one GPU
+    sweep from the GPU's own iterate against the oracle's per-block GMRES
+    sweep on sampled blocks."""
+    torch = torch_cuda()
+    w = workload("bumps512")
+    shape, cuts = w["shape"], w["cuts"]
+    g = len(cuts[0]) - 1
+    h = ms.ms_create(shape, cuts=[list(map(int, c)) for c in cuts], faces=None)
+    ms.ms_reserve_krylov(h, w["m"])
+    b = dev(w["b"])
+    x = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    say("fullsize gmres", precision, "2 sweeps")
+    ms.ms_solve(h, b, x, 0.0, w["m"], "sync", max_sweeps=2, precision=precision, inner="gmres")
+    x2 = host(x)
+    say("fullsize gmres", precision, "1 more sweep")
+    ms.ms_solve(h, b, x, 0.0, w["m"], "sync", max_sweeps=1, precision=precision, inner="gmres")
+    x3 = host(x)
+    del x, b
+    ms.ms_destroy(h)
+    torch.cuda.empty_cache()
+    beff = orc.lift_bc(w["b"], [None] * 6)
+    blocks = sampled_blocks(g)
+    xo = orc.multisplit_sweep_some(beff, x2, cuts, blocks, m=w["m"], inner="gmres")
+    cx, cy, cz = cuts
+    worst = 0.0
+    for blk in blocks:
+        bi, bj, bk = blk // (g * g), (blk // g) % g, blk % g
+        sl = (slice(cx[bi], cx[bi + 1]), slice(cy[bj], cy[bj + 1]), slice(cz[bk], cz[bk + 1]))
+        e = rel(x3[sl] - x2[sl], xo[sl] - x2[sl])
+        worst = max(worst, e)
+        assert e <= D_TOL[precision], (blk, e)
+    assert np.isfinite(x3).all()
+    print(f"bumps512 gmres {precision}: worst block correction error {worst:.2e}")
+
+
 def test_uneven384_batch_sampled_blocks(orc):
     """The batched workload at full size (384x320x448, uneven blocks with
     edges from {32,48,64,96}, 16 right-hand sides, mixed precision): sampled
