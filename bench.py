@@ -32,7 +32,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "time-to-1e-8 residual & stencil/CG HBM GB/s, 512^3 Laplace; mixed vs plain FP64"
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2009_12638_amd", "csrc", "ms_kernels.hip")
+# the sources of the sweep kernels: the traffic counters are only reused while
+# these are unchanged
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2009_12638_amd", "csrc", f)
+                  for f in ("ms_kernels.hip", "ms_device.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_bumps512_sync_mixed.json")
 HBM_PEAK_GBPS = 8000.0
 ALL_MODES = ["sync-mixed", "sync-fp64", "async-mixed", "async-fp64", "cg-fp64",
@@ -302,6 +305,38 @@ def overlap_study(args, torch, ms, inputs):
     return out
 
 
+def layout_study(args, torch, ms, inputs):
+    """Sweeps and time to a tolerance for several block layouts of the study
+    workload's grid (synchronous, mixed precision): the paper's comparison of
+    2 blocks along x, 16 along x and 4x2x2 (Section 3.2) on this GPU."""
+    w = inputs.workload(args.study_workload)
+    shape = w["shape"]
+    b = torch.from_numpy(w["b"]).to("cuda")
+    out = {"workload": args.study_workload, "tol": args.layout_tol, "inner_iters": args.m,
+           "precision": "mixed", "runs": []}
+    for lay in args.layout_study.split(","):
+        g = tuple(int(v) for v in lay.split("x"))
+        h = ms.ms_create(shape, blocks=g)
+        x = torch.zeros_like(b)
+        ms.ms_solve(h, b, x, 0.0, args.m, "sync", max_sweeps=2, precision="mixed")  # warm
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = ms.ms_solve(h, b, x, args.layout_tol, args.m, "sync", precision="mixed",
+                         max_sweeps=200000)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        out["runs"].append({"blocks": lay, "sweeps_to_tol": st.sweeps, "seconds": round(sec, 3),
+                            "ms_per_sweep": round(1e3 * sec / max(st.sweeps, 1), 4),
+                            "final_rel_residual": st.rel_residual})
+        log(f"layout {lay}: {st.sweeps} sweeps, {sec:.2f} s")
+        ms.ms_destroy(h)
+        del x
+    del b
+    torch.cuda.empty_cache()
+    return out
+
+
 def measured_traffic(kernel: str, unknowns_per_launch: int):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a
@@ -311,8 +346,11 @@ def measured_traffic(kernel: str, unknowns_per_launch: int):
     try:
         with open(TRAFFIC_FILE) as f:
             data = json.load(f)
-        with open(KERNEL_SOURCE, "rb") as f:
-            sha = hashlib.sha1(f.read()).hexdigest()
+        h = hashlib.sha1()
+        for src in KERNEL_SOURCES:
+            with open(src, "rb") as f:
+                h.update(f.read())
+        sha = h.hexdigest()
     except (OSError, ValueError):
         return None
     k = data.get("kernels", {}).get(kernel)
@@ -394,6 +432,10 @@ def main():
                     help="comma list of overlap depths: solve the study workload to "
                          "tolerance for each (sync, mixed)")
     ap.add_argument("--study-workload", default="poisson256")
+    ap.add_argument("--layout-study", default="",
+                    help="comma list of block layouts GXxGYxGZ: solve the study workload to "
+                         "--layout-tol for each (sync, mixed)")
+    ap.add_argument("--layout-tol", type=float, default=1e-5)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for hardware counters)")
     args = ap.parse_args()
@@ -447,6 +489,7 @@ def main():
             results[mo] = run_mode(args, torch, ms, w, mo,
                                    oracle_check if args.full_solve else None)
     study = overlap_study(args, torch, ms, inputs) if args.overlap_study else None
+    layouts = layout_study(args, torch, ms, inputs) if args.layout_study else None
     log("copy probe: device copy bandwidth")
     copy_gbps = copy_peak(torch)
     head = results[modes[0]]
@@ -501,6 +544,8 @@ def main():
         line["config"]["overlap"] = args.overlap
     if study:
         line["overlap_study"] = study
+    if layouts:
+        line["layout_study"] = layouts
     print(json.dumps(line), flush=True)
 
 
