@@ -99,13 +99,17 @@ CG_BYTES = {"stencil": 24, "update": 40}   # FP64 global CG, per unknown per ite
 
 
 def region_cells(shape, cuts, overlap: int) -> int:
-    """Cells of the inner-solve boxes with overlap (each block grown by the
-    overlap across faces that have a neighbour, clipped to the grid); the
-    grid size when overlap is 0."""
+    """Cells of the inner-solve boxes with overlap (each block grown across
+    faces that have a neighbour, clipped to the grid); the grid size when
+    overlap is 0."""
+    # z grows by the overlap rounded up to the widest vector the z cuts allow
+    vzb = next((w for w in (4, 2) if shape[2] % w == 0 and all(int(v) % w == 0 for v in cuts[2])),
+               1)
+    grow = [overlap, overlap, -(-overlap // vzb) * vzb]
     per_axis = []
-    for n, c in zip(shape, cuts):
+    for n, c, gr in zip(shape, cuts, grow):
         c = [int(v) for v in c]
-        per_axis.append([c[t + 1] - c[t] + min(overlap, c[t]) + min(overlap, n - c[t + 1])
+        per_axis.append([c[t + 1] - c[t] + min(gr, c[t]) + min(gr, n - c[t + 1])
                          for t in range(len(c) - 1)])
     total = 0
     for a in per_axis[0]:

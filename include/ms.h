@@ -170,8 +170,9 @@ ms_status ms_set_bc(ms_handle *h, const ms_bc *bc);
  * Applies to later ms_solve (MS_SYNC only; MS_ASYNC returns
  * MS_ERR_UNSUPPORTED while o > 0) and ms_solve_batch calls.  Allocates when
  * the regions need larger inner buffers than the handle holds (never
- * shrinks them).  Vector z accesses need o to be a multiple of the vector
- * width, so an odd o runs scalar z accesses.
+ * shrinks them).  The inner box of a block is grown in z by o rounded up
+ * to the vector width (the cells beyond depth o are masked), so z accesses
+ * keep their full width for any o.
  * Errors: MS_ERR_ARG (o < 0 or larger than the grid), MS_ERR_NOMEM (the
  * handle keeps its previous overlap), MS_ERR_HIP. */
 ms_status ms_set_overlap(ms_handle *h, int32_t overlap);

@@ -53,8 +53,8 @@ struct ms_handle {
     long long nx = 0, ny = 0, nz = 0, N = 0;
     int gx = 0, gy = 0, gz = 0, nblocks = 0;
     std::vector<int> cx, cy, cz;
-    int vzmax = 1;              // widest vector the z cuts, nz and the overlap allow
-    int vzbase = 1;             // widest vector the z cuts and nz allow
+    int vzmax = 1;              // widest vector the z cuts and nz allow
+    int vzbase = 1;             // ... and the width overlap boxes are aligned to in z
     int overlap = 0;            // block overlap depth (0: plain block Jacobi)
     long long inner_n = 0;      // inner-vector elements per right-hand side
     long long inner_cap = 0;    // ... that the inner buffers hold (>= inner_n)
@@ -148,26 +148,31 @@ bool dev_range_ok(const void *p, size_t bytes) {
     return (const char *)p + bytes <= (const char *)base + size;
 }
 
-// Inner-solve box of block b: the block, grown by the overlap depth across
-// every face that has a neighbour (clipped to the grid), with the block's
-// own cells recorded inside it.  The region proper is the box minus its
-// edge and corner parts (cells outside the own box along two or more axes).
+// Inner-solve box of block b: the block, grown across every face that has
+// a neighbour (clipped to the grid) by the overlap depth in x and y and by
+// the depth rounded up to the widest vector width in z (so every vector
+// width the handle uses divides the box's z offset and extent), with the
+// block's own cells recorded inside it.  The region proper is the box minus
+// its edge and corner parts and minus the z cells beyond the depth.
 void region_box(const ms_handle *h, int b, BlockInfo &B) {
     const int bi = b / (h->gy * h->gz), bj = (b / h->gz) % h->gy, bk = b % h->gz;
     const int o = h->overlap;
+    const int oz = (o + h->vzbase - 1) / h->vzbase * h->vzbase;
+    const int grow[3] = {o, o, oz};
     const int c0[3] = {h->cx[bi], h->cy[bj], h->cz[bk]};
     const int c1[3] = {h->cx[bi + 1], h->cy[bj + 1], h->cz[bk + 1]};
     const long long n[3] = {h->nx, h->ny, h->nz};
     int lo[3], ext[3];
     for (int a = 0; a < 3; a++) {
-        lo[a] = std::min(o, c0[a]);
-        const int hi = (int)std::min<long long>(o, n[a] - c1[a]);
+        lo[a] = std::min(grow[a], c0[a]);
+        const int hi = (int)std::min<long long>(grow[a], n[a] - c1[a]);
         ext[a] = c1[a] - c0[a] + lo[a] + hi;
     }
     B.i0 = c0[0] - lo[0]; B.j0 = c0[1] - lo[1]; B.k0 = c0[2] - lo[2];
     B.bx = ext[0]; B.by = ext[1]; B.bz = ext[2];
     B.oi = lo[0]; B.oj = lo[1]; B.ok = lo[2];
     B.obx = c1[0] - c0[0]; B.oby = c1[1] - c0[1]; B.obz = c1[2] - c0[2];
+    B.dep = o;
 }
 
 // Build the tile table for vector width vz, x chunk tx and rows per thread.
@@ -190,7 +195,6 @@ ms_status set_tiling(ms_handle *h, int vz, int tx, int rows, hipStream_t st) {
                 const int nxc = (B.bx + tx - 1) / tx;
                 B.ntiles = B.nplane * nxc;
                 B.tile0 = tile;
-                B.pad_ = 0;
                 for (int t = 0; t < B.ntiles; t++) tb.push_back(b);
                 tile += B.ntiles;
                 off += (long long)B.bx * P;
@@ -945,7 +949,7 @@ ms_status set_cg_tiling(ms_handle *h, int vz, hipStream_t st) {
     B.ntiles = B.nplane * (int)((h->nx + tx - 1) / tx);
     B.oi = B.oj = B.ok = 0;
     B.obx = B.bx; B.oby = B.by; B.obz = B.bz;
-    B.pad_ = 0;
+    B.dep = 0;
     if (B.ntiles > h->cg_cap) return fail(h, MS_ERR_ARG, "global CG tiling exceeds its table");
     std::vector<int> tb(B.ntiles, 0);
     HIPCHK(h, hipMemcpyAsync(h->cg_block_d, &B, sizeof(B), hipMemcpyHostToDevice, st));
@@ -1365,11 +1369,6 @@ ms_status ms_set_overlap(ms_handle *h, int32_t overlap) {
     if (gt) h->tiles_cap = (int)cap;
     h->overlap = overlap;
     h->inner_n = inner;
-    // the vector width must also divide the overlap (so it divides every
-    // region's z offset and extent)
-    h->vzmax = 1;
-    for (int w : {4, 2})
-        if (h->vzbase % w == 0 && overlap % w == 0) { h->vzmax = w; break; }
     h->cur_vz = 0;
     return set_tiling(h, std::min(h->vzmax, 2), 16, 1, nullptr);
 }

@@ -135,13 +135,15 @@ __device__ __forceinline__ int xcd_tile(int w, int n) {
     return c * q + min(c, rem) + k;
 }
 
-// Overlap regions (Section 3.2, block overlap): the number of axes along
-// which box-local cell (i, j, k) lies outside the block's own cells.  0: an
-// own cell; 1: in a face slab of the region; 2 or 3: an edge or corner of
-// the bounding box, outside the region (kept at zero in r, d and p).
+// Overlap regions (Section 3.2, block overlap): where box-local cell
+// (i, j, k) lies.  0: an own cell; 1: in a face slab of the region (outside
+// the own cells along one axis, by at most the overlap depth); 2 or more:
+// outside the region (an edge or corner of the box, or beyond the depth in
+// z where the box is grown further for alignment), kept at zero in r, d, p.
 __device__ __forceinline__ int axes_out(const BlockInfo &B, int i, int j, int k) {
+    const int zfar = (k < B.ok - B.dep) || (k >= B.ok + B.obz + B.dep);
     return ((unsigned)(i - B.oi) >= (unsigned)B.obx) + ((unsigned)(j - B.oj) >= (unsigned)B.oby) +
-           ((unsigned)(k - B.ok) >= (unsigned)B.obz);
+           ((unsigned)(k - B.ok) >= (unsigned)B.obz) + 2 * zfar;
 }
 
 }  // namespace ms

@@ -11,10 +11,12 @@ constexpr int kAsyncThreads = 512;  // threads per persistent asynchronous worke
 
 // One block of the partition (Section 3: the unknowns X_i of one block).
 // The box [i0, i0+bx) x [j0, j0+by) x [k0, k0+bz) is the block's inner-solve
-// domain: the block itself, or with overlap the bounding box of its region
-// (the block plus slabs of depth o across faces that have a neighbour).
-// The block's own cells are the sub-box at offset (oi, oj, ok) of extents
-// (obx, oby, obz); without overlap that is the whole box.
+// domain: the block itself, or with overlap the box holding its region (the
+// block plus slabs of depth dep across faces that have a neighbour).  The
+// box is grown by dep in x and y and by dep rounded up to the widest vector
+// width in z, so z vectors stay aligned.  The block's own cells are the
+// sub-box at offset (oi, oj, ok) of extents (obx, oby, obz); without overlap
+// that is the whole box.
 struct BlockInfo {
     int i0, j0, k0;   // origin in the global interior grid
     int bx, by, bz;   // extents
@@ -24,7 +26,7 @@ struct BlockInfo {
     int nplane;       // tiles across one y-z plane
     int oi, oj, ok;   // own cells: offset inside the box
     int obx, oby, obz;  // own cells: extents
-    int pad_;
+    int dep;          // overlap depth (0: none)
 };
 
 // Device-side control block: convergence state of one solve.
