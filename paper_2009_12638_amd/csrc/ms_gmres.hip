@@ -52,14 +52,20 @@ __device__ __forceinline__ double *rec(double *gm, const GmArgs &a, int k, int b
     return gm + ((long long)k * a.nblocks + b) * a.rec_stride;
 }
 
-// The whole block's tile partials of slot `slot`, in tile order (FP64).
+// The whole block's tile partials of slot `slot` (FP64), summed by the 64
+// lanes of one wavefront: lane l adds tiles l, l+64, ... in order, then a
+// butterfly; a fixed order, and every lane gets the sum.
 template <typename T>
 __device__ __forceinline__ double block_sum(const T *part, long long stride, int slot,
                                             int tile0, int ntiles) {
     double s = 0.0;
-    for (int t = 0; t < ntiles; t++) s += (double)part[(long long)(tile0 + t) * stride + slot];
-    return s;
+    for (int t = threadIdx.x; t < ntiles; t += 64)
+        s += (double)part[(long long)(tile0 + t) * stride + slot];
+    return wave_sum(s);
 }
+
+// Dot products reduced together (one workgroup barrier per batch).
+constexpr int kDotBatch = 8;
 
 // w = A_box u (zero outside the box; overlap: zero outside the region)
 // times inv_s, on one tile of one-row threads; w kept in wv and stored.
@@ -138,19 +144,21 @@ __device__ __forceinline__ void tile_gm_apply(const Tile &t, long long goff,
 
 }  // namespace
 
+// The per-block kernels below run one 64-lane workgroup per (right-hand
+// side, block of the group); lane 0 does the scalar work.
+
 // Start of a block's GMRES cycle: beta = ||r|| from the residual kernel's
-// region partials; one thread per (right-hand side, block of the group).
+// region partials.
 template <typename T>
-__global__ void k_gm_init(const BlockInfo *blocks, int b0, int nb, const T *pT, Batch bt,
-                          GmArgs a, Ctrl *ctrl) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nb * bt.nrhs) return;
-    const int k = q / nb, b = b0 + q % nb;
+__global__ __launch_bounds__(64) void k_gm_init(const BlockInfo *blocks, int b0, int nb,
+                                                const T *pT, Batch bt, GmArgs a, Ctrl *ctrl) {
+    const int k = blockIdx.x / nb, b = b0 + blockIdx.x % nb;
     if (ctrl[k].done) return;
     const BlockInfo &B = blocks[b];
     const GmRec R{a.M};
     double *st = rec(a.gm, a, k, b);
     const double beta = sqrt(block_sum(pT + (long long)k * bt.ps, 1, 0, B.tile0, B.ntiles));
+    if (threadIdx.x != 0) return;
     st[R.s()] = beta;
     st[R.g()] = beta;
     st[R.beta()] = beta;
@@ -179,31 +187,49 @@ __global__ __launch_bounds__(kThreads) void k_gm_apply(Geom g, int t0, long long
     const int bz = t.B.bz;
     const long long P = (long long)t.B.by * bz;
     const long long base = (t.B.off - goff) + (long long)t.j0 * bz + t.k;
-    for (int i = 0; i <= j; i++) {
-        const T *ui = V + (long long)i * a.kvs + ko;
-        T acc = T(0);
+    __shared__ T sh[kThreads / 64][kDotBatch];
+    for (int i0 = 0; i0 <= j; i0 += kDotBatch) {
+        T acc[kDotBatch];
+#pragma unroll
+        for (int c = 0; c < kDotBatch; c++) acc[c] = T(0);
         if (t.nrows > 0) {
 #pragma unroll
-            for (int q = 0; q < kGmPlanes; q++) {
-                if (t.xbeg + q >= t.xend) continue;
-                T uv[VZ];
-                vload<T, VZ>(ui + base + (long long)(t.xbeg + q) * P, uv);
+            for (int c = 0; c < kDotBatch; c++) {
+                if (i0 + c > j) continue;
+                const T *ui = V + (long long)(i0 + c) * a.kvs + ko + base;
 #pragma unroll
-                for (int v = 0; v < VZ; v++) acc += wv[q][v] * uv[v];
+                for (int q = 0; q < kGmPlanes; q++) {
+                    if (t.xbeg + q >= t.xend) continue;
+                    T uv[VZ];
+                    vload<T, VZ>(ui + (long long)(t.xbeg + q) * P, uv);
+#pragma unroll
+                    for (int v = 0; v < VZ; v++) acc[c] += wv[q][v] * uv[v];
+                }
             }
         }
-        const T s = wg_allsum<T, kThreads>(acc);
-        if (threadIdx.x == 0) part[i] = (double)s;
+        // workgroup sums of the batch: lanes by butterfly, then the four
+        // wavefronts in order
+#pragma unroll
+        for (int c = 0; c < kDotBatch; c++) {
+            const T sv = wave_sum(acc[c]);
+            if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6][c] = sv;
+        }
+        __syncthreads();
+        if (threadIdx.x < kDotBatch && i0 + (int)threadIdx.x <= j) {
+            T sv = T(0);
+#pragma unroll
+            for (int wv_ = 0; wv_ < kThreads / 64; wv_++) sv += sh[wv_][threadIdx.x];
+            part[i0 + threadIdx.x] = (double)sv;
+        }
+        __syncthreads();
     }
 }
 
 // Arnoldi step j, part 2 (per block): h_ij = (w, u_i) / s_i, i <= j.
 template <typename T>
-__global__ void k_gm_coef(const BlockInfo *blocks, int b0, int nb, int j, Batch bt, GmArgs a,
-                          Ctrl *ctrl) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nb * bt.nrhs) return;
-    const int k = q / nb, b = b0 + q % nb;
+__global__ __launch_bounds__(64) void k_gm_coef(const BlockInfo *blocks, int b0, int nb, int j,
+                                                Batch bt, GmArgs a, Ctrl *ctrl) {
+    const int k = blockIdx.x / nb, b = b0 + blockIdx.x % nb;
     if (ctrl[k].done) return;
     const GmRec R{a.M};
     double *st = rec(a.gm, a, k, b);
@@ -212,8 +238,10 @@ __global__ void k_gm_coef(const BlockInfo *blocks, int b0, int nb, int j, Batch 
     const double *part = a.gpart + (long long)k * bt.ps * a.gstride;
     for (int i = 0; i <= j; i++) {
         const double h = block_sum(part, a.gstride, i, B.tile0, B.ntiles) / st[R.s() + i];
-        st[R.R() + i * a.M + j] = h;
-        st[R.coef() + i] = h / st[R.s() + i];
+        if (threadIdx.x == 0) {
+            st[R.R() + i * a.M + j] = h;
+            st[R.coef() + i] = h / st[R.s() + i];
+        }
     }
 }
 
@@ -273,11 +301,10 @@ __global__ __launch_bounds__(kThreads) void k_gm_orth(Geom g, int t0, long long 
 // Arnoldi step j, part 4 (per block): h_{j+1,j} = ||u_{j+1}||, Givens
 // rotations of column j, least-squares residual and the stopping rules
 // (m steps, inner_tol, an invariant Krylov space).
-__global__ void k_gm_norm(const BlockInfo *blocks, int b0, int nb, int j, double inner_tol,
-                          Batch bt, GmArgs a, Ctrl *ctrl) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nb * bt.nrhs) return;
-    const int k = q / nb, b = b0 + q % nb;
+__global__ __launch_bounds__(64) void k_gm_norm(const BlockInfo *blocks, int b0, int nb, int j,
+                                                double inner_tol, Batch bt, GmArgs a,
+                                                Ctrl *ctrl) {
+    const int k = blockIdx.x / nb, b = b0 + blockIdx.x % nb;
     if (ctrl[k].done) return;
     const GmRec R{a.M};
     double *st = rec(a.gm, a, k, b);
@@ -286,6 +313,7 @@ __global__ void k_gm_norm(const BlockInfo *blocks, int b0, int nb, int j, double
     const int M = a.M;
     const double *part = a.gpart + (long long)k * bt.ps * a.gstride;
     const double hn = sqrt(block_sum(part, a.gstride, M + 1, B.tile0, B.ntiles));
+    if (threadIdx.x != 0) return;
     double *H = st + R.R();
     for (int i = 0; i < j; i++) {
         const double x0 = H[i * M + j], x1 = H[(i + 1) * M + j];
@@ -360,21 +388,31 @@ __global__ __launch_bounds__(kThreads) void k_gm_final(Geom g, int t0, long long
     const long long P = (long long)t.B.by * bz;
     const long long base = (t.B.off - goff) + (long long)t.j0 * bz + t.k;
     const long long J = t.B.j0 + t.j0, K = t.B.k0 + t.k;
-    for (int i = t.xbeg; i < t.xend; i++) {
-        if (OVL && axes_out(t.B, i, t.j0, t.k) != 0) continue;
-        const long long gI = ((long long)(t.B.i0 + i) * g.ny + J) * g.nz + K;
-        const long long o = base + (long long)i * P;
-        double xv[VZ];
-        vload<double, VZ>(xa + gI, xv);
-        for (int l = 0; l < n; l++) {
-            const double c = st[R.y() + l];
-            T uv[VZ];
-            vload<T, VZ>(V + (long long)l * a.kvs + ko + o, uv);
+    // planes of this thread that hold own cells (all of them without overlap)
+    bool mine[kGmPlanes];
+    double xv[kGmPlanes][VZ];
 #pragma unroll
-            for (int v = 0; v < VZ; v++) xv[v] += c * (double)uv[v];
-        }
-        vstore<double, VZ>(xb + gI, xv);
+    for (int q = 0; q < kGmPlanes; q++) {
+        const int i = t.xbeg + q;
+        mine[q] = i < t.xend && !(OVL && axes_out(t.B, i, t.j0, t.k) != 0);
+        if (mine[q]) vload<double, VZ>(xa + ((long long)(t.B.i0 + i) * g.ny + J) * g.nz + K, xv[q]);
     }
+    for (int l = 0; l < n; l++) {
+        const double c = st[R.y() + l];
+        const T *ul = V + (long long)l * a.kvs + ko + base;
+#pragma unroll
+        for (int q = 0; q < kGmPlanes; q++) {
+            if (!mine[q]) continue;
+            T uv[VZ];
+            vload<T, VZ>(ul + (long long)(t.xbeg + q) * P, uv);
+#pragma unroll
+            for (int v = 0; v < VZ; v++) xv[q][v] += c * (double)uv[v];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kGmPlanes; q++)
+        if (mine[q])
+            vstore<double, VZ>(xb + ((long long)(t.B.i0 + t.xbeg + q) * g.ny + J) * g.nz + K, xv[q]);
 }
 
 // ----------------------------------------------------------------------
@@ -393,9 +431,13 @@ __global__ __launch_bounds__(kThreads) void k_gm_final(Geom g, int t0, long long
         default: return hipErrorInvalidValue;                                       \
     }
 
+// one thread per (right-hand side, block)
 static inline dim3 small_grid(int nb, int nrhs) {
     return dim3((unsigned)((nb * nrhs + 63) / 64));
 }
+
+// one 64-lane workgroup per (right-hand side, block)
+static inline dim3 wave_grid(int nb, int nrhs) { return dim3((unsigned)(nb * nrhs)); }
 
 static inline dim3 gm_batch_grid(int t0, int t1, Batch &bt) {
     bt.nt = t1 - t0;
@@ -406,7 +448,7 @@ template <typename T>
 hipError_t launch_gm_init(const Geom &g, int b0, int b1, const T *pT, Batch bt, GmArgs a,
                           Ctrl *ctrl, hipStream_t st) {
     if (b1 <= b0) return hipSuccess;
-    hipLaunchKernelGGL(k_gm_init<T>, small_grid(b1 - b0, bt.nrhs), dim3(64), 0, st, g.blocks,
+    hipLaunchKernelGGL(k_gm_init<T>, wave_grid(b1 - b0, bt.nrhs), dim3(64), 0, st, g.blocks,
                        b0, b1 - b0, pT, bt, a, ctrl);
     return hipGetLastError();
 }
@@ -427,14 +469,14 @@ hipError_t launch_gm_step(const Geom &g, int vz, int t0, int t1, int b0, int b1,
                                                0, st, g, t0, goff, V, j, bt, a, ctrl));
         }
     } else if (part == 1) {
-        hipLaunchKernelGGL(k_gm_coef<T>, small_grid(b1 - b0, bt.nrhs), dim3(64), 0, st, g.blocks,
+        hipLaunchKernelGGL(k_gm_coef<T>, wave_grid(b1 - b0, bt.nrhs), dim3(64), 0, st, g.blocks,
                            b0, b1 - b0, j, bt, a, ctrl);
     } else if (part == 2) {
         const dim3 grid = gm_batch_grid(t0, t1, bt);
         GM_DISPATCH(vz, hipLaunchKernelGGL((k_gm_orth<T, VZ>), grid, dim3(kThreads), 0, st, g,
                                            t0, goff, V, j, bt, a, ctrl));
     } else {
-        hipLaunchKernelGGL(k_gm_norm, small_grid(b1 - b0, bt.nrhs), dim3(64), 0, st, g.blocks, b0,
+        hipLaunchKernelGGL(k_gm_norm, wave_grid(b1 - b0, bt.nrhs), dim3(64), 0, st, g.blocks, b0,
                            b1 - b0, j, inner_tol, bt, a, ctrl);
     }
     return hipGetLastError();
