@@ -276,33 +276,35 @@ def overlap_study(args, torch, ms, inputs):
     shape, cuts = w["shape"], w["cuts"]
     b = torch.from_numpy(w["b"]).to("cuda")
     h = ms.ms_create(shape, cuts=[list(map(int, c)) for c in cuts], faces=None)
-    out = {"workload": args.study_workload, "tol": w["tol"], "inner_iters": args.m,
-           "precision": "mixed", "runs": []}
+    ms_list = [int(v) for v in args.study_m.split(",")] if args.study_m else [args.m]
+    out = {"workload": args.study_workload, "tol": w["tol"], "precision": "mixed", "runs": []}
     for ov in [int(v) for v in args.overlap_study.split(",")]:
         ms.ms_set_overlap(h, ov)
-        x = torch.zeros_like(b)
-        ms.ms_solve(h, b, x, 0.0, args.m, "sync", max_sweeps=2, precision="mixed")  # warm
-        x.zero_()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        total = 0
-        while True:
-            fs = ms.ms_solve(h, b, x, w["tol"], args.m, "sync", precision="mixed",
-                             max_sweeps=args.chunk, raise_on_error=False)
-            total += fs.sweeps
-            if fs.status == ms.MS_OK:
-                break
-            if fs.status != ms.MS_ERR_NOT_CONVERGED or total > 200000:
-                raise RuntimeError(f"overlap {ov}: solve failed with status {fs.status}")
-        torch.cuda.synchronize()
-        sec = time.perf_counter() - t0
-        rel, _ = ms.ms_residual(h, b, x)
-        out["runs"].append({"overlap": ov, "sweeps_to_tol": total, "seconds": round(sec, 3),
-                            "ms_per_sweep": round(1e3 * sec / max(total, 1), 4),
-                            "region_cells": region_cells(shape, cuts, ov),
-                            "final_rel_residual": rel})
-        log(f"overlap {ov}: {total} sweeps, {sec:.2f} s, residual {rel:.3e}")
-        del x
+        for m in ms_list:
+            x = torch.zeros_like(b)
+            ms.ms_solve(h, b, x, 0.0, m, "sync", max_sweeps=2, precision="mixed")  # warm
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            total = 0
+            while True:
+                fs = ms.ms_solve(h, b, x, w["tol"], m, "sync", precision="mixed",
+                                 max_sweeps=args.chunk, raise_on_error=False)
+                total += fs.sweeps
+                if fs.status == ms.MS_OK:
+                    break
+                if fs.status != ms.MS_ERR_NOT_CONVERGED or total > 200000:
+                    raise RuntimeError(f"overlap {ov}, m {m}: solve failed, status {fs.status}")
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            rel, _ = ms.ms_residual(h, b, x)
+            out["runs"].append({"overlap": ov, "inner_iters": m, "sweeps_to_tol": total,
+                                "seconds": round(sec, 3),
+                                "ms_per_sweep": round(1e3 * sec / max(total, 1), 4),
+                                "region_cells": region_cells(shape, cuts, ov),
+                                "final_rel_residual": rel})
+            log(f"overlap {ov}, m {m}: {total} sweeps, {sec:.2f} s, residual {rel:.3e}")
+            del x
     ms.ms_destroy(h)
     del b
     torch.cuda.empty_cache()
@@ -436,6 +438,9 @@ def main():
                     help="comma list of overlap depths: solve the study workload to "
                          "tolerance for each (sync, mixed)")
     ap.add_argument("--study-workload", default="poisson256")
+    ap.add_argument("--study-m", default="",
+                    help="comma list of inner iteration counts for the overlap study "
+                         "(default: --m)")
     ap.add_argument("--layout-study", default="",
                     help="comma list of block layouts GXxGYxGZ: solve the study workload to "
                          "--layout-tol for each (sync, mixed)")

@@ -11,6 +11,11 @@ sides):
   candidate achieves per second of solve time, measured from a common
   iterate past the initial transient.
 
+It also runs solves whose inner-iteration count varies with the outer
+iteration (Section 2.3 names a fixed or a varying count as a design choice):
+an explicit schedule (solve_schedule), or one chosen while the solve runs
+(solve_adaptive), which records the schedule it used.
+
 Every timed run goes through the C ABI (ms_solve / ms_solve_batch); results
 are cached in a JSON file keyed by the problem.
 """
@@ -134,3 +139,57 @@ def autotune(shape, cuts, b, precision="mixed", cache=DEFAULT_CACHE, tune_m=True
         json.dump(db, f, indent=1)
     os.replace(tmp, cache)
     return out
+
+
+def solve_schedule(h, b, x, tol, schedule, mode="sync", **opts):
+    """Synchronous solve whose inner-iteration count follows `schedule`, a
+    list of (m, sweeps) pairs; the last m repeats until tol (or max_sweeps
+    in total).  x is updated in place.  Returns (status, sweeps, residual)."""
+    max_total = int(opts.pop("max_sweeps", 200000))
+    total = 0
+    st = None
+    steps = list(schedule)
+    while True:
+        m, n = steps.pop(0) if len(steps) > 1 else (steps[0][0], max_total - total)
+        n = min(n, max_total - total)
+        st = ms.ms_solve(h, b, x, tol, m, mode, max_sweeps=n, raise_on_error=False, **opts)
+        total += st.sweeps
+        if st.status != ms.MS_ERR_NOT_CONVERGED or total >= max_total:
+            return st.status, total, st.rel_residual
+
+
+def solve_adaptive(h, b, x, tol, m0=10, m_min=2, m_max=64, chunk=200, max_sweeps=200000,
+                   **opts):
+    """Synchronous solve that picks the inner-iteration count while it runs.
+
+    Sweeps run in chunks.  After each chunk the residual decay rate
+    (decades per second, from the chunk's residual history and wall time)
+    is compared with the previous chunk's: a step of m that made the rate
+    better is repeated in the same direction, one that made it worse is
+    undone and the direction reversed (m doubles or halves within
+    [m_min, m_max]).  x is updated in place.
+
+    Returns (status, total sweeps, final relative residual, schedule): the
+    schedule lists the (m, sweeps) actually run, so the solve can be
+    replayed exactly."""
+    schedule = []
+    total = 0
+    m, prev_rate, direction = int(m0), None, 1
+    while True:
+        n = min(chunk, max_sweeps - total)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = ms.ms_solve(h, b, x, tol, m, "sync", max_sweeps=n, history=n + 1,
+                         raise_on_error=False, **opts)
+        torch.cuda.synchronize()
+        sec = max(time.perf_counter() - t0, 1e-9)
+        schedule.append((m, st.sweeps))
+        total += st.sweeps
+        if st.status != ms.MS_ERR_NOT_CONVERGED or total >= max_sweeps:
+            return st.status, total, st.rel_residual, schedule
+        hist = st.history
+        rate = math.log10(hist[0] / max(hist[-1], 1e-300)) / sec
+        if prev_rate is not None and rate < prev_rate:
+            direction = -direction          # that step hurt: go the other way
+        prev_rate = rate
+        m = max(m_min, min(m_max, m * 2 if direction > 0 else max(1, m // 2)))

@@ -34,3 +34,56 @@ def test_autotune_valid_and_cached(tmp_path, orc):
                 rows=out["rows"], x_chunk=out["x_chunk"])
     d = float(torch.linalg.norm(x1 - x2) / torch.linalg.norm(x1))
     assert d <= 1e-5   # FP32 inner sums in a different tile order
+
+
+def _replay(orc, beff, cuts, schedule, tol):
+    """The oracle run through the same (m, sweeps) schedule, warm-starting
+    each piece from the previous iterate."""
+    x = np.zeros(beff.shape)
+    total = 0
+    for m, n in schedule:
+        st, x, sw, _, _ = orc.block_jacobi(beff, x, cuts, tol=tol, m=m, max_sweeps=n)
+        total += sw
+        if st == 0:
+            break
+    return st, x, total
+
+
+def test_scheduled_inner_iterations_match_oracle(orc):
+    """Inner-iteration counts that change with the outer iteration (an
+    explicit schedule): the same iterate and sweep count as the oracle run
+    through the same schedule."""
+    torch = torch_cuda()
+    from paper_2009_12638_amd import tune
+    shape, cuts = (48, 40, 36), ([0, 16, 32, 48], [0, 20, 40], [0, 12, 24, 36])
+    b = inputs.poisson_randn(shape, 141)
+    beff = orc.lift_bc(b, [None] * 6)
+    h = ms.ms_create(shape, cuts=[list(c) for c in cuts])
+    x = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    schedule = [(3, 40), (12, 25), (6, 10**6)]
+    say("scheduled inner iterations")
+    st, total, res = tune.solve_schedule(h, dev(b), x, 1e-8, schedule)
+    ms.ms_destroy(h)
+    ost, xo, ototal = _replay(orc, beff, cuts, schedule, 1e-8)
+    assert st == 0 and ost == 0 and total == ototal and res <= 1e-8
+    assert float(np.linalg.norm(host(x) - xo) / np.linalg.norm(xo)) <= 1e-10
+
+
+def test_adaptive_inner_iterations_replay(orc):
+    """The adaptive solve reaches tol, changes m along the way, and its
+    recorded schedule replayed by the oracle gives the same iterate."""
+    torch = torch_cuda()
+    from paper_2009_12638_amd import tune
+    shape, cuts = (48, 40, 36), ([0, 16, 32, 48], [0, 20, 40], [0, 12, 24, 36])
+    b = inputs.poisson_randn(shape, 142)
+    beff = orc.lift_bc(b, [None] * 6)
+    h = ms.ms_create(shape, cuts=[list(c) for c in cuts])
+    x = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    say("adaptive inner iterations")
+    st, total, res, schedule = tune.solve_adaptive(h, dev(b), x, 1e-8, m0=4, chunk=30)
+    ms.ms_destroy(h)
+    assert st == 0 and res <= 1e-8
+    assert len({m for m, _ in schedule}) > 1, schedule
+    ost, xo, ototal = _replay(orc, beff, cuts, schedule, 1e-8)
+    assert ost == 0 and ototal == total, (ototal, total)
+    assert float(np.linalg.norm(host(x) - xo) / np.linalg.norm(xo)) <= 1e-10
