@@ -189,6 +189,36 @@ def test_determinism_and_resume():
     assert np.array_equal(host(x), xs[0])
 
 
+@pytest.mark.parametrize("shape,cuts,m,K", [
+    ((1, 1, 1), ([0, 1], [0, 1], [0, 1]), 1, 1),        # one cell: x = b_eff / 6 in one step
+    ((1, 1, 9), ([0, 1], [0, 1], [0, 4, 9]), 4, 6),     # a single z line in two blocks
+    ((1, 7, 1), ([0, 1], [0, 3, 7], [0, 1]), 3, 6),     # a single y line
+    ((5, 1, 1), ([0, 2, 5], [0, 1], [0, 1]), 3, 6),     # a single x line
+    ((3, 2, 2), ([0, 1, 2, 3], [0, 1, 2], [0, 1, 2]), 1, 12),  # every cell its own block
+])
+def test_degenerate_grids(orc, shape, cuts, m, K):
+    """Grids one cell thick and blocks of one cell against the oracle (for
+    1x1x1 blocks one CG step is the point-Jacobi update of Section 2.1)."""
+    rng = np.random.default_rng(107)
+    b = rng.standard_normal(shape)
+    faces = inputs.random_faces(*shape, seed=108)
+    st, xg, xo, hist, inner = _solve_pair(orc, shape, cuts, b, faces, m, K)
+    assert st.status == 0 and st.sweeps == K
+    assert rel(xg, xo) <= TOL_FP64, rel(xg, xo)
+    # A block of c cells has at most c distinct eigenvalues, so CG solves it
+    # exactly in c steps; later steps run on a residual that is zero up to
+    # rounding, and whether they break down (zero) or take a negligible step
+    # (tiny) depends on summation order.  The count is unique only when no
+    # block has fewer cells than m.
+    vols = [(cuts[0][i + 1] - cuts[0][i]) * (cuts[1][j + 1] - cuts[1][j]) *
+            (cuts[2][k + 1] - cuts[2][k]) for i in range(len(cuts[0]) - 1)
+            for j in range(len(cuts[1]) - 1) for k in range(len(cuts[2]) - 1)]
+    slack = K * sum(max(0, m - v) for v in vols)
+    assert abs(st.inner_iters - inner) <= slack, (st.inner_iters, inner, slack)
+    if shape == (1, 1, 1):
+        assert abs(xg[0, 0, 0] - orc.lift_bc(b, faces)[0, 0, 0] / 6.0) <= 1e-15 * abs(xg[0, 0, 0])
+
+
 def test_zero_rhs_gives_zero():
     torch = torch_cuda()
     shape = (16, 16, 16)
