@@ -11,9 +11,12 @@ Prints one JSON line.  `value` is the whole-sweep memory throughput of the
 headline run (synchronous sweeps, mixed precision: FP32 inner CG, FP64
 residual/test/update) in GB/s, from the compulsory bytes per unknown of the
 kernels that make up a sweep (kernel_bytes).  The same line carries the FP64
-and asynchronous sweeps, the global CG baseline, per-kernel event timings,
-the dominant kernel's fraction of the 8 TB/s HBM peak, and the CPU oracle
-timed on this host over a bounded sample of the same workload.  With
+and asynchronous sweeps, the global CG baseline, sweeps on overlapping blocks
+(ovl-*, depth --ovl-depth), sweeps with GMRES inner solves (gmres-*), the
+16-right-hand-side batched workload (batch-*), per-kernel event timings, the
+dominant kernel's fraction of the 8 TB/s HBM peak beside a measured device
+copy, and the CPU oracle timed on this host over a bounded sample of the same
+workload.  With
 --full-solve each mode is also run to the 1e-8 relative residual and timed
 (time-to-tolerance), and the CPU oracle re-checks the final residual.
 
@@ -39,7 +42,8 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2009_12638_amd", "csrc", f)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_bumps512_sync_mixed.json")
 HBM_PEAK_GBPS = 8000.0
 ALL_MODES = ["sync-mixed", "sync-fp64", "async-mixed", "async-fp64", "cg-fp64",
-             "batch-mixed", "batch-fp64", "gmres-mixed", "gmres-fp64"]
+             "batch-mixed", "batch-fp64", "gmres-mixed", "gmres-fp64", "ovl-mixed", "ovl-fp64"]
+DEFAULT_MODES = "sync-mixed,sync-fp64,async-mixed,cg-fp64,ovl-mixed,gmres-mixed,batch-mixed"
 BATCH_WORKLOAD = "uneven384"   # batched modes: 16 right-hand sides, uneven blocks
 
 
@@ -151,7 +155,9 @@ def run_mode(args, torch, ms, w, mode: str, oracle_check):
     b = torch.from_numpy(w["b"]).to("cuda")
     nrhs = b.shape[0] if kind == "batch" else 1
     h = ms.ms_create(shape, cuts=[list(map(int, c)) for c in cuts], faces=None)
-    ov = args.overlap if kind in ("sync", "batch", "gmres") else 0
+    # ovl-*: synchronous sweeps on overlapping blocks of depth --ovl-depth
+    ov = (args.ovl_depth if kind == "ovl" else
+          args.overlap if kind in ("sync", "batch", "gmres") else 0)
     if ov:
         ms.ms_set_overlap(h, ov)
     if kind == "gmres":
@@ -177,7 +183,8 @@ def run_mode(args, torch, ms, w, mode: str, oracle_check):
         if kind == "gmres":
             return ms.ms_solve(h, b, x, 0.0, m, "sync", max_sweeps=k, precision=precision,
                                inner="gmres", **kw)
-        return ms.ms_solve(h, b, x, 0.0, m, kind, max_sweeps=k, precision=precision, **kw)
+        return ms.ms_solve(h, b, x, 0.0, m, "sync" if kind == "ovl" else kind, max_sweeps=k,
+                           precision=precision, **kw)
 
     log(f"{mode}: warmup {args.warmup}")
     if args.warmup > 0:
@@ -209,9 +216,9 @@ def run_mode(args, torch, ms, w, mode: str, oracle_check):
         res["unknown_iters_per_s"] = N * nrhs * m * args.steps / sec
     if kind == "async":
         res["max_staleness_seen"] = st.max_staleness_seen
-    if kind in ("sync", "cg", "batch", "gmres"):
+    if kind in ("sync", "cg", "batch", "gmres", "ovl"):
         prof = step(max(2, min(args.steps, 5)), profile=True)
-        if kind in ("sync", "batch", "gmres"):
+        if kind in ("sync", "batch", "gmres", "ovl"):
             lists = {}
             for name, by in (kernel_bytes_gmres if kind == "gmres" else kernel_bytes)(m, T):
                 lists.setdefault(name, []).append(by)
@@ -240,7 +247,8 @@ def run_mode(args, torch, ms, w, mode: str, oracle_check):
             total = 0
             extra = {"inner": "gmres"} if kind == "gmres" else {}
             while True:
-                fs = ms.ms_solve(h, b, x, w["tol"], m, "sync" if kind == "gmres" else kind,
+                fs = ms.ms_solve(h, b, x, w["tol"], m,
+                                 "sync" if kind in ("gmres", "ovl") else kind,
                                  precision=precision, max_sweeps=args.chunk,
                                  raise_on_error=False, **extra)
                 total += fs.sweeps
@@ -425,7 +433,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="bumps512")
     ap.add_argument("--m", type=int, default=10)
-    ap.add_argument("--modes", default="sync-mixed,sync-fp64,async-mixed,cg-fp64")
+    ap.add_argument("--modes", default=DEFAULT_MODES)
     ap.add_argument("--full-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=4)
@@ -433,7 +441,9 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="batched modes: pick tile shape and m with the autotuner first")
     ap.add_argument("--overlap", type=int, default=0,
-                    help="overlap depth of the blocks in sync and batch modes")
+                    help="overlap depth of the blocks in sync, batch and gmres modes")
+    ap.add_argument("--ovl-depth", type=int, default=2,
+                    help="overlap depth of the ovl-* modes")
     ap.add_argument("--overlap-study", default="",
                     help="comma list of overlap depths: solve the study workload to "
                          "tolerance for each (sync, mixed)")

@@ -640,8 +640,11 @@ ms_status solve_sync(ms_handle *h, const double *b, double *x, int nrhs, double 
                     "last ms_reserve / ms_set_overlap");
     const int vz = std::min(h->vzmax, (int)(16 / sizeof(T)));
     // blocks per launch: cache-sized groups by default (-1: all blocks at
-    // once, > 0: that many blocks)
-    long long cap_cells = kGroupBytes / (4 * (long long)sizeof(T) * nrhs);
+    // once, > 0: that many blocks).  CG keeps four inner vectors per block;
+    // GMRES re-reads its basis at every step, and groups half the CG size
+    // were measured fastest for GMRES(10) at 512^3 (32 blocks of 64^3 in
+    // FP32, 16 in FP64)
+    long long cap_cells = kGroupBytes / ((gmres ? 8 : 4) * (long long)sizeof(T) * nrhs);
     if (o.group_blocks < 0) {
         cap_cells = h->inner_n;
     } else if (o.group_blocks > 0) {
