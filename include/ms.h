@@ -69,8 +69,8 @@ typedef struct {
  * product of per-axis cuts.  gx,gy,gz = blocks per axis.  cuts_x is a HOST
  * array of gx+1 increasing offsets 0 = c[0] < ... < c[gx] = nx (likewise y,
  * z); NULL means a uniform split, which requires nx % gx == 0.  Block
- * edges may be any size >= 1 (kernels use 16-byte accesses when nz and every
- * z cut are multiples of 4, or 2); block (bi,bj,bk) has number
+ * edges may be any size >= 1 (kernels use wider z accesses when nz and every
+ * z cut are multiples of 8, 4 or 2); block (bi,bj,bk) has number
  * (bi*gy + bj)*gz + bk. */
 typedef struct {
     int32_t gx, gy, gz;
@@ -107,6 +107,10 @@ typedef struct {
                              at a time (0 = automatic) */
     int32_t inner_solver; /* ms_inner (default MS_INNER_CG).  MS_INNER_GMRES:
                              sync only, needs ms_reserve_krylov */
+    int32_t z_vector;     /* sync: z cells each thread accesses at once, 1, 2, 4
+                             or 8 (0 = automatic: 16 bytes; at most 32 bytes,
+                             16 with GMRES, 4 cells with overlap; nz and every
+                             z cut must be multiples of it) */
 } ms_opts;
 
 /* Kernel classes reported by the profile counters of ms_stats. */

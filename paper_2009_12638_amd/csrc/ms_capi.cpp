@@ -53,8 +53,8 @@ struct ms_handle {
     long long nx = 0, ny = 0, nz = 0, N = 0;
     int gx = 0, gy = 0, gz = 0, nblocks = 0;
     std::vector<int> cx, cy, cz;
-    int vzmax = 1;              // widest vector the z cuts and nz allow
-    int vzbase = 1;             // ... and the width overlap boxes are aligned to in z
+    int vzmax = 1;              // widest z vector (cells) the z cuts and nz allow, <= 8
+    int vzbase = 1;             // min(vzmax, 4): the width overlap boxes are aligned to in z
     int overlap = 0;            // block overlap depth (0: plain block Jacobi)
     long long inner_n = 0;      // inner-vector elements per right-hand side
     long long inner_cap = 0;    // ... that the inner buffers hold (>= inner_n)
@@ -638,7 +638,20 @@ ms_status solve_sync(ms_handle *h, const double *b, double *x, int nrhs, double 
         return fail(h, MS_ERR_ARG,
                     "GMRES inner solves need ms_reserve_krylov(h, >= inner_iters) after the "
                     "last ms_reserve / ms_set_overlap");
-    const int vz = std::min(h->vzmax, (int)(16 / sizeof(T)));
+    // z cells per thread access: 16 bytes of the inner type by default; up
+    // to 32 bytes on request (a wavefront then spans more y rows, but the
+    // FP64 x and b accesses of the residual and final kernels double too:
+    // measured slower at 512^3).  GMRES kernels take at most 16 bytes;
+    // overlap boxes are aligned to vzbase.
+    int vzlim = std::min(h->vzmax, (int)((gmres ? 16 : 32) / sizeof(T)));
+    if (h->overlap > 0) vzlim = std::min(vzlim, h->vzbase);
+    int vz = std::min(vzlim, (int)(16 / sizeof(T)));
+    if (o.z_vector > 0) {
+        if ((o.z_vector & (o.z_vector - 1)) || o.z_vector > vzlim)
+            return fail(h, MS_ERR_ARG, "z_vector must be a power of two the z cuts, nz, the "
+                                       "precision and the inner solver allow");
+        vz = o.z_vector;
+    }
     // blocks per launch: cache-sized groups by default (-1: all blocks at
     // once, > 0: that many blocks).  CG keeps four inner vectors per block;
     // GMRES re-reads its basis at every step, and groups half the CG size
@@ -1077,6 +1090,7 @@ void ms_default_opts(ms_opts *o) {
     o->rows = 0;
     o->workers = 0;
     o->inner_solver = MS_INNER_CG;
+    o->z_vector = 0;
 }
 
 const char *ms_status_string(ms_status s) {
@@ -1136,12 +1150,12 @@ ms_status ms_create(const ms_grid *grid, const ms_blocks *blocks, const ms_bc *b
     tmp.nblocks = tmp.gx * tmp.gy * tmp.gz;
     // vector width: every z cut and nz divisible
     tmp.vzmax = 1;
-    for (int w : {4, 2}) {
+    for (int w : {8, 4, 2}) {
         bool ok = tmp.nz % w == 0;
         for (int c : tmp.cz) ok = ok && (c % w == 0);
         if (ok) { tmp.vzmax = w; break; }
     }
-    tmp.vzbase = tmp.vzmax;
+    tmp.vzbase = std::min(tmp.vzmax, 4);
     tmp.inner_n = tmp.inner_cap = tmp.N;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -1258,6 +1272,7 @@ static ms_status check_solve(ms_handle *h, const double *b, double *x, long long
         return fail(h, MS_ERR_ARG, "unknown precision");
     if (o.inner_solver != MS_INNER_CG && o.inner_solver != MS_INNER_GMRES)
         return fail(h, MS_ERR_ARG, "unknown inner solver");
+    if (o.z_vector < 0) return fail(h, MS_ERR_ARG, "z_vector must be >= 0");
     return MS_OK;
 }
 

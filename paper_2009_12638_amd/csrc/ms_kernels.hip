@@ -893,7 +893,18 @@ __global__ __launch_bounds__(kThreads) void k_apply(long long nx, long long ny, 
         __VA_ARGS__;                                                  \
         break;                                                        \
     }
+// Synchronous phase kernels: z vectors of 1, 2, 4 or 8 cells (up to 32
+// bytes per thread and row, split into 16-byte accesses).
 #define MS_DISPATCH(vz, rows, ...)                                    \
+    switch ((vz) * 8 + (rows)) {                                      \
+        MS_CASE(1, 1, __VA_ARGS__) MS_CASE(1, 2, __VA_ARGS__) MS_CASE(1, 4, __VA_ARGS__) \
+        MS_CASE(2, 1, __VA_ARGS__) MS_CASE(2, 2, __VA_ARGS__) MS_CASE(2, 4, __VA_ARGS__) \
+        MS_CASE(4, 1, __VA_ARGS__) MS_CASE(4, 2, __VA_ARGS__) MS_CASE(4, 4, __VA_ARGS__) \
+        MS_CASE(8, 1, __VA_ARGS__) MS_CASE(8, 2, __VA_ARGS__) MS_CASE(8, 4, __VA_ARGS__) \
+        default: return hipErrorInvalidValue;                         \
+    }
+// The persistent asynchronous kernel: up to 4 cells.
+#define MS_DISPATCH_A(vz, rows, ...)                                  \
     switch ((vz) * 8 + (rows)) {                                      \
         MS_CASE(1, 1, __VA_ARGS__) MS_CASE(1, 2, __VA_ARGS__) MS_CASE(1, 4, __VA_ARGS__) \
         MS_CASE(2, 1, __VA_ARGS__) MS_CASE(2, 2, __VA_ARGS__) MS_CASE(2, 4, __VA_ARGS__) \
@@ -973,7 +984,7 @@ hipError_t launch_async(const Geom &g, int vz, int grid, const double *b, double
                         T *r, T *p0, T *p1, T *d, AsyncState as, int m, int S, int max_sweeps,
                         double tol2, double inner_tol, Ctrl *ctrl, hipStream_t st) {
     if (grid < 1) return hipErrorInvalidValue;
-    MS_DISPATCH(vz, g.rows, hipLaunchKernelGGL((k_async<T, VZ, RR>), dim3(grid),
+    MS_DISPATCH_A(vz, g.rows, hipLaunchKernelGGL((k_async<T, VZ, RR>), dim3(grid),
                                                dim3(kAsyncThreads), 0, st, g, b, x, faces, r,
                                                p0, p1, d, as, m, S, max_sweeps, tol2, inner_tol,
                                                ctrl));
@@ -983,7 +994,7 @@ hipError_t launch_async(const Geom &g, int vz, int grid, const double *b, double
 template <typename T>
 hipError_t async_occupancy(int vz, int rows, int *per_cu) {
     *per_cu = 0;
-    MS_DISPATCH(vz, rows, return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+    MS_DISPATCH_A(vz, rows, return hipOccupancyMaxActiveBlocksPerMultiprocessor(
                               per_cu, (const void *)k_async<T, VZ, RR>, kAsyncThreads, 0));
     return hipSuccess;
 }

@@ -50,7 +50,7 @@ class ms_opts(C.Structure):
                 ("stream", C.c_void_p), ("check_every", C.c_int32),
                 ("group_blocks", C.c_int32), ("x_chunk", C.c_int32),
                 ("profile", C.c_int32), ("use_graph", C.c_int32), ("rows", C.c_int32),
-                ("workers", C.c_int32), ("inner_solver", C.c_int32)]
+                ("workers", C.c_int32), ("inner_solver", C.c_int32), ("z_vector", C.c_int32)]
 
 
 class ms_stats(C.Structure):
@@ -253,7 +253,7 @@ class Stats:
 
 def _opts(precision="fp64", max_sweeps=100000, inner_tol=0.0, staleness=2, stream=None,
           check_every=0, group_blocks=0, x_chunk=0, profile=False, use_graph=True,
-          rows=0, workers=0, inner="cg") -> ms_opts:
+          rows=0, workers=0, inner="cg", z_vector=0) -> ms_opts:
     o = ms_default_opts()
     o.max_sweeps = int(max_sweeps)
     o.inner_tol = float(inner_tol)
@@ -270,6 +270,7 @@ def _opts(precision="fp64", max_sweeps=100000, inner_tol=0.0, staleness=2, strea
     o.workers = int(workers)
     o.inner_solver = {"cg": MS_INNER_CG, "gmres": MS_INNER_GMRES}[inner] \
         if isinstance(inner, str) else int(inner)
+    o.z_vector = int(z_vector)
     return o
 
 

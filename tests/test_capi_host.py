@@ -39,8 +39,8 @@ def test_struct_sizes_match_c_layout():
     assert C.sizeof(ms.ms_blocks) == 12 + 4 + 24
     assert C.sizeof(ms.ms_bc) == 48
     # max_sweeps, pad, inner_tol, staleness, precision, stream, five int32
-    # options, rows, workers, inner_solver
-    assert C.sizeof(ms.ms_opts) == 4 + 4 + 8 + 4 + 4 + 8 + 4 * 5 + 4 + 4 + 4
+    # options, rows, workers, inner_solver, z_vector, tail padding to 8
+    assert C.sizeof(ms.ms_opts) == 4 + 4 + 8 + 4 + 4 + 8 + 4 * 5 + 4 + 4 + 4 + 4 + 4
     assert C.sizeof(ms.ms_stats) == 4 + 4 + 8 + 8 + 8 + 4 + 4 + 4 + 4 + 8 + 4 + 4 + 64 + 64
 
 

@@ -334,3 +334,39 @@ def test_graph_replay_equals_eager(precision):
         ms.ms_apply(h, xg, y)
         other = "mixed" if precision == "fp64" else "fp64"
         ms.ms_solve(h, b, torch.zeros_like(xg), 0.0, 3, "sync", max_sweeps=2, precision=other)
+
+
+@pytest.mark.parametrize("precision,widths", [("fp64", [1, 2, 4]), ("mixed", [1, 2, 4, 8])])
+def test_z_vector_widths(orc, precision, widths):
+    """Every z access width gives the oracle's iterate (FP64: to 1e-10;
+    mixed: the same answer at tol), and widths the grid or precision do not
+    allow are refused."""
+    torch = torch_cuda()
+    shape, cuts = (32, 24, 48), ([0, 8, 16, 32], [0, 12, 24], [0, 16, 32, 48])
+    rng = np.random.default_rng(109)
+    b = rng.standard_normal(shape) / 100
+    faces = inputs.random_faces(*shape, seed=110)
+    beff = orc.lift_bc(b, faces)
+    h, _ = make(ms, shape, cuts, faces)
+    if precision == "fp64":
+        _, xo, _, _, _ = orc.block_jacobi(beff, np.zeros(shape), cuts, tol=0.0, m=6, max_sweeps=9)
+    else:
+        _, xo, _, _, _ = orc.block_jacobi(beff, np.zeros(shape), cuts, tol=1e-8, m=6)
+    for vz in widths:
+        x = torch.zeros(shape, dtype=torch.float64, device="cuda")
+        say("z vector", precision, vz)
+        if precision == "fp64":
+            ms.ms_solve(h, dev(b), x, 0.0, 6, "sync", max_sweeps=9, z_vector=vz)
+            assert rel(host(x), xo) <= TOL_FP64, (vz, rel(host(x), xo))
+        else:
+            st = ms.ms_solve(h, dev(b), x, 1e-8, 6, "sync", precision="mixed", z_vector=vz)
+            assert st.rel_residual <= 1e-8
+            assert rel(host(x), xo) <= TOL_MIXED, (vz, rel(host(x), xo))
+    x = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    bad = [3, 16] + ([8] if precision == "fp64" else [])
+    for vz in bad:
+        with pytest.raises(ms.MsError) as e:
+            ms.ms_solve(h, dev(b), x, 0.0, 6, "sync", max_sweeps=1, precision=precision,
+                        z_vector=vz)
+        assert e.value.status == ms.MS_ERR_ARG
+    ms.ms_destroy(h)
