@@ -171,8 +171,11 @@ ms_status ms_set_bc(ms_handle *h, const ms_bc *bc);
  * the correction of the block that owns it (D_i = indicator of block i's
  * own cells).  The global residual counts each cell once.  o = 0 restores
  * plain block Jacobi.
- * Applies to later ms_solve (MS_SYNC only; MS_ASYNC returns
- * MS_ERR_UNSUPPORTED while o > 0) and ms_solve_batch calls.  Allocates when
+ * Applies to later ms_solve (sync and async) and ms_solve_batch calls.  In
+ * async mode the overlap values, like the halo, are whatever the neighbours
+ * last wrote; the staleness bound applies to face neighbours, and cells of
+ * the region's halo in edge-adjacent blocks (two face steps away) are at
+ * most twice as stale.  Allocates when
  * the regions need larger inner buffers than the handle holds (never
  * shrinks them).  The inner box of a block is grown in z by o rounded up
  * to the vector width (the cells beyond depth o are masked), so z accesses

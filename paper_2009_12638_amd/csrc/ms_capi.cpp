@@ -832,8 +832,6 @@ ms_status solve_async(ms_handle *h, const double *b, double *x, double tol, int 
                       const ms_opts &o, ms_stats *stats, hipStream_t st) {
     if (o.staleness < 1)
         return fail(h, MS_ERR_ARG, "asynchronous mode needs staleness >= 1");
-    if (h->overlap > 0)
-        return fail(h, MS_ERR_UNSUPPORTED, "overlapping blocks are synchronous only");
     if (o.inner_solver != MS_INNER_CG)
         return fail(h, MS_ERR_UNSUPPORTED, "GMRES inner solves are synchronous only");
     const int vz = std::min(h->vzmax, (int)(16 / sizeof(T)));
@@ -854,7 +852,7 @@ ms_status solve_async(ms_handle *h, const double *b, double *x, double tol, int 
         return MS_OK;
     }
     int per_cu = 0;
-    HIPCHK(h, ms::async_occupancy<T>(vz, rows, &per_cu));
+    HIPCHK(h, ms::async_occupancy<T>(vz, rows, h->overlap > 0 ? 1 : 0, &per_cu));
     if (per_cu < 1) return fail(h, MS_ERR_HIP, "asynchronous kernel cannot be resident");
     int grid = (int)std::min<long long>(h->nblocks, (long long)per_cu * h->num_cu);
     if (o.workers > 0) grid = std::min(grid, o.workers);

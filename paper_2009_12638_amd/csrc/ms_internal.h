@@ -136,7 +136,7 @@ hipError_t launch_async(const Geom &g, int vz, int grid, const double *b, double
                         T *r, T *p0, T *p1, T *d, AsyncState as, int m, int S, int max_sweeps,
                         double tol2, double inner_tol, Ctrl *ctrl, hipStream_t st);
 template <typename T>
-hipError_t async_occupancy(int vz, int rows, int *per_cu);
+hipError_t async_occupancy(int vz, int rows, int ovl, int *per_cu);
 
 // Global CG on the single-block geometry g (device scalars scal[3]).
 hipError_t launch_gcg_stencil(const Geom &g, int vz, int ntiles, const double *r,

@@ -656,7 +656,7 @@ __global__ __launch_bounds__(kThreads) void k_gcg_reduce(const double *__restric
 
 constexpr int kSub = kAsyncThreads / kThreads;
 
-template <typename T, int VZ, int R>
+template <typename T, int VZ, int R, bool OVL>
 __global__ __launch_bounds__(kAsyncThreads) void k_async(Geom g, const double *__restrict__ b,
                                                          double *x, Faces F, T *r, T *p0,
                                                          T *p1, T *d, AsyncState as, int m,
@@ -742,7 +742,7 @@ __global__ __launch_bounds__(kAsyncThreads) void k_async(Geom g, const double *_
         T accT = T(0);
         for (int lt = sub; lt < B.ntiles; lt += kSub) {
             const Tile t = decode_tile<VZ, R>(g, B.tile0 + lt, ltid);
-            tile_resid<T, VZ, R, true>(g, t, 0, b, x, F, r, acc64, accT);
+            tile_resid<T, VZ, R, true, OVL>(g, t, 0, b, x, F, r, acc64, accT);
         }
         const double res2 = wg_allsum<double, kAsyncThreads>(acc64);
         T rho = wg_allsum<T, kAsyncThreads>(accT);
@@ -766,7 +766,7 @@ __global__ __launch_bounds__(kAsyncThreads) void k_async(Geom g, const double *_
                 if (j == m - 1) {
                     for (int lt = sub; lt < B.ntiles; lt += kSub) {
                         const Tile t = decode_tile<VZ, R>(g, B.tile0 + lt, ltid);
-                        tile_final<T, VZ, R>(g, t, 0, pnew, d, alpha, j > 0, true, x, x);
+                        tile_final<T, VZ, R, OVL>(g, t, 0, pnew, d, alpha, j > 0, true, x, x);
                     }
                     applied = true;
                     iters = m;
@@ -775,7 +775,7 @@ __global__ __launch_bounds__(kAsyncThreads) void k_async(Geom g, const double *_
                 acc = T(0);
                 for (int lt = sub; lt < B.ntiles; lt += kSub) {
                     const Tile t = decode_tile<VZ, R>(g, B.tile0 + lt, ltid);
-                    acc += tile_update<T, T, VZ, R>(t, 0, r, pnew, d, alpha, j > 0);
+                    acc += tile_update<T, T, VZ, R, OVL>(t, 0, r, pnew, d, alpha, j > 0);
                 }
                 const T rho_new = wg_allsum<T, kAsyncThreads>(acc);
                 iters = j + 1;
@@ -787,7 +787,7 @@ __global__ __launch_bounds__(kAsyncThreads) void k_async(Geom g, const double *_
         if (!applied && iters > 0) {
             for (int lt = sub; lt < B.ntiles; lt += kSub) {
                 const Tile t = decode_tile<VZ, R>(g, B.tile0 + lt, ltid);
-                tile_final<T, VZ, R>(g, t, 0, (const T *)nullptr, d, T(0), true, false, x, x);
+                tile_final<T, VZ, R, OVL>(g, t, 0, (const T *)nullptr, d, T(0), true, false, x, x);
             }
         }
         // ---- publish: x of this block, then its version ----
@@ -984,18 +984,30 @@ hipError_t launch_async(const Geom &g, int vz, int grid, const double *b, double
                         T *r, T *p0, T *p1, T *d, AsyncState as, int m, int S, int max_sweeps,
                         double tol2, double inner_tol, Ctrl *ctrl, hipStream_t st) {
     if (grid < 1) return hipErrorInvalidValue;
-    MS_DISPATCH_A(vz, g.rows, hipLaunchKernelGGL((k_async<T, VZ, RR>), dim3(grid),
-                                               dim3(kAsyncThreads), 0, st, g, b, x, faces, r,
-                                               p0, p1, d, as, m, S, max_sweeps, tol2, inner_tol,
-                                               ctrl));
+    if (g.ovl) {
+        MS_DISPATCH_A(vz, g.rows, hipLaunchKernelGGL((k_async<T, VZ, RR, true>), dim3(grid),
+                                                     dim3(kAsyncThreads), 0, st, g, b, x, faces,
+                                                     r, p0, p1, d, as, m, S, max_sweeps, tol2,
+                                                     inner_tol, ctrl));
+    } else {
+        MS_DISPATCH_A(vz, g.rows, hipLaunchKernelGGL((k_async<T, VZ, RR, false>), dim3(grid),
+                                                     dim3(kAsyncThreads), 0, st, g, b, x, faces,
+                                                     r, p0, p1, d, as, m, S, max_sweeps, tol2,
+                                                     inner_tol, ctrl));
+    }
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t async_occupancy(int vz, int rows, int *per_cu) {
+hipError_t async_occupancy(int vz, int rows, int ovl, int *per_cu) {
     *per_cu = 0;
-    MS_DISPATCH_A(vz, rows, return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                              per_cu, (const void *)k_async<T, VZ, RR>, kAsyncThreads, 0));
+    if (ovl) {
+        MS_DISPATCH_A(vz, rows, return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                  per_cu, (const void *)k_async<T, VZ, RR, true>, kAsyncThreads, 0));
+    } else {
+        MS_DISPATCH_A(vz, rows, return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                  per_cu, (const void *)k_async<T, VZ, RR, false>, kAsyncThreads, 0));
+    }
     return hipSuccess;
 }
 
@@ -1068,7 +1080,7 @@ hipError_t launch_apply(long long nx, long long ny, long long nz, const double *
     template hipError_t launch_async<T>(const Geom &, int, int, const double *, double *,     \
                                         Faces, T *, T *, T *, T *, AsyncState, int, int, int, \
                                         double, double, Ctrl *, hipStream_t);                 \
-    template hipError_t async_occupancy<T>(int, int, int *);
+    template hipError_t async_occupancy<T>(int, int, int, int *);
 MS_INST(double)
 MS_INST(float)
 

@@ -35,6 +35,8 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2009_1263
                              "tune.json")
 TILE_CANDIDATES = [(r, t) for r in (1, 2, 4) for t in (8, 16, 32)]
 INNER_CANDIDATES = (5, 10, 20, 40)
+OVERLAP_CANDIDATES = (0, 2, 4, 6)
+OVERLAP_INNER_CANDIDATES = (10, 20, 30)
 
 
 def problem_key(shape, cuts, precision, nrhs=1) -> str:
@@ -102,6 +104,45 @@ def tune_inner(h, b, precision="mixed", candidates=INNER_CANDIDATES, warm_res=0.
         drop = min(math.log10(hh[0] / max(hh[-1], 1e-300)) for hh in hists)
         results.append(dict(m=m, sweeps=sweeps, seconds=sec, decades_per_s=drop / sec))
     best = max(results, key=lambda r: r["decades_per_s"])
+    return best, results
+
+
+def tune_overlap_inner(h, b, precision="mixed", overlaps=OVERLAP_CANDIDATES,
+                       inners=OVERLAP_INNER_CANDIDATES, warm_res=1e-3, budget_s=0.4,
+                       warm_max=5000):
+    """(overlap depth, m) pair with the largest log10 residual reduction per
+    second of synchronous sweeps (the paper tunes the overlap and the inner
+    iterations by hand, Section 3.2).  Every pair starts from the same
+    iterate (the first one with residual <= warm_res, without overlap, m =
+    10), past the fast initial drop, and runs for about budget_s.  Leaves
+    the handle at the best overlap."""
+    x0 = torch.zeros_like(b)
+    ms.ms_set_overlap(h, 0)
+    ms.ms_solve(h, b, x0, warm_res, 10, "sync", raise_on_error=False, max_sweeps=warm_max,
+                precision=precision)
+    results = []
+    for ov in overlaps:
+        ms.ms_set_overlap(h, ov)
+        for m in inners:
+            x = x0.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ms.ms_solve(h, b, x.clone(), 0.0, m, "sync", max_sweeps=1, precision=precision)
+            torch.cuda.synchronize()
+            per = max(time.perf_counter() - t0, 1e-5)
+            sweeps = max(4, int(budget_s / per))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s = ms.ms_solve(h, b, x, 0.0, m, "sync", max_sweeps=sweeps, history=sweeps + 1,
+                            precision=precision)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            hh = s.history
+            drop = math.log10(hh[0] / max(hh[-1], 1e-300))
+            results.append(dict(overlap=ov, m=m, sweeps=sweeps, seconds=sec,
+                                decades_per_s=drop / sec))
+    best = max(results, key=lambda r: r["decades_per_s"])
+    ms.ms_set_overlap(h, best["overlap"])
     return best, results
 
 
