@@ -105,8 +105,8 @@ typedef struct {
     int32_t rows;         /* y rows each thread owns: 1, 2 or 4 (0 = automatic) */
     int32_t workers;      /* async: persistent workgroups, each sweeping one block
                              at a time (0 = automatic) */
-    int32_t inner_solver; /* ms_inner (default MS_INNER_CG).  MS_INNER_GMRES:
-                             sync only, needs ms_reserve_krylov */
+    int32_t inner_solver; /* ms_inner (default MS_INNER_CG).  MS_INNER_GMRES
+                             needs ms_reserve_krylov */
     int32_t z_vector;     /* sync: z cells each thread accesses at once, 1, 2, 4
                              or 8 (0 = automatic: 16 bytes; at most 32 bytes,
                              16 with GMRES, 4 cells with overlap; nz and every
@@ -226,7 +226,8 @@ ms_status ms_reserve(ms_handle *h, int32_t nrhs);
  * minimises the block residual over the Krylov space (Givens rotations of
  * the Hessenberg matrix), early stop when that least-squares residual is
  * <= inner_tol * ||r_i|| or the space becomes invariant.  Works with
- * overlap and with several right-hand sides; synchronous mode only.
+ * overlap, with several right-hand sides (synchronous) and in asynchronous
+ * mode (each worker runs the whole cycle of the block it took).
  * This call allocates the m+1 basis vectors and per-block state for
  * inner_iters up to max_inner (1..128) for the handle's current right-hand
  * side capacity and overlap; call it again after ms_reserve or

@@ -832,13 +832,21 @@ ms_status solve_async(ms_handle *h, const double *b, double *x, double tol, int 
                       const ms_opts &o, ms_stats *stats, hipStream_t st) {
     if (o.staleness < 1)
         return fail(h, MS_ERR_ARG, "asynchronous mode needs staleness >= 1");
-    if (o.inner_solver != MS_INNER_CG)
-        return fail(h, MS_ERR_UNSUPPORTED, "GMRES inner solves are synchronous only");
+    const bool gmres = o.inner_solver == MS_INNER_GMRES;
+    if (gmres && (m > h->kry_M || h->kry_rhs < 1 || h->inner_n > h->kry_inner ||
+                  h->tiles_cap > h->kry_tiles))
+        return fail(h, MS_ERR_ARG,
+                    "GMRES inner solves need ms_reserve_krylov(h, >= inner_iters) after the "
+                    "last ms_reserve / ms_set_overlap");
     const int vz = std::min(h->vzmax, (int)(16 / sizeof(T)));
     int tx = 0, rows = 0;
     auto_tiling(h, vz, 1, 0, h->nblocks, &tx, &rows);
     if (o.x_chunk > 0) tx = std::max(kTxMin, o.x_chunk);
     if (o.rows == 1 || o.rows == 2 || o.rows == 4) rows = o.rows;
+    if (gmres) {   // GMRES tiles: one row per thread, at most gm_max_planes() planes
+        rows = 1;
+        tx = std::min(tx, ms::gm_max_planes());
+    }
     ms_status s = set_tiling(h, vz, tx, rows, st);
     if (s != MS_OK) return s;
     double nbeff = 0.0, absres = 0.0;
@@ -852,7 +860,10 @@ ms_status solve_async(ms_handle *h, const double *b, double *x, double tol, int 
         return MS_OK;
     }
     int per_cu = 0;
-    HIPCHK(h, ms::async_occupancy<T>(vz, rows, h->overlap > 0 ? 1 : 0, &per_cu));
+    if (gmres)
+        HIPCHK(h, ms::async_gmres_occupancy<T>(vz, h->overlap > 0 ? 1 : 0, &per_cu));
+    else
+        HIPCHK(h, ms::async_occupancy<T>(vz, rows, h->overlap > 0 ? 1 : 0, &per_cu));
     if (per_cu < 1) return fail(h, MS_ERR_HIP, "asynchronous kernel cannot be resident");
     int grid = (int)std::min<long long>(h->nblocks, (long long)per_cu * h->num_cu);
     if (o.workers > 0) grid = std::min(grid, o.workers);
@@ -909,9 +920,14 @@ ms_status solve_async(ms_handle *h, const double *b, double *x, double tol, int 
         first = false;
         {
             Prof p(h, st, MS_K_OTHER);
-            HIPCHK(h, ms::launch_async<T>(geom(h), vz, grid, b, x, faces(h), B.r, B.p[0], B.p[1],
-                                          B.d, as, m, o.staleness, limit, tol2, o.inner_tol,
-                                          h->ctrl, st));
+            if (gmres)
+                HIPCHK(h, ms::launch_async_gmres<T>(geom(h), vz, grid, b, x, faces(h), (T *)h->V,
+                                                    as, m, o.staleness, limit, tol2, o.inner_tol,
+                                                    gm_args(h), h->ctrl, st));
+            else
+                HIPCHK(h, ms::launch_async<T>(geom(h), vz, grid, b, x, faces(h), B.r, B.p[0],
+                                              B.p[1], B.d, as, m, o.staleness, limit, tol2,
+                                              o.inner_tol, h->ctrl, st));
         }
         HIPCHK(h, hipMemcpyAsync(ver.data(), h->version_d, sizeof(int) * nbk,
                                  hipMemcpyDeviceToHost, st));

@@ -146,4 +146,118 @@ __device__ __forceinline__ int axes_out(const BlockInfo &B, int i, int j, int k)
            ((unsigned)(k - B.ok) >= (unsigned)B.obz) + 2 * zfar;
 }
 
+
+// ---- asynchronous sweeps: choosing and publishing blocks ---------------
+// (shared by the CG and GMRES workers; every thread of the workgroup calls
+// these)
+
+struct AsyncShared {
+    int blk;
+    int gap;
+    unsigned long long key[kAsyncThreads / 64];
+};
+
+// The eligible unclaimed block with the lowest version (every neighbour at
+// least version + 1 - S), claimed by compare-and-swap; the neighbours'
+// published x values are acquired.  Returns the block, -1 when nothing is
+// eligible right now, -2 once the worker should exit (stop flag, or every
+// block reached the launch's sweep limit).  sh.gap: the largest version gap
+// to a neighbour this sweep will see.
+__device__ __forceinline__ int async_claim(const Geom &g, AsyncState as, int S, int max_sweeps,
+                                           Ctrl *ctrl, AsyncShared &sh) {
+    const int tid = threadIdx.x;
+    const int nb = g.nblocks;
+    // ---- the eligible unclaimed block with the lowest version ----
+    unsigned long long best = ~0ull;
+    for (int c = tid; c < nb; c += kAsyncThreads) {
+        const int blk = (c + (int)blockIdx.x * 7) % nb;   // spread the start per worker
+        if (__hip_atomic_load(&as.claim[blk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) continue;
+        const int v = __hip_atomic_load(&as.version[blk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (v >= max_sweeps) continue;
+        bool ok = true;
+        for (int f = 0; f < 6 && ok; f++) {
+            const int nbk = as.nbr[blk * 6 + f];
+            if (nbk < 0) continue;
+            const int vn = __hip_atomic_load(&as.version[nbk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok = vn >= v + 1 - S;
+        }
+        if (!ok) continue;
+        const unsigned long long key = ((unsigned long long)(unsigned)v << 32) | (unsigned)blk;
+        best = key < best ? key : best;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long other = __shfl_xor(best, o, 64);
+        best = other < best ? other : best;
+    }
+    if ((tid & 63) == 0) sh.key[tid >> 6] = best;
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long k = ~0ull;
+        for (int w = 0; w < kAsyncThreads / 64; w++) k = sh.key[w] < k ? sh.key[w] : k;
+        int pick = -1;
+        if (__hip_atomic_load(&ctrl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+            k = ~0ull;       // the residual estimate is below tol: start nothing new
+        }
+        if (k != ~0ull) {
+            const int cand = (int)(k & 0xffffffffu);
+            int zero = 0;
+            if (__hip_atomic_compare_exchange_strong(&as.claim[cand], &zero, 1, __ATOMIC_ACQUIRE,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                pick = cand;
+        }
+        if (pick < 0) {
+            const bool stop = __hip_atomic_load(&ctrl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+            const int fin = __hip_atomic_load(as.finished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (stop || fin >= nb) pick = -2;
+        } else {
+            // staleness this sweep will see, then acquire the neighbours'
+            // published x values
+            const int v = __hip_atomic_load(&as.version[pick], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            int gap = 0;
+            for (int f = 0; f < 6; f++) {
+                const int nbk = as.nbr[pick * 6 + f];
+                if (nbk < 0) continue;
+                const int vn = __hip_atomic_load(&as.version[nbk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                gap = max(gap, v - vn);
+            }
+            sh.gap = gap;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        sh.blk = pick;
+    }
+    __syncthreads();
+    const int blk = sh.blk;
+    __syncthreads();
+    return blk;
+}
+
+// After a block's sweep: release its new x, then publish version + 1, the
+// inner iterations and the residual estimate (Section 3: an estimate that
+// may be some sweeps old) from the latest published block residuals.
+__device__ __forceinline__ void async_publish(AsyncState as, int blk, int max_sweeps, int iters,
+                                              double tol2, Ctrl *ctrl, const AsyncShared &sh,
+                                              int nb) {
+    const int tid = threadIdx.x;
+    // ---- publish: x of this block, then its version ----
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (tid == 0) {
+        const int v = __hip_atomic_load(&as.version[blk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+        __hip_atomic_store(&as.version[blk], v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&as.claim[blk], 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (v >= max_sweeps) atomicAdd(as.finished, 1);
+        atomicAdd(&ctrl->inner_iters, (unsigned long long)iters);
+        atomicAdd(&ctrl->work_items, 1ull);
+        atomicMax(&ctrl->max_stale, sh.gap);
+        if (tol2 > 0.0) {
+            // residual estimate from the latest published block residuals
+            // (Section 3: an estimate that may be some sweeps old)
+            double est = 0.0;
+            for (int q = 0; q < nb; q++)
+                est += __hip_atomic_load(&as.board[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (est <= tol2) __hip_atomic_store(&ctrl->stop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
 }  // namespace ms

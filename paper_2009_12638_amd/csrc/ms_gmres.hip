@@ -23,6 +23,7 @@
 // partials are in the inner type T (FP32 in mixed precision).
 #include "ms_internal.h"
 #include "ms_device.h"
+#include "ms_tiles.h"
 
 #include <math.h>
 
@@ -32,6 +33,8 @@ namespace {
 
 // x planes one workgroup marches (the tile's w values stay in registers)
 constexpr int kGmPlanes = 8;
+// most inner steps a basis may hold (ms_reserve_krylov's limit)
+constexpr int kGmMaxSteps = 128;
 
 // Fields of one (right-hand side, block) GMRES record, in doubles.
 struct GmRec {
@@ -142,6 +145,189 @@ __device__ __forceinline__ void tile_gm_apply(const Tile &t, long long goff,
     }
 }
 
+// Tile partials of (w, u_i), i = 0..j, from the w values of one tile (wv),
+// reduced over the NT threads of the workgroup kDotBatch dots at a time.
+// Thread c < kDotBatch then stores (ADD: adds) dot i0 + c to out[i0 + c].
+// Threads of an idle tile (live = false) contribute zeros but take part.
+template <typename T, int VZ, int NT, bool ADD, typename O>
+__device__ __forceinline__ void gm_dots(const Tile &t, bool live, long long goff, const T *V,
+                                        long long kvs, long long ko, int j,
+                                        const T (&wv)[kGmPlanes][VZ], T (*sh)[kDotBatch],
+                                        O *out) {
+    const int bz = t.B.bz;
+    const long long P = (long long)t.B.by * bz;
+    const long long base = (t.B.off - goff) + (long long)t.j0 * bz + t.k;
+    for (int i0 = 0; i0 <= j; i0 += kDotBatch) {
+        T acc[kDotBatch];
+#pragma unroll
+        for (int c = 0; c < kDotBatch; c++) acc[c] = T(0);
+        if (live && t.nrows > 0) {
+#pragma unroll
+            for (int c = 0; c < kDotBatch; c++) {
+                if (i0 + c > j) continue;
+                const T *ui = V + (long long)(i0 + c) * kvs + ko + base;
+#pragma unroll
+                for (int q = 0; q < kGmPlanes; q++) {
+                    if (t.xbeg + q >= t.xend) continue;
+                    T uv[VZ];
+                    vload<T, VZ>(ui + (long long)(t.xbeg + q) * P, uv);
+#pragma unroll
+                    for (int v = 0; v < VZ; v++) acc[c] += wv[q][v] * uv[v];
+                }
+            }
+        }
+        // lanes by butterfly, then the wavefronts in order
+#pragma unroll
+        for (int c = 0; c < kDotBatch; c++) {
+            const T sv = wave_sum(acc[c]);
+            if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6][c] = sv;
+        }
+        __syncthreads();
+        if (threadIdx.x < kDotBatch && i0 + (int)threadIdx.x <= j) {
+            T sv = T(0);
+#pragma unroll
+            for (int w = 0; w < NT / 64; w++) sv += sh[w][threadIdx.x];
+            if (ADD) out[i0 + threadIdx.x] += (O)sv;
+            else out[i0 + threadIdx.x] = (O)sv;
+        }
+        __syncthreads();
+    }
+}
+
+// u_{j+1} = w - sum_i coef[i] u_i on one tile; returns the thread's part of
+// ||u_{j+1}||^2.
+template <typename T, int VZ>
+__device__ __forceinline__ T tile_gm_orth(const Tile &t, long long goff, T *V, long long kvs,
+                                          long long ko, int j, const double *coef) {
+    T *un = V + (long long)(j + 1) * kvs + ko;
+    const int bz = t.B.bz;
+    const long long P = (long long)t.B.by * bz;
+    const long long base = (t.B.off - goff) + (long long)t.j0 * bz + t.k;
+    T wv[kGmPlanes][VZ];
+    const bool live = t.nrows > 0;
+#pragma unroll
+    for (int q = 0; q < kGmPlanes; q++) {
+#pragma unroll
+        for (int v = 0; v < VZ; v++) wv[q][v] = T(0);
+        if (live && t.xbeg + q < t.xend) vload<T, VZ>(un + base + (long long)(t.xbeg + q) * P, wv[q]);
+    }
+    for (int i = 0; i <= j; i++) {
+        const T c = (T)coef[i];
+        const T *ui = V + (long long)i * kvs + ko;
+        if (!live) continue;
+#pragma unroll
+        for (int q = 0; q < kGmPlanes; q++) {
+            if (t.xbeg + q >= t.xend) continue;
+            T uv[VZ];
+            vload<T, VZ>(ui + base + (long long)(t.xbeg + q) * P, uv);
+#pragma unroll
+            for (int v = 0; v < VZ; v++) wv[q][v] = wv[q][v] - c * uv[v];
+        }
+    }
+    T acc = T(0);
+    if (live) {
+#pragma unroll
+        for (int q = 0; q < kGmPlanes; q++) {
+            if (t.xbeg + q >= t.xend) continue;
+            vstore<T, VZ>(un + base + (long long)(t.xbeg + q) * P, wv[q]);
+#pragma unroll
+            for (int v = 0; v < VZ; v++) acc += wv[q][v] * wv[q][v];
+        }
+    }
+    return acc;
+}
+
+// xb = xa + sum_{l < n} c[l] u_l on the tile's own cells (xb may be xa).
+template <typename T, int VZ, bool OVL>
+__device__ __forceinline__ void tile_gm_final(const Geom &g, const Tile &t, long long goff,
+                                              const T *V, long long kvs, long long ko,
+                                              const double *c, int n, const double *xa,
+                                              double *xb) {
+    if (t.nrows == 0) return;
+    const int bz = t.B.bz;
+    const long long P = (long long)t.B.by * bz;
+    const long long base = (t.B.off - goff) + (long long)t.j0 * bz + t.k;
+    const long long J = t.B.j0 + t.j0, K = t.B.k0 + t.k;
+    // planes of this thread that hold own cells (all of them without overlap)
+    bool mine[kGmPlanes];
+    double xv[kGmPlanes][VZ];
+#pragma unroll
+    for (int q = 0; q < kGmPlanes; q++) {
+        const int i = t.xbeg + q;
+        mine[q] = i < t.xend && !(OVL && axes_out(t.B, i, t.j0, t.k) != 0);
+        if (mine[q]) vload<double, VZ>(xa + ((long long)(t.B.i0 + i) * g.ny + J) * g.nz + K, xv[q]);
+    }
+    for (int l = 0; l < n; l++) {
+        const double cl = c[l];
+        const T *ul = V + (long long)l * kvs + ko + base;
+#pragma unroll
+        for (int q = 0; q < kGmPlanes; q++) {
+            if (!mine[q]) continue;
+            T uv[VZ];
+            vload<T, VZ>(ul + (long long)(t.xbeg + q) * P, uv);
+#pragma unroll
+            for (int v = 0; v < VZ; v++) xv[q][v] += cl * (double)uv[v];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kGmPlanes; q++)
+        if (mine[q])
+            vstore<double, VZ>(xb + ((long long)(t.B.i0 + t.xbeg + q) * g.ny + J) * g.nz + K, xv[q]);
+}
+
+// Givens step of Arnoldi step j for one block record (one thread): the
+// rotations of column j with h_{j+1,j} = hn, the least-squares residual and
+// the stopping rules.  Returns -1 when the step cannot be taken (nothing
+// left to reduce), 0 when it was taken and the block stops, 1 when it was
+// taken and the block goes on.
+__device__ __forceinline__ int gm_givens(double *st, const GmRec &R, int M, int j, double hn,
+                                         double inner_tol) {
+    double *H = st + R.R();
+    for (int i = 0; i < j; i++) {
+        const double x0 = H[i * M + j], x1 = H[(i + 1) * M + j];
+        const double c = st[R.cs() + i], s = st[R.sn() + i];
+        H[i * M + j] = c * x0 + s * x1;
+        H[(i + 1) * M + j] = -s * x0 + c * x1;
+    }
+    const double d = H[j * M + j];
+    const double den = sqrt(d * d + hn * hn);
+    if (!(den > 0.0)) {          // nothing left to reduce
+        st[R.active()] = 0.0;
+        return -1;
+    }
+    const double c = d / den, s = hn / den;
+    st[R.cs() + j] = c;
+    st[R.sn() + j] = s;
+    H[j * M + j] = den;
+    const double gj = st[R.g() + j];
+    st[R.g() + j + 1] = -s * gj;
+    st[R.g() + j] = c * gj;
+    st[R.steps()] = (double)(j + 1);
+    if (!(hn > 0.0)) {
+        st[R.active()] = 0.0;   // invariant Krylov space: the block is solved
+        return 0;
+    }
+    st[R.s() + j + 1] = hn;
+    if (inner_tol > 0.0 && fabs(st[R.g() + j + 1]) <= inner_tol * st[R.beta()]) {
+        st[R.active()] = 0.0;
+        return 0;
+    }
+    return 1;
+}
+
+// y from the triangular system of a block record (one thread), stored as
+// y_i / s_i into c[0..n) (c may be the record's y field).
+__device__ __forceinline__ void gm_backsolve(const double *st, const GmRec &R, int M, int n,
+                                             double *c) {
+    const double *H = st + R.R();
+    for (int i = n - 1; i >= 0; i--) {
+        double s = st[R.g() + i];
+        for (int l = i + 1; l < n; l++) s -= H[i * M + l] * c[l];
+        c[i] = s / H[i * M + i];
+    }
+    for (int i = 0; i < n; i++) c[i] /= st[R.s() + i];
+}
+
 }  // namespace
 
 // The per-block kernels below run one 64-lane workgroup per (right-hand
@@ -179,50 +365,12 @@ __global__ __launch_bounds__(kThreads) void k_gm_apply(Geom g, int t0, long long
     const double *st = rec(a.gm, a, k, t.b);
     if (st[R.active()] == 0.0) return;   // uniform over the workgroup
     const long long ko = (long long)k * bt.is;
-    const T *uj = V + (long long)j * a.kvs + ko;
-    T *un = V + (long long)(j + 1) * a.kvs + ko;
     T wv[kGmPlanes][VZ];
-    tile_gm_apply<T, VZ, OVL>(t, goff, uj, un, T(1.0 / st[R.s() + j]), wv);
-    double *part = a.gpart + ((long long)k * bt.ps + tile) * a.gstride;
-    const int bz = t.B.bz;
-    const long long P = (long long)t.B.by * bz;
-    const long long base = (t.B.off - goff) + (long long)t.j0 * bz + t.k;
+    tile_gm_apply<T, VZ, OVL>(t, goff, V + (long long)j * a.kvs + ko,
+                              V + (long long)(j + 1) * a.kvs + ko, T(1.0 / st[R.s() + j]), wv);
     __shared__ T sh[kThreads / 64][kDotBatch];
-    for (int i0 = 0; i0 <= j; i0 += kDotBatch) {
-        T acc[kDotBatch];
-#pragma unroll
-        for (int c = 0; c < kDotBatch; c++) acc[c] = T(0);
-        if (t.nrows > 0) {
-#pragma unroll
-            for (int c = 0; c < kDotBatch; c++) {
-                if (i0 + c > j) continue;
-                const T *ui = V + (long long)(i0 + c) * a.kvs + ko + base;
-#pragma unroll
-                for (int q = 0; q < kGmPlanes; q++) {
-                    if (t.xbeg + q >= t.xend) continue;
-                    T uv[VZ];
-                    vload<T, VZ>(ui + (long long)(t.xbeg + q) * P, uv);
-#pragma unroll
-                    for (int v = 0; v < VZ; v++) acc[c] += wv[q][v] * uv[v];
-                }
-            }
-        }
-        // workgroup sums of the batch: lanes by butterfly, then the four
-        // wavefronts in order
-#pragma unroll
-        for (int c = 0; c < kDotBatch; c++) {
-            const T sv = wave_sum(acc[c]);
-            if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6][c] = sv;
-        }
-        __syncthreads();
-        if (threadIdx.x < kDotBatch && i0 + (int)threadIdx.x <= j) {
-            T sv = T(0);
-#pragma unroll
-            for (int wv_ = 0; wv_ < kThreads / 64; wv_++) sv += sh[wv_][threadIdx.x];
-            part[i0 + threadIdx.x] = (double)sv;
-        }
-        __syncthreads();
-    }
+    gm_dots<T, VZ, kThreads, false>(t, true, goff, V, a.kvs, ko, j, wv, sh,
+                                    a.gpart + ((long long)k * bt.ps + tile) * a.gstride);
 }
 
 // Arnoldi step j, part 2 (per block): h_ij = (w, u_i) / s_i, i <= j.
@@ -258,42 +406,8 @@ __global__ __launch_bounds__(kThreads) void k_gm_orth(Geom g, int t0, long long 
     const GmRec R{a.M};
     const double *st = rec(a.gm, a, k, t.b);
     if (st[R.active()] == 0.0) return;
-    const long long ko = (long long)k * bt.is;
-    T *un = V + (long long)(j + 1) * a.kvs + ko;
-    const int bz = t.B.bz;
-    const long long P = (long long)t.B.by * bz;
-    const long long base = (t.B.off - goff) + (long long)t.j0 * bz + t.k;
-    T wv[kGmPlanes][VZ];
-    const bool live = t.nrows > 0;
-#pragma unroll
-    for (int q = 0; q < kGmPlanes; q++) {
-#pragma unroll
-        for (int v = 0; v < VZ; v++) wv[q][v] = T(0);
-        if (live && t.xbeg + q < t.xend) vload<T, VZ>(un + base + (long long)(t.xbeg + q) * P, wv[q]);
-    }
-    for (int i = 0; i <= j; i++) {
-        const T c = (T)st[R.coef() + i];
-        const T *ui = V + (long long)i * a.kvs + ko;
-        if (!live) continue;
-#pragma unroll
-        for (int q = 0; q < kGmPlanes; q++) {
-            if (t.xbeg + q >= t.xend) continue;
-            T uv[VZ];
-            vload<T, VZ>(ui + base + (long long)(t.xbeg + q) * P, uv);
-#pragma unroll
-            for (int v = 0; v < VZ; v++) wv[q][v] = wv[q][v] - c * uv[v];
-        }
-    }
-    T acc = T(0);
-    if (live) {
-#pragma unroll
-        for (int q = 0; q < kGmPlanes; q++) {
-            if (t.xbeg + q >= t.xend) continue;
-            vstore<T, VZ>(un + base + (long long)(t.xbeg + q) * P, wv[q]);
-#pragma unroll
-            for (int v = 0; v < VZ; v++) acc += wv[q][v] * wv[q][v];
-        }
-    }
+    const T acc = tile_gm_orth<T, VZ>(t, goff, V, a.kvs, (long long)k * bt.is, j,
+                                      st + R.coef());
     const T s = wg_allsum<T, kThreads>(acc);
     if (threadIdx.x == 0) a.gpart[((long long)k * bt.ps + tile) * a.gstride + a.M + 1] = (double)s;
 }
@@ -310,39 +424,10 @@ __global__ __launch_bounds__(64) void k_gm_norm(const BlockInfo *blocks, int b0,
     double *st = rec(a.gm, a, k, b);
     if (st[R.active()] == 0.0) return;
     const BlockInfo &B = blocks[b];
-    const int M = a.M;
     const double *part = a.gpart + (long long)k * bt.ps * a.gstride;
-    const double hn = sqrt(block_sum(part, a.gstride, M + 1, B.tile0, B.ntiles));
+    const double hn = sqrt(block_sum(part, a.gstride, a.M + 1, B.tile0, B.ntiles));
     if (threadIdx.x != 0) return;
-    double *H = st + R.R();
-    for (int i = 0; i < j; i++) {
-        const double x0 = H[i * M + j], x1 = H[(i + 1) * M + j];
-        const double c = st[R.cs() + i], s = st[R.sn() + i];
-        H[i * M + j] = c * x0 + s * x1;
-        H[(i + 1) * M + j] = -s * x0 + c * x1;
-    }
-    const double d = H[j * M + j];
-    const double den = sqrt(d * d + hn * hn);
-    if (!(den > 0.0)) {          // nothing left to reduce
-        st[R.active()] = 0.0;
-        return;
-    }
-    const double c = d / den, s = hn / den;
-    st[R.cs() + j] = c;
-    st[R.sn() + j] = s;
-    H[j * M + j] = den;
-    const double gj = st[R.g() + j];
-    st[R.g() + j + 1] = -s * gj;
-    st[R.g() + j] = c * gj;
-    st[R.steps()] = (double)(j + 1);
-    atomicAdd(&ctrl[k].inner_iters, 1ull);
-    if (!(hn > 0.0)) {
-        st[R.active()] = 0.0;   // invariant Krylov space: the block is solved
-        return;
-    }
-    st[R.s() + j + 1] = hn;
-    if (inner_tol > 0.0 && fabs(st[R.g() + j + 1]) <= inner_tol * st[R.beta()])
-        st[R.active()] = 0.0;
+    if (gm_givens(st, R, a.M, j, hn, inner_tol) >= 0) atomicAdd(&ctrl[k].inner_iters, 1ull);
 }
 
 // End of the cycle (per block): y from the triangular system, stored as
@@ -354,16 +439,7 @@ __global__ void k_gm_solve(int b0, int nb, Batch bt, GmArgs a, Ctrl *ctrl) {
     if (ctrl[k].done) return;
     const GmRec R{a.M};
     double *st = rec(a.gm, a, k, b);
-    const int n = (int)st[R.steps()];
-    const int M = a.M;
-    const double *H = st + R.R();
-    double *y = st + R.y();
-    for (int i = n - 1; i >= 0; i--) {
-        double s = st[R.g() + i];
-        for (int l = i + 1; l < n; l++) s -= H[i * M + l] * y[l];
-        y[i] = s / H[i * M + i];
-    }
-    for (int i = 0; i < n; i++) y[i] /= st[R.s() + i];
+    gm_backsolve(st, R, a.M, (int)st[R.steps()], st + R.y());
 }
 
 // x_new = x_old + sum_i (y_i / s_i) u_i on the block's own cells (every own
@@ -377,42 +453,112 @@ __global__ __launch_bounds__(kThreads) void k_gm_final(Geom g, int t0, long long
     if (ctrl[k].done) return;
     const int tile = t0 + (w - k * bt.nt);
     const Tile t = decode_tile<VZ, 1>(g, tile, threadIdx.x);
-    if (t.nrows == 0) return;
     const GmRec R{a.M};
     const double *st = rec(a.gm, a, k, t.b);
-    const int n = (int)st[R.steps()];
-    xa += k * bt.vs;
-    xb += k * bt.vs;
-    const long long ko = (long long)k * bt.is;
-    const int bz = t.B.bz;
-    const long long P = (long long)t.B.by * bz;
-    const long long base = (t.B.off - goff) + (long long)t.j0 * bz + t.k;
-    const long long J = t.B.j0 + t.j0, K = t.B.k0 + t.k;
-    // planes of this thread that hold own cells (all of them without overlap)
-    bool mine[kGmPlanes];
-    double xv[kGmPlanes][VZ];
-#pragma unroll
-    for (int q = 0; q < kGmPlanes; q++) {
-        const int i = t.xbeg + q;
-        mine[q] = i < t.xend && !(OVL && axes_out(t.B, i, t.j0, t.k) != 0);
-        if (mine[q]) vload<double, VZ>(xa + ((long long)(t.B.i0 + i) * g.ny + J) * g.nz + K, xv[q]);
-    }
-    for (int l = 0; l < n; l++) {
-        const double c = st[R.y() + l];
-        const T *ul = V + (long long)l * a.kvs + ko + base;
-#pragma unroll
-        for (int q = 0; q < kGmPlanes; q++) {
-            if (!mine[q]) continue;
-            T uv[VZ];
-            vload<T, VZ>(ul + (long long)(t.xbeg + q) * P, uv);
-#pragma unroll
-            for (int v = 0; v < VZ; v++) xv[q][v] += c * (double)uv[v];
+    tile_gm_final<T, VZ, OVL>(g, t, goff, V, a.kvs, (long long)k * bt.is, st + R.y(),
+                              (int)st[R.steps()], xa + k * bt.vs, xb + k * bt.vs);
+}
+
+// ----------------------------------------------------------------------
+// asynchronous sweeps with GMRES inner solves
+// ----------------------------------------------------------------------
+
+// Persistent worker (kAsyncThreads threads): takes one block at a time like
+// the CG worker (staleness-bounded, latest values in memory, Sections 2.1
+// and 2.3), runs a GMRES(m) cycle on it with the Arnoldi dots reduced inside
+// the workgroup, and updates the block's own cells of x in place.  Block
+// records of right-hand side 0 hold the Hessenberg/Givens state.
+template <typename T, int VZ, bool OVL>
+__global__ __launch_bounds__(kAsyncThreads) void k_async_gmres(
+    Geom g, const double *__restrict__ b, double *x, Faces F, T *V, AsyncState as, int m, int S,
+    int max_sweeps, double tol2, double inner_tol, GmArgs a, Ctrl *ctrl) {
+    constexpr int kSubs = kAsyncThreads / kThreads;
+    __shared__ AsyncShared sh;
+    __shared__ T red[kAsyncThreads / 64][kDotBatch];
+    __shared__ double sdot[kGmMaxSteps + 2];
+    __shared__ double scoef[kGmMaxSteps + 1];
+    __shared__ int sflag;
+    const int tid = threadIdx.x;
+    const int sub = tid / kThreads;
+    const int ltid = tid % kThreads;
+    const int nb = g.nblocks;
+    const GmRec R{a.M};
+    for (;;) {
+        const int blk = async_claim(g, as, S, max_sweeps, ctrl, sh);
+        if (blk == -2) return;
+        if (blk < 0) {
+            __builtin_amdgcn_s_sleep(2);
+            continue;
         }
-    }
+        const BlockInfo B = g.blocks[blk];
+        double *st = rec(a.gm, a, 0, blk);
+        // residual of the block's region, stored as u_0
+        double acc64 = 0.0;
+        T accT = T(0);
+        for (int lt = sub; lt < B.ntiles; lt += kSubs) {
+            const Tile t = decode_tile<VZ, 1>(g, B.tile0 + lt, ltid);
+            tile_resid<T, VZ, 1, true, OVL>(g, t, 0, b, x, F, V, acc64, accT);
+        }
+        const double res2 = wg_allsum<double, kAsyncThreads>(acc64);
+        const double beta = sqrt((double)wg_allsum<T, kAsyncThreads>(accT));
+        if (tid == 0) {
+            __hip_atomic_store(&as.board[blk], res2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            st[R.s()] = beta;
+            st[R.g()] = beta;
+            st[R.beta()] = beta;
+            st[R.steps()] = 0.0;
+            st[R.active()] = beta > 0.0 ? 1.0 : 0.0;
+            sflag = beta > 0.0 ? 1 : 0;
+        }
+        __syncthreads();
+        for (int j = 0; j < m && sflag; j++) {
+            // w = A v_j into u_{j+1}, dots with u_0..u_j summed over the tiles
+            if (tid <= j) sdot[tid] = 0.0;
+            __syncthreads();
+            const T inv_s = T(1.0 / st[R.s() + j]);
+            for (int l0 = 0; l0 < B.ntiles; l0 += kSubs) {
+                const int lt = l0 + sub;
+                const bool live = lt < B.ntiles;
+                const Tile t = decode_tile<VZ, 1>(g, B.tile0 + (live ? lt : 0), ltid);
+                T wv[kGmPlanes][VZ];
 #pragma unroll
-    for (int q = 0; q < kGmPlanes; q++)
-        if (mine[q])
-            vstore<double, VZ>(xb + ((long long)(t.B.i0 + t.xbeg + q) * g.ny + J) * g.nz + K, xv[q]);
+                for (int q = 0; q < kGmPlanes; q++)
+#pragma unroll
+                    for (int v = 0; v < VZ; v++) wv[q][v] = T(0);
+                if (live)
+                    tile_gm_apply<T, VZ, OVL>(t, 0, V + (long long)j * a.kvs,
+                                              V + (long long)(j + 1) * a.kvs, inv_s, wv);
+                gm_dots<T, VZ, kAsyncThreads, true>(t, live, 0, V, a.kvs, 0, j, wv, red, sdot);
+            }
+            if (tid == 0)
+                for (int i = 0; i <= j; i++) {
+                    const double h = sdot[i] / st[R.s() + i];
+                    st[R.R() + i * a.M + j] = h;
+                    scoef[i] = h / st[R.s() + i];
+                }
+            __syncthreads();
+            // classical Gram-Schmidt and the new norm
+            T nacc = T(0);
+            for (int lt = sub; lt < B.ntiles; lt += kSubs) {
+                const Tile t = decode_tile<VZ, 1>(g, B.tile0 + lt, ltid);
+                nacc += tile_gm_orth<T, VZ>(t, 0, V, a.kvs, 0, j, scoef);
+            }
+            const double hn = sqrt((double)wg_allsum<T, kAsyncThreads>(nacc));
+            if (tid == 0) sflag = gm_givens(st, R, a.M, j, hn, inner_tol) > 0 ? 1 : 0;
+            __syncthreads();
+        }
+        const int n = (int)st[R.steps()];
+        if (tid == 0) gm_backsolve(st, R, a.M, n, scoef);
+        __syncthreads();
+        if (n > 0) {
+            for (int lt = sub; lt < B.ntiles; lt += kSubs) {
+                const Tile t = decode_tile<VZ, 1>(g, B.tile0 + lt, ltid);
+                tile_gm_final<T, VZ, OVL>(g, t, 0, V, a.kvs, 0, scoef, n, x, x);
+            }
+        }
+        async_publish(as, blk, max_sweeps, n, tol2, ctrl, sh, nb);
+        __syncthreads();
+    }
 }
 
 // ----------------------------------------------------------------------
@@ -504,6 +650,38 @@ hipError_t launch_gm_finish(const Geom &g, int vz, int t0, int t1, int b0, int b
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_async_gmres(const Geom &g, int vz, int grid, const double *b, double *x,
+                              Faces faces, T *V, AsyncState as, int m, int S, int max_sweeps,
+                              double tol2, double inner_tol, GmArgs a, Ctrl *ctrl,
+                              hipStream_t st) {
+    if (grid < 1 || g.rows != 1 || g.tx > kGmPlanes || a.M > kGmMaxSteps)
+        return hipErrorInvalidValue;
+    if (g.ovl) {
+        GM_DISPATCH(vz, hipLaunchKernelGGL((k_async_gmres<T, VZ, true>), dim3(grid),
+                                           dim3(kAsyncThreads), 0, st, g, b, x, faces, V, as, m,
+                                           S, max_sweeps, tol2, inner_tol, a, ctrl));
+    } else {
+        GM_DISPATCH(vz, hipLaunchKernelGGL((k_async_gmres<T, VZ, false>), dim3(grid),
+                                           dim3(kAsyncThreads), 0, st, g, b, x, faces, V, as, m,
+                                           S, max_sweeps, tol2, inner_tol, a, ctrl));
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t async_gmres_occupancy(int vz, int ovl, int *per_cu) {
+    *per_cu = 0;
+    if (ovl) {
+        GM_DISPATCH(vz, return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                            per_cu, (const void *)k_async_gmres<T, VZ, true>, kAsyncThreads, 0));
+    } else {
+        GM_DISPATCH(vz, return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                            per_cu, (const void *)k_async_gmres<T, VZ, false>, kAsyncThreads, 0));
+    }
+    return hipSuccess;
+}
+
 int gm_record_doubles(int M) { return 6 * M + 3 + (M + 1) * M + 4; }
 int gm_max_planes() { return kGmPlanes; }
 
@@ -515,7 +693,11 @@ int gm_max_planes() { return kGmPlanes; }
                                           hipStream_t, int);                                  \
     template hipError_t launch_gm_finish<T>(const Geom &, int, int, int, int, int, long long, \
                                             const T *, const double *, double *, Batch,      \
-                                            GmArgs, Ctrl *, hipStream_t, int);
+                                            GmArgs, Ctrl *, hipStream_t, int);                \
+    template hipError_t launch_async_gmres<T>(const Geom &, int, int, const double *,         \
+                                              double *, Faces, T *, AsyncState, int, int, int, \
+                                              double, double, GmArgs, Ctrl *, hipStream_t);   \
+    template hipError_t async_gmres_occupancy<T>(int, int, int *);
 GM_INST(double)
 GM_INST(float)
 

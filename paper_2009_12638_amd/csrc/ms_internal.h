@@ -186,4 +186,14 @@ hipError_t launch_gm_finish(const Geom &g, int vz, int t0, int t1, int b0, int b
 int gm_record_doubles(int M);
 int gm_max_planes();
 
+// Asynchronous sweeps with GMRES inner solves (persistent workers, as
+// launch_async; Krylov vectors and records of right-hand side 0).
+template <typename T>
+hipError_t launch_async_gmres(const Geom &g, int vz, int grid, const double *b, double *x,
+                              Faces faces, T *V, AsyncState as, int m, int S, int max_sweeps,
+                              double tol2, double inner_tol, GmArgs a, Ctrl *ctrl,
+                              hipStream_t st);
+template <typename T>
+hipError_t async_gmres_occupancy(int vz, int ovl, int *per_cu);
+
 }  // namespace ms

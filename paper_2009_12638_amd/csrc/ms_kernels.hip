@@ -18,390 +18,11 @@
 // synchronous results are bitwise reproducible run to run.
 #include "ms_internal.h"
 #include "ms_device.h"
+#include "ms_tiles.h"
 
 #include <math.h>
 
 namespace ms {
-
-// ----------------------------------------------------------------------
-// tile bodies
-// ----------------------------------------------------------------------
-
-// Outer residual r = b_eff - A x on one tile (Section 3: the right-hand side
-// B_i - sum_j A_ij X_j of a block, with neighbour-block values read straight
-// from x: the halo exchange of Listing 1).  x == nullptr means x = 0.
-// Adds r.r in FP64 to acc64 and in T to accT; stores r packed when STORE.
-// OVL (overlap regions): r is zero outside the region; acc64 counts the
-// block's own cells only (every cell of the grid once), accT the region.
-template <typename T, int VZ, int R, bool STORE, bool OVL = false>
-__device__ __forceinline__ void tile_resid(const Geom &g, const Tile &t, long long goff,
-                                           const double *__restrict__ b, const double *x,
-                                           const Faces &F, T *__restrict__ r, double &acc64,
-                                           T &accT) {
-    const long long nx = g.nx, ny = g.ny, nz = g.nz;
-    const long long J0 = t.B.j0 + t.j0, K = t.B.k0 + t.k;
-    const long long P = (long long)t.B.by * t.B.bz;
-    auto gidx = [&](long long I, int rr) { return (I * ny + J0 + rr) * nz + K; };
-    const bool zm_in = K > 0, zp_in = K + VZ < nz;        // z neighbour exists in the grid
-    const bool zm_sh = t.zc > 0 && t.lane > 0;            // ... and sits in the lane to the left
-    const bool zp_sh = t.zc < t.tpr - 1 && t.lane < 63;
-    const bool ym_ld = t.nrows > 0 && J0 > 0;              // row above the group
-    const bool yp_ld = t.nrows > 0 && J0 + t.nrows < ny;   // row below the group
-    const bool ym_sh = t.j0 > 0 && t.lane >= t.tpr;         // ... held by a lane of this wave
-    const bool yp_sh = t.j0 + t.nrows < t.B.by && t.lane + t.tpr < 64;
-    double xm[R][VZ], xc[R][VZ], xp[R][VZ];
-#pragma unroll
-    for (int rr = 0; rr < R; rr++)
-#pragma unroll
-        for (int v = 0; v < VZ; v++) { xm[rr][v] = 0.0; xc[rr][v] = 0.0; xp[rr][v] = 0.0; }
-    const long long I0 = t.B.i0 + t.xbeg;
-    if (x) {
-#pragma unroll
-        for (int rr = 0; rr < R; rr++) {
-            if (rr < t.nrows) {
-                if (I0 > 0) vload<double, VZ>(x + gidx(I0 - 1, rr), xm[rr]);
-                vload<double, VZ>(x + gidx(I0, rr), xc[rr]);
-            }
-        }
-    }
-    for (int i = t.xbeg; i < t.xend; i++) {
-        const long long I = t.B.i0 + i;
-        double ym[VZ], yp[VZ];
-#pragma unroll
-        for (int v = 0; v < VZ; v++) { ym[v] = 0.0; yp[v] = 0.0; }
-        // rows next to the group: from the neighbouring group tpr lanes away
-        // when it is in this wavefront and in this block, else from memory
-        double ysu[VZ], ysd[VZ];
-#pragma unroll
-        for (int v = 0; v < VZ; v++) {
-            ysu[v] = __shfl_up(xc[R - 1][v], t.tpr, 64);
-            ysd[v] = __shfl_down(xc[0][v], t.tpr, 64);
-        }
-        if (x) {
-#pragma unroll
-            for (int rr = 0; rr < R; rr++)
-                if (rr < t.nrows && I + 1 < nx) vload<double, VZ>(x + gidx(I + 1, rr), xp[rr]);
-            if (ym_ld) {
-                if (ym_sh) {
-#pragma unroll
-                    for (int v = 0; v < VZ; v++) ym[v] = ysu[v];
-                } else {
-                    vload<double, VZ>(x + gidx(I, -1), ym);
-                }
-            }
-            if (yp_ld) {
-                if (yp_sh) {
-#pragma unroll
-                    for (int v = 0; v < VZ; v++) yp[v] = ysd[v];
-                } else {
-                    vload<double, VZ>(x + gidx(I, t.nrows), yp);
-                }
-            }
-        }
-#pragma unroll
-        for (int rr = 0; rr < R; rr++) {
-            const double sl = from_left(xc[rr][VZ - 1]);
-            const double sr = from_right(xc[rr][0]);
-            if (rr >= t.nrows) continue;
-            const long long c = gidx(I, rr);
-            double zm = 0.0, zp = 0.0;
-            if (x && zm_in) zm = zm_sh ? sl : x[c - 1];
-            if (x && zp_in) zp = zp_sh ? sr : x[c + VZ];
-            double bb[VZ];
-            if (b) {
-                vload<double, VZ>(b + c, bb);
-            } else {
-#pragma unroll
-                for (int v = 0; v < VZ; v++) bb[v] = 0.0;
-            }
-            const long long J = J0 + rr;
-            // Dirichlet lifting: boundary neighbours' g moved to the right
-            if (I == 0 && F.f[0]) {
-#pragma unroll
-                for (int v = 0; v < VZ; v++) bb[v] += F.f[0][J * nz + K + v];
-            }
-            if (I == nx - 1 && F.f[1]) {
-#pragma unroll
-                for (int v = 0; v < VZ; v++) bb[v] += F.f[1][J * nz + K + v];
-            }
-            if (J == 0 && F.f[2]) {
-#pragma unroll
-                for (int v = 0; v < VZ; v++) bb[v] += F.f[2][I * nz + K + v];
-            }
-            if (J == ny - 1 && F.f[3]) {
-#pragma unroll
-                for (int v = 0; v < VZ; v++) bb[v] += F.f[3][I * nz + K + v];
-            }
-            if (K == 0 && F.f[4]) bb[0] += F.f[4][I * ny + J];
-            if (K + VZ == nz && F.f[5]) bb[VZ - 1] += F.f[5][I * ny + J];
-            T out[VZ];
-#pragma unroll
-            for (int v = 0; v < VZ; v++) {
-                const double left = v == 0 ? zm : xc[rr][v - 1];
-                const double right = v == VZ - 1 ? zp : xc[rr][v + 1];
-                const double up = rr == 0 ? ym[v] : xc[rr - 1][v];
-                const double down = (rr == R - 1 || rr + 1 == t.nrows) ? yp[v] : xc[rr + 1][v];
-                const double ax = 6.0 * xc[rr][v] - xm[rr][v] - xp[rr][v] - up - down - left - right;
-                double rv = bb[v] - ax;
-                if (OVL) {
-                    const int n = axes_out(t.B, i, t.j0 + rr, t.k + v);
-                    if (n > 1) rv = 0.0;
-                    if (n == 0) acc64 += rv * rv;
-                } else {
-                    acc64 += rv * rv;
-                }
-                out[v] = (T)rv;
-                accT += out[v] * out[v];
-            }
-            if (STORE)
-                vstore<T, VZ>(r + (t.B.off - goff) + (long long)i * P +
-                                  (long long)(t.j0 + rr) * t.B.bz + t.k, out);
-        }
-#pragma unroll
-        for (int rr = 0; rr < R; rr++)
-#pragma unroll
-            for (int v = 0; v < VZ; v++) { xm[rr][v] = xc[rr][v]; xc[rr][v] = xp[rr][v]; xp[rr][v] = 0.0; }
-    }
-}
-
-// Inner CG phase 1 on one tile (Section 3: the inner Krylov solve of a
-// block on A_ii, here CG): p_new = r + beta p_old (p_new = r when !use_old),
-// returns the thread's part of p_new . A_ii p_new (zero outside the block).
-template <typename T, int VZ, int R>
-__device__ __forceinline__ T tile_stencil(const Tile &t, long long goff,
-                                          const T *__restrict__ r, const T *__restrict__ pold,
-                                          T *__restrict__ pnew, T beta, bool use_old) {
-    const int bz = t.B.bz, by = t.B.by, bx = t.B.bx;
-    const long long P = (long long)by * bz;
-    const long long base = (t.B.off - goff) + (long long)t.j0 * bz + t.k;
-    const bool zm_in = t.zc > 0, zp_in = t.zc < t.tpr - 1;
-    const bool zm_sh = zm_in && t.lane > 0, zp_sh = zp_in && t.lane < 63;
-    const bool ym_ld = t.nrows > 0 && t.j0 > 0;
-    const bool yp_ld = t.nrows > 0 && t.j0 + t.nrows < by;
-    const bool ym_sh = t.lane >= t.tpr, yp_sh = t.lane + t.tpr < 64;
-    auto pv = [&](long long o, T(&out)[VZ]) {
-        vload<T, VZ>(r + o, out);
-        if (use_old) {
-            T po[VZ];
-            vload<T, VZ>(pold + o, po);
-#pragma unroll
-            for (int v = 0; v < VZ; v++) out[v] = out[v] + beta * po[v];
-        }
-    };
-    auto ps = [&](long long o) -> T {
-        T v = r[o];
-        if (use_old) v = v + beta * pold[o];
-        return v;
-    };
-    T pm[R][VZ], pc[R][VZ], pp[R][VZ];
-#pragma unroll
-    for (int rr = 0; rr < R; rr++)
-#pragma unroll
-        for (int v = 0; v < VZ; v++) { pm[rr][v] = T(0); pc[rr][v] = T(0); pp[rr][v] = T(0); }
-#pragma unroll
-    for (int rr = 0; rr < R; rr++) {
-        if (rr < t.nrows) {
-            if (t.xbeg > 0) pv(base + (long long)(t.xbeg - 1) * P + (long long)rr * bz, pm[rr]);
-            pv(base + (long long)t.xbeg * P + (long long)rr * bz, pc[rr]);
-        }
-    }
-    T acc = T(0);
-    for (int i = t.xbeg; i < t.xend; i++) {
-        const long long o = base + (long long)i * P;
-        T ym[VZ], yp[VZ];
-#pragma unroll
-        for (int v = 0; v < VZ; v++) { ym[v] = T(0); yp[v] = T(0); }
-        T ysu[VZ], ysd[VZ];
-#pragma unroll
-        for (int v = 0; v < VZ; v++) {
-            ysu[v] = __shfl_up(pc[R - 1][v], t.tpr, 64);
-            ysd[v] = __shfl_down(pc[0][v], t.tpr, 64);
-        }
-#pragma unroll
-        for (int rr = 0; rr < R; rr++)
-            if (rr < t.nrows && i + 1 < bx) pv(o + P + (long long)rr * bz, pp[rr]);
-        if (ym_ld) {
-            if (ym_sh) {
-#pragma unroll
-                for (int v = 0; v < VZ; v++) ym[v] = ysu[v];
-            } else {
-                pv(o - bz, ym);
-            }
-        }
-        if (yp_ld) {
-            if (yp_sh) {
-#pragma unroll
-                for (int v = 0; v < VZ; v++) yp[v] = ysd[v];
-            } else {
-                pv(o + (long long)t.nrows * bz, yp);
-            }
-        }
-#pragma unroll
-        for (int rr = 0; rr < R; rr++) {
-            const T sl = from_left(pc[rr][VZ - 1]);
-            const T sr = from_right(pc[rr][0]);
-            if (rr >= t.nrows) continue;
-            const long long orow = o + (long long)rr * bz;
-            T zm = T(0), zp = T(0);
-            if (zm_in) zm = zm_sh ? sl : ps(orow - 1);
-            if (zp_in) zp = zp_sh ? sr : ps(orow + VZ);
-#pragma unroll
-            for (int v = 0; v < VZ; v++) {
-                const T left = v == 0 ? zm : pc[rr][v - 1];
-                const T right = v == VZ - 1 ? zp : pc[rr][v + 1];
-                const T up = rr == 0 ? ym[v] : pc[rr - 1][v];
-                const T down = (rr == R - 1 || rr + 1 == t.nrows) ? yp[v] : pc[rr + 1][v];
-                const T q = T(6) * pc[rr][v] - pm[rr][v] - pp[rr][v] - up - down - left - right;
-                acc += pc[rr][v] * q;
-            }
-            vstore<T, VZ>(pnew + orow, pc[rr]);
-        }
-#pragma unroll
-        for (int rr = 0; rr < R; rr++)
-#pragma unroll
-            for (int v = 0; v < VZ; v++) { pm[rr][v] = pc[rr][v]; pc[rr][v] = pp[rr][v]; pp[rr][v] = T(0); }
-    }
-    return acc;
-}
-
-// Inner CG phase 2 on one tile: d += alpha p (d taken as 0 when !have_d);
-// r -= alpha A_ii p; returns the thread's part of r.r.  OVL: A_ii p is taken
-// as zero outside the region, so r (and d, p) stay zero there.
-template <typename T, typename TD, int VZ, int R, bool OVL = false>
-__device__ __forceinline__ T tile_update(const Tile &t, long long goff, T *__restrict__ r,
-                                         const T *__restrict__ p, TD *__restrict__ d, T alpha,
-                                         bool have_d) {
-    const int bz = t.B.bz, by = t.B.by, bx = t.B.bx;
-    const long long P = (long long)by * bz;
-    const long long base = (t.B.off - goff) + (long long)t.j0 * bz + t.k;
-    const bool zm_in = t.zc > 0, zp_in = t.zc < t.tpr - 1;
-    const bool zm_sh = zm_in && t.lane > 0, zp_sh = zp_in && t.lane < 63;
-    const bool ym_ld = t.nrows > 0 && t.j0 > 0;
-    const bool yp_ld = t.nrows > 0 && t.j0 + t.nrows < by;
-    const bool ym_sh = t.lane >= t.tpr, yp_sh = t.lane + t.tpr < 64;
-    T pm[R][VZ], pc[R][VZ], pp[R][VZ];
-#pragma unroll
-    for (int rr = 0; rr < R; rr++)
-#pragma unroll
-        for (int v = 0; v < VZ; v++) { pm[rr][v] = T(0); pc[rr][v] = T(0); pp[rr][v] = T(0); }
-#pragma unroll
-    for (int rr = 0; rr < R; rr++) {
-        if (rr < t.nrows) {
-            if (t.xbeg > 0) vload<T, VZ>(p + base + (long long)(t.xbeg - 1) * P + (long long)rr * bz, pm[rr]);
-            vload<T, VZ>(p + base + (long long)t.xbeg * P + (long long)rr * bz, pc[rr]);
-        }
-    }
-    T acc = T(0);
-    for (int i = t.xbeg; i < t.xend; i++) {
-        const long long o = base + (long long)i * P;
-        T ym[VZ], yp[VZ];
-#pragma unroll
-        for (int v = 0; v < VZ; v++) { ym[v] = T(0); yp[v] = T(0); }
-        T ysu[VZ], ysd[VZ];
-#pragma unroll
-        for (int v = 0; v < VZ; v++) {
-            ysu[v] = __shfl_up(pc[R - 1][v], t.tpr, 64);
-            ysd[v] = __shfl_down(pc[0][v], t.tpr, 64);
-        }
-#pragma unroll
-        for (int rr = 0; rr < R; rr++)
-            if (rr < t.nrows && i + 1 < bx) vload<T, VZ>(p + o + P + (long long)rr * bz, pp[rr]);
-        if (ym_ld) {
-            if (ym_sh) {
-#pragma unroll
-                for (int v = 0; v < VZ; v++) ym[v] = ysu[v];
-            } else {
-                vload<T, VZ>(p + o - bz, ym);
-            }
-        }
-        if (yp_ld) {
-            if (yp_sh) {
-#pragma unroll
-                for (int v = 0; v < VZ; v++) yp[v] = ysd[v];
-            } else {
-                vload<T, VZ>(p + o + (long long)t.nrows * bz, yp);
-            }
-        }
-#pragma unroll
-        for (int rr = 0; rr < R; rr++) {
-            const T sl = from_left(pc[rr][VZ - 1]);
-            const T sr = from_right(pc[rr][0]);
-            if (rr >= t.nrows) continue;
-            const long long orow = o + (long long)rr * bz;
-            T zm = T(0), zp = T(0);
-            if (zm_in) zm = zm_sh ? sl : p[orow - 1];
-            if (zp_in) zp = zp_sh ? sr : p[orow + VZ];
-            T rv[VZ];
-            TD dd[VZ];
-            vload<T, VZ>(r + orow, rv);
-            if (have_d) {
-                vload<TD, VZ>(d + orow, dd);
-            } else {
-#pragma unroll
-                for (int v = 0; v < VZ; v++) dd[v] = TD(0);
-            }
-#pragma unroll
-            for (int v = 0; v < VZ; v++) {
-                const T left = v == 0 ? zm : pc[rr][v - 1];
-                const T right = v == VZ - 1 ? zp : pc[rr][v + 1];
-                const T up = rr == 0 ? ym[v] : pc[rr - 1][v];
-                const T down = (rr == R - 1 || rr + 1 == t.nrows) ? yp[v] : pc[rr + 1][v];
-                T q = T(6) * pc[rr][v] - pm[rr][v] - pp[rr][v] - up - down - left - right;
-                if (OVL && axes_out(t.B, i, t.j0 + rr, t.k + v) > 1) q = T(0);
-                dd[v] = dd[v] + alpha * pc[rr][v];
-                rv[v] = rv[v] - alpha * q;
-                acc += rv[v] * rv[v];
-            }
-            vstore<TD, VZ>(d + orow, dd);
-            vstore<T, VZ>(r + orow, rv);
-        }
-#pragma unroll
-        for (int rr = 0; rr < R; rr++)
-#pragma unroll
-            for (int v = 0; v < VZ; v++) { pm[rr][v] = pc[rr][v]; pc[rr][v] = pp[rr][v]; pp[rr][v] = T(0); }
-    }
-    return acc;
-}
-
-// Outer update on one tile (Section 3: X_i^(k) = X_i^(k-1) + correction):
-// xb = xa + d (when have_d) + alpha p (when use_p), in FP64.  xb may equal xa.
-// OVL: only the block's own cells are written (each cell takes its owner's
-// correction: the multisplitting weights D_i of Section 2.3 are 0/1); the
-// vector width divides the own box's z offset and extent, so a z vector is
-// wholly own or wholly not.
-template <typename T, int VZ, int R, bool OVL = false>
-__device__ __forceinline__ void tile_final(const Geom &g, const Tile &t, long long goff,
-                                           const T *p, const T *d, T alpha, bool have_d,
-                                           bool use_p, const double *xa, double *xb) {
-    const int bz = t.B.bz, by = t.B.by;
-    const long long P = (long long)by * bz;
-    const long long base = (t.B.off - goff) + (long long)t.j0 * bz + t.k;
-    const long long J0 = t.B.j0 + t.j0, K = t.B.k0 + t.k;
-    for (int i = t.xbeg; i < t.xend; i++) {
-#pragma unroll
-        for (int rr = 0; rr < R; rr++) {
-            if (rr >= t.nrows) continue;
-            if (OVL && axes_out(t.B, i, t.j0 + rr, t.k) != 0) continue;
-            const long long o = base + (long long)i * P + (long long)rr * bz;
-            const long long gI = ((long long)(t.B.i0 + i) * g.ny + J0 + rr) * g.nz + K;
-            double xo[VZ];
-            vload<double, VZ>(xa + gI, xo);
-            if (have_d) {
-                T dd[VZ];
-                vload<T, VZ>(d + o, dd);
-#pragma unroll
-                for (int v = 0; v < VZ; v++) xo[v] += (double)dd[v];
-            }
-            if (use_p) {
-                T pc[VZ];
-                vload<T, VZ>(p + o, pc);
-#pragma unroll
-                for (int v = 0; v < VZ; v++) xo[v] += (double)(alpha * pc[v]);
-            }
-            vstore<double, VZ>(xb + gI, xo);
-        }
-    }
-}
 
 // ----------------------------------------------------------------------
 // synchronous phase kernels: one tile per workgroup
@@ -662,75 +283,13 @@ __global__ __launch_bounds__(kAsyncThreads) void k_async(Geom g, const double *_
                                                          T *p1, T *d, AsyncState as, int m,
                                                          int S, int max_sweeps, double tol2,
                                                          double inner_tol, Ctrl *ctrl) {
-    __shared__ int s_blk;
-    __shared__ int s_gap;
-    __shared__ unsigned long long s_key[kAsyncThreads / 64];
+    __shared__ AsyncShared sh;
     const int tid = threadIdx.x;
     const int sub = tid / kThreads;
     const int ltid = tid % kThreads;
     const int nb = g.nblocks;
     for (;;) {
-        // ---- the eligible unclaimed block with the lowest version ----
-        unsigned long long best = ~0ull;
-        for (int c = tid; c < nb; c += kAsyncThreads) {
-            const int blk = (c + (int)blockIdx.x * 7) % nb;   // spread the start per worker
-            if (__hip_atomic_load(&as.claim[blk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) continue;
-            const int v = __hip_atomic_load(&as.version[blk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (v >= max_sweeps) continue;
-            bool ok = true;
-            for (int f = 0; f < 6 && ok; f++) {
-                const int nbk = as.nbr[blk * 6 + f];
-                if (nbk < 0) continue;
-                const int vn = __hip_atomic_load(&as.version[nbk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = vn >= v + 1 - S;
-            }
-            if (!ok) continue;
-            const unsigned long long key = ((unsigned long long)(unsigned)v << 32) | (unsigned)blk;
-            best = key < best ? key : best;
-        }
-        for (int o = 32; o > 0; o >>= 1) {
-            const unsigned long long other = __shfl_xor(best, o, 64);
-            best = other < best ? other : best;
-        }
-        if ((tid & 63) == 0) s_key[tid >> 6] = best;
-        __syncthreads();
-        if (tid == 0) {
-            unsigned long long k = ~0ull;
-            for (int w = 0; w < kAsyncThreads / 64; w++) k = s_key[w] < k ? s_key[w] : k;
-            int pick = -1;
-            if (__hip_atomic_load(&ctrl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-                k = ~0ull;       // the residual estimate is below tol: start nothing new
-            }
-            if (k != ~0ull) {
-                const int cand = (int)(k & 0xffffffffu);
-                int zero = 0;
-                if (__hip_atomic_compare_exchange_strong(&as.claim[cand], &zero, 1, __ATOMIC_ACQUIRE,
-                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                    pick = cand;
-            }
-            if (pick < 0) {
-                const bool stop = __hip_atomic_load(&ctrl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-                const int fin = __hip_atomic_load(as.finished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (stop || fin >= nb) pick = -2;
-            } else {
-                // staleness this sweep will see, then acquire the neighbours'
-                // published x values
-                const int v = __hip_atomic_load(&as.version[pick], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                int gap = 0;
-                for (int f = 0; f < 6; f++) {
-                    const int nbk = as.nbr[pick * 6 + f];
-                    if (nbk < 0) continue;
-                    const int vn = __hip_atomic_load(&as.version[nbk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    gap = max(gap, v - vn);
-                }
-                s_gap = gap;
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            }
-            s_blk = pick;
-        }
-        __syncthreads();
-        const int blk = s_blk;
-        __syncthreads();
+        const int blk = async_claim(g, as, S, max_sweeps, ctrl, sh);
         if (blk == -2) return;                      // stop flag, or every block finished
         if (blk < 0) {                              // nothing eligible right now
             __builtin_amdgcn_s_sleep(2);
@@ -790,26 +349,7 @@ __global__ __launch_bounds__(kAsyncThreads) void k_async(Geom g, const double *_
                 tile_final<T, VZ, R, OVL>(g, t, 0, (const T *)nullptr, d, T(0), true, false, x, x);
             }
         }
-        // ---- publish: x of this block, then its version ----
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        if (tid == 0) {
-            const int v = __hip_atomic_load(&as.version[blk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
-            __hip_atomic_store(&as.version[blk], v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&as.claim[blk], 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            if (v >= max_sweeps) atomicAdd(as.finished, 1);
-            atomicAdd(&ctrl->inner_iters, (unsigned long long)iters);
-            atomicAdd(&ctrl->work_items, 1ull);
-            atomicMax(&ctrl->max_stale, s_gap);
-            if (tol2 > 0.0) {
-                // residual estimate from the latest published block residuals
-                // (Section 3: an estimate that may be some sweeps old)
-                double est = 0.0;
-                for (int q = 0; q < nb; q++)
-                    est += __hip_atomic_load(&as.board[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (est <= tol2) __hip_atomic_store(&ctrl->stop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
+        async_publish(as, blk, max_sweeps, iters, tol2, ctrl, sh, nb);
         __syncthreads();
     }
 }
