@@ -16,12 +16,14 @@ and asynchronous sweeps, the global CG baseline, sweeps on overlapping blocks
 16-right-hand-side batched workload (batch-*), per-kernel event timings, the
 dominant kernel's fraction of the 8 TB/s HBM peak beside a measured device
 copy, and the CPU oracle timed on this host over a bounded sample of the same
-workload.  With
---full-solve each mode is also run to the 1e-8 relative residual and timed
-(time-to-tolerance), and the CPU oracle re-checks the final residual.
+workload (the only use of the oracle here).  After the timed region one
+configuration (overlap 6, m = 30, mixed by default) is solved to the 1e-8
+relative residual and timed (time_to_tol; --no-tol-solve skips it).  With
+--full-solve every mode is also run to 1e-8 and timed; the final residuals are
+the library's own FP64 evaluation.
 
     python bench.py [--steps K] [--warmup W] [--modes sync-mixed,sync-fp64,...]
-                    [--full-solve] [--no-cpu]
+                    [--full-solve] [--no-cpu] [--no-tol-solve]
 """
 from __future__ import annotations
 
@@ -38,7 +40,7 @@ METRIC = "time-to-1e-8 residual & stencil/CG HBM GB/s, 512^3 Laplace; mixed vs p
 # the sources of the sweep kernels: the traffic counters are only reused while
 # these are unchanged
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2009_12638_amd", "csrc", f)
-                  for f in ("ms_kernels.hip", "ms_device.h")]
+                  for f in ("ms_kernels.hip", "ms_device.h", "ms_tiles.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_bumps512_sync_mixed.json")
 HBM_PEAK_GBPS = 8000.0
 ALL_MODES = ["sync-mixed", "sync-fp64", "async-mixed", "async-fp64", "cg-fp64",
@@ -145,7 +147,7 @@ def per_kernel(prof, N, byte_lists, extra=None, cells=None):
     return out
 
 
-def run_mode(args, torch, ms, w, mode: str, oracle_check):
+def run_mode(args, torch, ms, w, mode: str):
     kind, prec = mode.split("-")
     shape, cuts = w["shape"], w["cuts"]
     N = shape[0] * shape[1] * shape[2]
@@ -162,9 +164,22 @@ def run_mode(args, torch, ms, w, mode: str, oracle_check):
         ms.ms_set_overlap(h, ov)
     if kind == "gmres":
         ms.ms_reserve_krylov(h, m)
+    tuned = {}
+    if kind == "ovl" and args.autotune:
+        from paper_2009_12638_amd import tune
+        log(f"{mode}: autotuning overlap depth and m")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        best, table = tune.tune_overlap_inner(shape, cuts, precision=precision, tol=w["tol"])
+        ov, m = best["overlap"], best["m"]
+        ms.ms_set_overlap(h, ov)
+        tuned = {"overlap": ov, "inner_iters": m,
+                 "tune_seconds": round(time.perf_counter() - t0, 2),
+                 "table": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+                           for r in table]}
+        log(f"{mode}: tuned overlap {ov}, m {m} in {tuned['tune_seconds']} s")
     NR = region_cells(shape, cuts, ov)   # cells the residual and inner kernels touch
     x = torch.zeros_like(b)
-    tuned = {}
     if kind == "batch":
         ms.ms_reserve(h, nrhs)
         if args.autotune:
@@ -201,7 +216,8 @@ def run_mode(args, torch, ms, w, mode: str, oracle_check):
         res["overlap"] = ov
         res["region_cells"] = NR
     if tuned:
-        res["autotuned"] = {k: tuned[k] for k in ("rows", "x_chunk", "inner_iters")}
+        res["autotuned"] = {k: tuned[k] for k in ("rows", "x_chunk", "inner_iters", "overlap",
+                                                  "tune_seconds", "table") if k in tuned}
     if kind == "cg":
         bpu = sum(CG_BYTES.values())
         res["GBps"] = round(bpu * N * args.steps / sec / 1e9, 1)
@@ -266,8 +282,6 @@ def run_mode(args, torch, ms, w, mode: str, oracle_check):
             rel = max(rels)
         else:
             rel, _ = ms.ms_residual(h, b, x)
-            if oracle_check is not None:
-                res["final_rel_residual_oracle"] = oracle_check(x.cpu().numpy())
         res["final_rel_residual_gpu"] = rel
         log(f"{mode}: {total} sweeps, {res['time_to_tol_s']} s, residual {rel:.3e}")
     ms.ms_destroy(h)
@@ -315,6 +329,43 @@ def overlap_study(args, torch, ms, inputs):
             del x
     ms.ms_destroy(h)
     del b
+    torch.cuda.empty_cache()
+    return out
+
+
+def tol_solve(args, torch, ms, w):
+    """Time to the workload's tolerance for one configuration (synchronous,
+    overlap --tol-overlap, m = --tol-m, --tol-precision), from x = 0."""
+    shape, cuts = w["shape"], w["cuts"]
+    b = torch.from_numpy(w["b"]).to("cuda")
+    h = ms.ms_create(shape, cuts=[list(map(int, c)) for c in cuts], faces=None)
+    if args.tol_overlap:
+        ms.ms_set_overlap(h, args.tol_overlap)
+    x = torch.zeros_like(b)
+    ms.ms_solve(h, b, x, 0.0, args.tol_m, "sync", max_sweeps=2, precision=args.tol_precision)
+    x.zero_()
+    log(f"time to {w['tol']}: overlap {args.tol_overlap}, m {args.tol_m}, {args.tol_precision}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    total = 0
+    while True:
+        fs = ms.ms_solve(h, b, x, w["tol"], args.tol_m, "sync", precision=args.tol_precision,
+                         max_sweeps=200, raise_on_error=False)
+        total += fs.sweeps
+        if fs.status == ms.MS_OK:
+            break
+        if fs.status != ms.MS_ERR_NOT_CONVERGED or total > 200000:
+            raise RuntimeError(f"time-to-tol solve failed with status {fs.status}")
+        log(f"  {total} sweeps, residual {fs.rel_residual:.3e}, {time.perf_counter() - t0:.1f} s")
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    rel, _ = ms.ms_residual(h, b, x)
+    out = {"mode": f"sync-{args.tol_precision}", "overlap": args.tol_overlap,
+           "inner_iters": args.tol_m, "tol": w["tol"], "sweeps": total,
+           "seconds": round(sec, 3), "final_rel_residual_gpu": rel}
+    log(f"time to tol: {total} sweeps, {sec:.2f} s, residual {rel:.3e}")
+    ms.ms_destroy(h)
+    del x, b
     torch.cuda.empty_cache()
     return out
 
@@ -406,8 +457,13 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(o, beff, w, m: int, sweeps: int):
+def cpu_baseline(w, m: int, sweeps: int):
+    """The CPU oracle (test infrastructure, used here only as the reported
+    baseline) timed on this host over `sweeps` FP64 sweeps of the workload."""
     import numpy as np
+    import oracle
+    o = oracle.load()
+    beff = o.lift_bc(w["b"], [None] * 6)
     shape, cuts = w["shape"], w["cuts"]
     N = shape[0] * shape[1] * shape[2]
     log(f"cpu oracle: {sweeps} FP64 sweeps on {o.num_threads()} threads")
@@ -439,7 +495,8 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=4)
     ap.add_argument("--chunk", type=int, default=400, help="sweeps per call in --full-solve")
     ap.add_argument("--autotune", action="store_true",
-                    help="batched modes: pick tile shape and m with the autotuner first")
+                    help="batched modes: pick tile shape and m with the autotuner first; "
+                         "ovl modes: pick the overlap depth and m")
     ap.add_argument("--overlap", type=int, default=0,
                     help="overlap depth of the blocks in sync, batch and gmres modes")
     ap.add_argument("--ovl-depth", type=int, default=2,
@@ -455,6 +512,11 @@ def main():
                     help="comma list of block layouts GXxGYxGZ: solve the study workload to "
                          "--layout-tol for each (sync, mixed)")
     ap.add_argument("--layout-tol", type=float, default=1e-5)
+    ap.add_argument("--no-tol-solve", action="store_true",
+                    help="skip the time-to-tolerance solve of the default line")
+    ap.add_argument("--tol-overlap", type=int, default=6)
+    ap.add_argument("--tol-m", type=int, default=30)
+    ap.add_argument("--tol-precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for hardware counters)")
     args = ap.parse_args()
@@ -484,18 +546,6 @@ def main():
         del src, dst
     log(f"building inputs for {args.workload}")
     w = inputs.workload(args.workload)
-    o = beff = None
-    if not args.no_cpu or args.full_solve:
-        import numpy as np
-        import oracle
-        o = oracle.load()
-        beff = o.lift_bc(w["b"], [None] * 6)
-        nbeff = float(np.linalg.norm(beff))
-
-        def oracle_check(xh):
-            return o.residual(beff, xh) / nbeff
-    else:
-        oracle_check = None
     results = {}
     wb = None
     for mo in modes:
@@ -503,10 +553,10 @@ def main():
             if wb is None:
                 log(f"building inputs for {BATCH_WORKLOAD}")
                 wb = inputs.workload(BATCH_WORKLOAD)
-            results[mo] = run_mode(args, torch, ms, wb, mo, None)
+            results[mo] = run_mode(args, torch, ms, wb, mo)
         else:
-            results[mo] = run_mode(args, torch, ms, w, mo,
-                                   oracle_check if args.full_solve else None)
+            results[mo] = run_mode(args, torch, ms, w, mo)
+    to_tol = None if args.no_tol_solve else tol_solve(args, torch, ms, w)
     study = overlap_study(args, torch, ms, inputs) if args.overlap_study else None
     layouts = layout_study(args, torch, ms, inputs) if args.layout_study else None
     log("copy probe: device copy bandwidth")
@@ -526,7 +576,7 @@ def main():
                 "algorithmic_bytes_per_launch": dom["bytes_per_launch"],
                 "traffic_bytes_per_launch": None if tb is None else int(tb),
                 "unknowns_per_launch": dom["unknowns_per_launch"]}
-    cpu = None if args.no_cpu else cpu_baseline(o, beff, w, args.m, args.cpu_sweeps)
+    cpu = None if args.no_cpu else cpu_baseline(w, args.m, args.cpu_sweeps)
     kind, prec = modes[0].split("-")
     if kind == "batch":
         w = wb
@@ -561,6 +611,8 @@ def main():
     }
     if args.overlap:
         line["config"]["overlap"] = args.overlap
+    if to_tol:
+        line["time_to_tol"] = to_tol
     if study:
         line["overlap_study"] = study
     if layouts:

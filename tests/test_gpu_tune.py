@@ -87,3 +87,31 @@ def test_adaptive_inner_iterations_replay(orc):
     ost, xo, ototal = _replay(orc, beff, cuts, schedule, 1e-8)
     assert ost == 0 and ototal == total, (ototal, total)
     assert float(np.linalg.norm(host(x) - xo) / np.linalg.norm(xo)) <= 1e-10
+
+
+def test_tune_overlap_and_inner(orc):
+    """The (overlap, m) tuner solves a proxy with the same block shapes for
+    every pair and returns the fastest converged one; the proxy keeps the
+    block shapes; a solve of the real problem with the chosen pair matches
+    the oracle's overlapping block Jacobi with the same m."""
+    torch = torch_cuda()
+    from paper_2009_12638_amd import tune
+    shape, cuts = (48, 40, 36), ([0, 16, 32, 48], [0, 20, 40], [0, 12, 24, 36])
+    pshape, pcuts, _ = tune.proxy_problem(shape, cuts)
+    assert pshape == (32, 40, 24) and pcuts == [[0, 16, 32], [0, 20, 40], [0, 12, 24]]
+    say("tune overlap and m")
+    best, results = tune.tune_overlap_inner(shape, cuts, precision="mixed", overlaps=(0, 2),
+                                            inners=(5, 10), tol=1e-6)
+    assert len(results) == 4 and best in results and best["converged"]
+    assert best["seconds"] == min(r["seconds"] for r in results if r["converged"])
+    b = inputs.poisson_randn(shape, 143)
+    h = ms.ms_create(shape, cuts=[list(c) for c in cuts])
+    ms.ms_set_overlap(h, best["overlap"])
+    x = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    st = ms.ms_solve(h, dev(b), x, 1e-8, best["m"], "sync")
+    ms.ms_destroy(h)
+    beff = orc.lift_bc(b, [None] * 6)
+    ost, xo, K, _, _ = orc.multisplit(beff, np.zeros(shape), cuts, tol=1e-8, m=best["m"],
+                                      overlap=best["overlap"])
+    assert st.status == 0 and ost == 0 and st.sweeps == K
+    assert float(np.linalg.norm(host(x) - xo) / np.linalg.norm(xo)) <= 1e-10
