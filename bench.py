@@ -165,12 +165,16 @@ def run_mode(args, torch, ms, w, mode: str):
     if kind == "gmres":
         ms.ms_reserve_krylov(h, m)
     tuned = {}
-    if kind == "ovl" and args.autotune:
+    if kind in ("ovl", "batch") and args.autotune:
         from paper_2009_12638_amd import tune
         log(f"{mode}: autotuning overlap depth and m")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        best, table = tune.tune_overlap_inner(shape, cuts, precision=precision, tol=w["tol"])
+        best, table = tune.tune_overlap_inner(
+            shape, cuts, precision=precision, tol=w["tol"],
+            progress=lambda r: log(f"{mode}: proxy o={r['overlap']} m={r['m']}: "
+                                   f"{r['sweeps']} sweeps, {r['seconds']:.2f} s"
+                                   + (" (stopped: slower than the best)" if r["stopped"] else "")))
         ov, m = best["overlap"], best["m"]
         ms.ms_set_overlap(h, ov)
         tuned = {"overlap": ov, "inner_iters": m,
@@ -182,11 +186,6 @@ def run_mode(args, torch, ms, w, mode: str):
     x = torch.zeros_like(b)
     if kind == "batch":
         ms.ms_reserve(h, nrhs)
-        if args.autotune:
-            from paper_2009_12638_amd import tune
-            log(f"{mode}: autotuning tiles and m")
-            tuned = tune.autotune(shape, cuts, b, precision=precision, refresh=True)
-            m = tuned["inner_iters"]
     tile_kw = {k: tuned[k] for k in ("rows", "x_chunk") if k in tuned}
 
     def step(k, **kw):
@@ -509,8 +508,8 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=4)
     ap.add_argument("--chunk", type=int, default=400, help="sweeps per call in --full-solve")
     ap.add_argument("--autotune", action="store_true",
-                    help="batched modes: pick tile shape and m with the autotuner first; "
-                         "ovl modes: pick the overlap depth and m")
+                    help="ovl and batched modes: pick the overlap depth and m first "
+                         "(proxy solves with the same block shapes)")
     ap.add_argument("--overlap", type=int, default=0,
                     help="overlap depth of the blocks in sync, async, batch and gmres modes")
     ap.add_argument("--ovl-depth", type=int, default=2,

@@ -101,6 +101,8 @@ struct ms_handle {
     std::vector<int> ev_class;
     int ev_used = 0;
     bool profiling = false;
+    double prof_ms[8] = {0};        // timed launches drained from the event pool
+    long long prof_n[8] = {0};
     std::string err;
 };
 
@@ -268,13 +270,30 @@ void free_all(ms_handle *h) {
 
 // ---- profiling -------------------------------------------------------
 
+// Moves the timings of the recorded launches into the per-class totals and
+// empties the event pool (waits for the last recorded launch).
+void prof_drain(ms_handle *h) {
+    if (h->ev_used >= 2) (void)hipEventSynchronize(h->ev[h->ev_used - 1]);
+    for (int s = 0; s + 1 < h->ev_used; s += 2) {
+        float ms_ = 0.f;
+        if (hipEventElapsedTime(&ms_, h->ev[s], h->ev[s + 1]) == hipSuccess) {
+            h->prof_ms[h->ev_class[s]] += ms_;
+            h->prof_n[h->ev_class[s]] += 1;
+        }
+    }
+    h->ev_used = 0;
+}
+
+// Times one launch (the scope around it) with a pair of events.  A full
+// pool is drained first, so every launch of a profiled solve is timed.
 struct Prof {
     ms_handle *h;
     hipStream_t st;
     int cls;
     int slot;
     Prof(ms_handle *h_, hipStream_t s, int c) : h(h_), st(s), cls(c), slot(-1) {
-        if (!h->profiling || h->ev_used + 2 > (int)h->ev.size()) return;
+        if (!h->profiling) return;
+        if (h->ev_used + 2 > (int)h->ev.size()) prof_drain(h);
         slot = h->ev_used;
         h->ev_used += 2;
         h->ev_class[slot] = cls;
@@ -287,19 +306,21 @@ struct Prof {
 
 void prof_collect(ms_handle *h, ms_stats *stats) {
     if (!h->profiling) return;
-    for (int s = 0; s + 1 < h->ev_used; s += 2) {
-        float ms_ = 0.f;
-        if (hipEventElapsedTime(&ms_, h->ev[s], h->ev[s + 1]) == hipSuccess && stats) {
-            stats->kernel_ms[h->ev_class[s]] += ms_;
-            stats->kernel_launches[h->ev_class[s]] += 1;
+    prof_drain(h);
+    for (int c = 0; c < 8; c++) {
+        if (stats) {
+            stats->kernel_ms[c] += h->prof_ms[c];
+            stats->kernel_launches[c] += h->prof_n[c];
         }
+        h->prof_ms[c] = 0.0;
+        h->prof_n[c] = 0;
     }
-    h->ev_used = 0;
 }
 
 ms_status prof_begin(ms_handle *h, bool on) {
     h->profiling = on;
     h->ev_used = 0;
+    for (int c = 0; c < 8; c++) { h->prof_ms[c] = 0.0; h->prof_n[c] = 0; }
     if (on && h->ev.empty()) {
         h->ev.resize(2 * kMaxEvents);
         h->ev_class.assign(2 * kMaxEvents, 0);

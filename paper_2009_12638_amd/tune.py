@@ -35,8 +35,8 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2009_1263
                              "tune.json")
 TILE_CANDIDATES = [(r, t) for r in (1, 2, 4) for t in (8, 16, 32)]
 INNER_CANDIDATES = (5, 10, 20, 40)
-OVERLAP_CANDIDATES = (0, 2, 4, 6, 8)
-OVERLAP_INNER_CANDIDATES = (10, 20, 30, 40)
+OVERLAP_CANDIDATES = (0, 2, 4, 6, 8, 12)
+OVERLAP_INNER_CANDIDATES = (10, 20, 30, 40, 60)
 
 
 def problem_key(shape, cuts, precision, nrhs=1) -> str:
@@ -125,7 +125,8 @@ def proxy_problem(shape, cuts, seed=7):
 
 
 def tune_overlap_inner(shape, cuts, precision="mixed", overlaps=OVERLAP_CANDIDATES,
-                       inners=OVERLAP_INNER_CANDIDATES, tol=1e-8, max_sweeps=20000):
+                       inners=OVERLAP_INNER_CANDIDATES, tol=1e-8, max_sweeps=20000,
+                       progress=None, cutoff=1.5, chunk=100):
     """(overlap depth, m) pair that reaches tol fastest (the paper tunes the
     overlap and the inner iterations by hand, Section 3.2).
 
@@ -133,11 +134,14 @@ def tune_overlap_inner(shape, cuts, precision="mixed", overlaps=OVERLAP_CANDIDAT
     win early, more win late), so short rate measurements mislead; instead
     every pair solves a proxy problem with the same block shapes
     (proxy_problem) to tol, and the pair with the shortest wall time wins.
-    Returns (best, results)."""
+    A pair still running after cutoff times the best time so far cannot win
+    and is stopped (converged False, stopped True).  progress, if given, is
+    called with each pair's result as it completes.  Returns (best, results)."""
     pshape, pcuts, b_host = proxy_problem(shape, cuts)
     b = b_host.to("cuda")
     h = ms.ms_create(pshape, cuts=pcuts)
     results = []
+    best_sec = None
     for ov in overlaps:
         ms.ms_set_overlap(h, ov)
         for m in inners:
@@ -146,12 +150,25 @@ def tune_overlap_inner(shape, cuts, precision="mixed", overlaps=OVERLAP_CANDIDAT
             x.zero_()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            s = ms.ms_solve(h, b, x, tol, m, "sync", max_sweeps=max_sweeps, precision=precision,
-                            raise_on_error=False)
+            total, stopped = 0, False
+            while True:   # in chunks (a solve resumed from x is the same solve)
+                s = ms.ms_solve(h, b, x, tol, m, "sync", max_sweeps=min(chunk, max_sweeps - total),
+                                precision=precision, raise_on_error=False)
+                total += s.sweeps
+                if s.status != ms.MS_ERR_NOT_CONVERGED or total >= max_sweeps:
+                    break
+                if best_sec is not None and time.perf_counter() - t0 > cutoff * best_sec:
+                    stopped = True
+                    break
             torch.cuda.synchronize()
             sec = time.perf_counter() - t0
             ok = s.status == ms.MS_OK
-            results.append(dict(overlap=ov, m=m, sweeps=s.sweeps, seconds=sec, converged=ok))
+            results.append(dict(overlap=ov, m=m, sweeps=total, seconds=sec, converged=ok,
+                                stopped=stopped))
+            if ok and (best_sec is None or sec < best_sec):
+                best_sec = sec
+            if progress:
+                progress(results[-1])
     ms.ms_destroy(h)
     done = [r for r in results if r["converged"]] or results
     best = min(done, key=lambda r: r["seconds"])

@@ -370,3 +370,28 @@ def test_z_vector_widths(orc, precision, widths):
                         z_vector=vz)
         assert e.value.status == ms.MS_ERR_ARG
     ms.ms_destroy(h)
+
+
+def test_profile_times_every_launch(orc):
+    """profile=1 times every launch, also when one host check covers more
+    launches than the event pool holds (here 8135, one launch per block and
+    phase): K sweeps over G groups of m inner iterations plus the final
+    check are (K+1)G residual, KGm stencil, KG(m-1) update, KG final and K+1
+    check launches; the profiled run is the same iterate as the plain one."""
+    torch = torch_cuda()
+    shape, cuts = (64, 64, 64), [inputs.uniform_cuts(64, 4)] * 3
+    b = dev(inputs.poisson_randn(shape, 150))
+    h = ms.ms_create(shape, cuts=[list(map(int, c)) for c in cuts])
+    K, m, G = 6, 10, 64
+    x1 = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    x2 = torch.zeros_like(x1)
+    say("profile launch counts")
+    st = ms.ms_solve(h, b, x1, 0.0, m, "sync", max_sweeps=K, group_blocks=1, profile=True,
+                     precision="mixed")
+    ms.ms_solve(h, b, x2, 0.0, m, "sync", max_sweeps=K, group_blocks=1, precision="mixed")
+    ms.ms_destroy(h)
+    n = st.kernel_launches
+    assert n["resid"] == (K + 1) * G and n["stencil"] == K * G * m, n
+    assert n["update"] == K * G * (m - 1) and n["final"] == K * G and n["check"] == K + 1, n
+    assert all(st.kernel_ms[k] > 0 for k in ("resid", "stencil", "update", "final", "check"))
+    assert torch.equal(x1, x2)
