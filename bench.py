@@ -186,7 +186,19 @@ def run_mode(args, torch, ms, w, mode: str):
     x = torch.zeros_like(b)
     if kind == "batch":
         ms.ms_reserve(h, nrhs)
-    tile_kw = {k: tuned[k] for k in ("rows", "x_chunk") if k in tuned}
+    if kind in ("ovl", "batch") and args.autotune:
+        # tile shape, then blocks per launch, on the real problem with the tuned m
+        tile, tiles = tune.tune_tiles(h, b, x, precision, m=m, sweeps=2)
+        log(f"{mode}: tiles rows {tile['rows']}, x chunk {tile['x_chunk']}: "
+            f"{tile['ms_per_sweep']:.1f} ms per sweep")
+        grp, grps = tune.tune_groups(h, b, x, precision, m=m, tile=tile)
+        log(f"{mode}: blocks per launch {grp['group_blocks']}: "
+            f"{grp['ms_per_sweep']:.1f} ms per sweep")
+        tuned.update(rows=tile["rows"], x_chunk=tile["x_chunk"],
+                     group_blocks=grp["group_blocks"],
+                     layout_table=[{k: (round(v, 2) if isinstance(v, float) else v)
+                                    for k, v in r.items()} for r in tiles + grps])
+    tile_kw = {k: tuned[k] for k in ("rows", "x_chunk", "group_blocks") if k in tuned}
 
     def step(k, **kw):
         if kind == "cg":
@@ -215,8 +227,9 @@ def run_mode(args, torch, ms, w, mode: str):
         res["overlap"] = ov
         res["region_cells"] = NR
     if tuned:
-        res["autotuned"] = {k: tuned[k] for k in ("rows", "x_chunk", "inner_iters", "overlap",
-                                                  "tune_seconds", "table") if k in tuned}
+        res["autotuned"] = {k: tuned[k] for k in ("rows", "x_chunk", "group_blocks",
+                                                  "inner_iters", "overlap", "tune_seconds",
+                                                  "table", "layout_table") if k in tuned}
     if kind == "cg":
         bpu = sum(CG_BYTES.values())
         res["GBps"] = round(bpu * N * args.steps / sec / 1e9, 1)

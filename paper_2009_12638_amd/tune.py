@@ -5,8 +5,10 @@ auto-tuning of such parameters as future work (Sections 3.2 and 5).  This
 module chooses, for one problem (grid, partition, precision, right-hand
 sides):
 
-* the tile shape (rows per thread, x chunk) by timing a few sweeps of each
-  candidate, and
+* the tile shape (rows per thread, x chunk) and the blocks per launch by
+  timing a few sweeps of each candidate,
+* the overlap depth together with m by solving a smaller proxy problem
+  with the same block shapes to tolerance for each pair, and
 * the number of inner CG iterations m by the residual reduction each
   candidate achieves per second of solve time, measured from a common
   iterate past the initial transient.
@@ -37,6 +39,7 @@ TILE_CANDIDATES = [(r, t) for r in (1, 2, 4) for t in (8, 16, 32)]
 INNER_CANDIDATES = (5, 10, 20, 40)
 OVERLAP_CANDIDATES = (0, 2, 4, 6, 8, 12)
 OVERLAP_INNER_CANDIDATES = (10, 20, 30, 40, 60)
+GROUP_CANDIDATES = (0, -1, 2, 4, 16)
 
 
 def problem_key(shape, cuts, precision, nrhs=1) -> str:
@@ -68,6 +71,30 @@ def tune_tiles(h, b, x, precision="mixed", m=10, sweeps=4, candidates=TILE_CANDI
         if best is None or ms_sweep < best["ms_per_sweep"]:
             best = results[-1]
     return best, results
+
+
+def tune_groups(h, b, x, precision="mixed", m=10, sweeps=2, tile=None,
+                candidates=GROUP_CANDIDATES):
+    """Fastest blocks-per-launch setting by wall time of `sweeps` synchronous
+    sweeps with the given tile shape: 0 = launch groups whose inner vectors
+    fit the on-package cache, -1 = every block in one launch per phase,
+    k > 0 = k blocks per launch.  Small groups re-read their vectors from the
+    cache but launch more often; which wins depends on the block sizes and
+    the number of right-hand sides."""
+    batch = b.dim() == 4
+    tile = tile or {}
+    results = []
+    for g in candidates:
+        kw = dict(precision=precision, group_blocks=g,
+                  **{k: tile[k] for k in ("rows", "x_chunk") if k in tile})
+        _run(h, b, x, 1, m, batch, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _run(h, b, x, sweeps, m, batch, **kw)
+        torch.cuda.synchronize()
+        results.append(dict(group_blocks=g,
+                            ms_per_sweep=1e3 * (time.perf_counter() - t0) / sweeps))
+    return min(results, key=lambda r: r["ms_per_sweep"]), results
 
 
 def tune_inner(h, b, precision="mixed", candidates=INNER_CANDIDATES, warm_res=0.05,
@@ -177,8 +204,9 @@ def tune_overlap_inner(shape, cuts, precision="mixed", overlaps=OVERLAP_CANDIDAT
 
 def autotune(shape, cuts, b, precision="mixed", cache=DEFAULT_CACHE, tune_m=True,
              refresh=False):
-    """Tuned options {rows, x_chunk, inner_iters} for this problem, from the
-    cache when present.  b: device tensor [nx,ny,nz] or [nrhs,nx,ny,nz]."""
+    """Tuned options {rows, x_chunk, group_blocks, inner_iters} for this
+    problem, from the cache when present.  b: device tensor [nx,ny,nz] or
+    [nrhs,nx,ny,nz]."""
     nrhs = b.shape[0] if b.dim() == 4 else 1
     key = problem_key(shape, cuts, precision, nrhs)
     db = {}
@@ -195,10 +223,12 @@ def autotune(shape, cuts, b, precision="mixed", cache=DEFAULT_CACHE, tune_m=True
         ms.ms_reserve(h, nrhs)
     x = torch.zeros_like(b)
     tile, tile_all = tune_tiles(h, b, x, precision)
-    out = dict(rows=tile["rows"], x_chunk=tile["x_chunk"], inner_iters=10,
-               ms_per_sweep=tile["ms_per_sweep"], tiles=tile_all)
+    grp, grp_all = tune_groups(h, b, x, precision, tile=tile)
+    out = dict(rows=tile["rows"], x_chunk=tile["x_chunk"], group_blocks=grp["group_blocks"],
+               inner_iters=10, ms_per_sweep=min(tile["ms_per_sweep"], grp["ms_per_sweep"]),
+               tiles=tile_all, groups=grp_all)
     if tune_m:
-        inner, inner_all = tune_inner(h, b, precision, tile=tile)
+        inner, inner_all = tune_inner(h, b, precision, tile=tile)   # with automatic groups
         out["inner_iters"] = inner["m"]
         out["inner"] = inner_all
     ms.ms_destroy(h)

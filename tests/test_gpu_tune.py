@@ -22,6 +22,7 @@ def test_autotune_valid_and_cached(tmp_path, orc):
     out = tune.autotune(shape, cuts, b, precision="mixed", cache=cache)
     assert out["rows"] in (1, 2, 4) and out["x_chunk"] in (8, 16, 32)
     assert out["inner_iters"] in tune.INNER_CANDIDATES
+    assert out["group_blocks"] in tune.GROUP_CANDIDATES
     assert os.path.exists(cache)
     again = tune.autotune(shape, cuts, b, precision="mixed", cache=cache)
     assert again == out
@@ -31,7 +32,7 @@ def test_autotune_valid_and_cached(tmp_path, orc):
     x2 = torch.zeros_like(x1)
     ms.ms_solve(h, b, x1, 0.0, 10, "sync", max_sweeps=6, precision="mixed")
     ms.ms_solve(h, b, x2, 0.0, 10, "sync", max_sweeps=6, precision="mixed",
-                rows=out["rows"], x_chunk=out["x_chunk"])
+                rows=out["rows"], x_chunk=out["x_chunk"], group_blocks=out["group_blocks"])
     d = float(torch.linalg.norm(x1 - x2) / torch.linalg.norm(x1))
     assert d <= 1e-5   # FP32 inner sums in a different tile order
 
