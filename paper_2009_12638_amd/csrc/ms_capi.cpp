@@ -106,6 +106,10 @@ struct ms_handle {
     std::string err;
 };
 
+namespace ms {
+thread_local LaunchEvents g_launch_events;
+}
+
 namespace {
 
 ms_status fail(ms_handle *h, ms_status s, const std::string &msg) {
@@ -271,12 +275,12 @@ void free_all(ms_handle *h) {
 // ---- profiling -------------------------------------------------------
 
 // Moves the timings of the recorded launches into the per-class totals and
-// empties the event pool (waits for the last recorded launch).
+// empties the event pool (waits for those launches).
 void prof_drain(ms_handle *h) {
-    if (h->ev_used >= 2) (void)hipEventSynchronize(h->ev[h->ev_used - 1]);
     for (int s = 0; s + 1 < h->ev_used; s += 2) {
         float ms_ = 0.f;
-        if (hipEventElapsedTime(&ms_, h->ev[s], h->ev[s + 1]) == hipSuccess) {
+        if (h->ev_class[s] >= 0 && hipEventSynchronize(h->ev[s + 1]) == hipSuccess &&
+            hipEventElapsedTime(&ms_, h->ev[s], h->ev[s + 1]) == hipSuccess) {
             h->prof_ms[h->ev_class[s]] += ms_;
             h->prof_n[h->ev_class[s]] += 1;
         }
@@ -284,23 +288,26 @@ void prof_drain(ms_handle *h) {
     h->ev_used = 0;
 }
 
-// Times one launch (the scope around it) with a pair of events.  A full
-// pool is drained first, so every launch of a profiled solve is timed.
+// Times the one launch in its scope with a pair of events attached to that
+// dispatch (kernel time alone).  A full pool is drained first, so every
+// launch of a profiled solve is timed; a scope that launched nothing leaves
+// its slot out.
 struct Prof {
     ms_handle *h;
-    hipStream_t st;
-    int cls;
     int slot;
-    Prof(ms_handle *h_, hipStream_t s, int c) : h(h_), st(s), cls(c), slot(-1) {
+    Prof(ms_handle *h_, hipStream_t, int c) : h(h_), slot(-1) {
         if (!h->profiling) return;
         if (h->ev_used + 2 > (int)h->ev.size()) prof_drain(h);
         slot = h->ev_used;
         h->ev_used += 2;
-        h->ev_class[slot] = cls;
-        (void)hipEventRecord(h->ev[slot], st);
+        h->ev_class[slot] = c;
+        ms::g_launch_events = {h->ev[slot], h->ev[slot + 1], true};
     }
     ~Prof() {
-        if (slot >= 0) (void)hipEventRecord(h->ev[slot + 1], st);
+        if (slot >= 0 && ms::g_launch_events.pending) {
+            ms::g_launch_events.pending = false;
+            h->ev_class[slot] = -1;
+        }
     }
 };
 

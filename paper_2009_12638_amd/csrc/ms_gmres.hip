@@ -594,7 +594,7 @@ template <typename T>
 hipError_t launch_gm_init(const Geom &g, int b0, int b1, const T *pT, Batch bt, GmArgs a,
                           Ctrl *ctrl, hipStream_t st) {
     if (b1 <= b0) return hipSuccess;
-    hipLaunchKernelGGL(k_gm_init<T>, wave_grid(b1 - b0, bt.nrhs), dim3(64), 0, st, g.blocks,
+    launch(k_gm_init<T>, wave_grid(b1 - b0, bt.nrhs), dim3(64), 0, st, g.blocks,
                        b0, b1 - b0, pT, bt, a, ctrl);
     return hipGetLastError();
 }
@@ -608,21 +608,21 @@ hipError_t launch_gm_step(const Geom &g, int vz, int t0, int t1, int b0, int b1,
     if (part == 0) {
         const dim3 grid = gm_batch_grid(t0, t1, bt);
         if (g.ovl) {
-            GM_DISPATCH(vz, hipLaunchKernelGGL((k_gm_apply<T, VZ, true>), grid, dim3(kThreads),
+            GM_DISPATCH(vz, launch((k_gm_apply<T, VZ, true>), grid, dim3(kThreads),
                                                0, st, g, t0, goff, V, j, bt, a, ctrl));
         } else {
-            GM_DISPATCH(vz, hipLaunchKernelGGL((k_gm_apply<T, VZ, false>), grid, dim3(kThreads),
+            GM_DISPATCH(vz, launch((k_gm_apply<T, VZ, false>), grid, dim3(kThreads),
                                                0, st, g, t0, goff, V, j, bt, a, ctrl));
         }
     } else if (part == 1) {
-        hipLaunchKernelGGL(k_gm_coef<T>, wave_grid(b1 - b0, bt.nrhs), dim3(64), 0, st, g.blocks,
+        launch(k_gm_coef<T>, wave_grid(b1 - b0, bt.nrhs), dim3(64), 0, st, g.blocks,
                            b0, b1 - b0, j, bt, a, ctrl);
     } else if (part == 2) {
         const dim3 grid = gm_batch_grid(t0, t1, bt);
-        GM_DISPATCH(vz, hipLaunchKernelGGL((k_gm_orth<T, VZ>), grid, dim3(kThreads), 0, st, g,
+        GM_DISPATCH(vz, launch((k_gm_orth<T, VZ>), grid, dim3(kThreads), 0, st, g,
                                            t0, goff, V, j, bt, a, ctrl));
     } else {
-        hipLaunchKernelGGL(k_gm_norm, wave_grid(b1 - b0, bt.nrhs), dim3(64), 0, st, g.blocks, b0,
+        launch(k_gm_norm, wave_grid(b1 - b0, bt.nrhs), dim3(64), 0, st, g.blocks, b0,
                            b1 - b0, j, inner_tol, bt, a, ctrl);
     }
     return hipGetLastError();
@@ -635,15 +635,15 @@ hipError_t launch_gm_finish(const Geom &g, int vz, int t0, int t1, int b0, int b
     if (t1 <= t0) return hipSuccess;
     if (g.rows != 1 || g.tx > kGmPlanes) return hipErrorInvalidValue;
     if (part == 0) {
-        hipLaunchKernelGGL(k_gm_solve, small_grid(b1 - b0, bt.nrhs), dim3(64), 0, st, b0,
+        launch(k_gm_solve, small_grid(b1 - b0, bt.nrhs), dim3(64), 0, st, b0,
                            b1 - b0, bt, a, ctrl);
     } else {
         const dim3 grid = gm_batch_grid(t0, t1, bt);
         if (g.ovl) {
-            GM_DISPATCH(vz, hipLaunchKernelGGL((k_gm_final<T, VZ, true>), grid, dim3(kThreads),
+            GM_DISPATCH(vz, launch((k_gm_final<T, VZ, true>), grid, dim3(kThreads),
                                                0, st, g, t0, goff, V, xa, xb, bt, a, ctrl));
         } else {
-            GM_DISPATCH(vz, hipLaunchKernelGGL((k_gm_final<T, VZ, false>), grid, dim3(kThreads),
+            GM_DISPATCH(vz, launch((k_gm_final<T, VZ, false>), grid, dim3(kThreads),
                                                0, st, g, t0, goff, V, xa, xb, bt, a, ctrl));
         }
     }
@@ -658,11 +658,11 @@ hipError_t launch_async_gmres(const Geom &g, int vz, int grid, const double *b, 
     if (grid < 1 || g.rows != 1 || g.tx > kGmPlanes || a.M > kGmMaxSteps)
         return hipErrorInvalidValue;
     if (g.ovl) {
-        GM_DISPATCH(vz, hipLaunchKernelGGL((k_async_gmres<T, VZ, true>), dim3(grid),
+        GM_DISPATCH(vz, launch((k_async_gmres<T, VZ, true>), dim3(grid),
                                            dim3(kAsyncThreads), 0, st, g, b, x, faces, V, as, m,
                                            S, max_sweeps, tol2, inner_tol, a, ctrl));
     } else {
-        GM_DISPATCH(vz, hipLaunchKernelGGL((k_async_gmres<T, VZ, false>), dim3(grid),
+        GM_DISPATCH(vz, launch((k_async_gmres<T, VZ, false>), dim3(grid),
                                            dim3(kAsyncThreads), 0, st, g, b, x, faces, V, as, m,
                                            S, max_sweeps, tol2, inner_tol, a, ctrl));
     }

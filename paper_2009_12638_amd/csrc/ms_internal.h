@@ -2,6 +2,7 @@
 // Not part of the public ABI (include/ms.h is).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 namespace ms {
@@ -98,6 +99,28 @@ struct AsyncState {
     const int *nbr;      // 6 neighbour blocks per block (-1 = none)
     int *finished;       // blocks that reached the sweep limit this launch
 };
+
+// ---- kernel launches ------------------------------------------------------
+// Profiling: the host sets events that the next launch of this thread
+// records its start and end into.  They are attached to the dispatch itself
+// (hipExtLaunchKernelGGL), so they time the kernel alone, without the gap
+// before it starts.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+    bool pending = false;
+};
+extern thread_local LaunchEvents g_launch_events;
+
+template <typename F, typename... Args>
+inline void launch(F kernel, dim3 grid, dim3 block, uint32_t shm, hipStream_t st, Args... args) {
+    if (g_launch_events.pending) {
+        g_launch_events.pending = false;
+        hipExtLaunchKernelGGL(kernel, grid, block, shm, st, g_launch_events.start,
+                              g_launch_events.stop, 0u, args...);
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, shm, st, args...);
+    }
+}
 
 // ---- launchers (ms_kernels.hip) ----------------------------------------
 // All launchers enqueue on `st` and return the launch error.

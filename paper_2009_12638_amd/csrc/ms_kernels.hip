@@ -190,7 +190,7 @@ __global__ __launch_bounds__(kThreads) void k_gcg_stencil(Geom g, const double *
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const Tile t = decode_tile<VZ, R>(g, tile, threadIdx.x);
     const double beta = iter > 0 ? scal[2] : 0.0;
-    const double acc = tile_stencil<double, VZ, R>(t, 0, r, pold, pnew, beta, iter > 0);
+    const double acc = tile_stencil_pf<double, VZ, R>(t, 0, r, pold, pnew, beta, iter > 0);
     const double s = wg_allsum<double, kThreads>(acc);
     if (threadIdx.x == 0) psig[tile] = s;
 }
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(kThreads) void k_gcg_update(Geom g, double *__restr
     if (ctrl->done) return;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const Tile t = decode_tile<VZ, R>(g, tile, threadIdx.x);
-    const double acc = tile_update<double, double, VZ, R>(t, 0, r, p, x, scal[1], true);
+    const double acc = tile_update_pf<double, double, VZ, R>(t, 0, r, p, x, scal[1], true);
     const double s = wg_allsum<double, kThreads>(acc);
     if (threadIdx.x == 0) prho[tile] = s;
 }
@@ -472,7 +472,7 @@ hipError_t launch_resid(const Geom &g, int vz, int t0, int t1, long long goff,
     if (t1 <= t0) return hipSuccess;
     const dim3 grid = batch_grid(t0, t1, bt);
 #define MS_RESID(STORE, OVL)                                                               \
-    MS_DISPATCH(vz, g.rows, hipLaunchKernelGGL((k_resid<T, VZ, RR, STORE, OVL>), grid,      \
+    MS_DISPATCH(vz, g.rows, launch((k_resid<T, VZ, RR, STORE, OVL>), grid,      \
                                                dim3(kThreads), 0, st, g, t0, goff, b, x,   \
                                                faces, r, p64, pT, ctrl, bt))
     if (r) {
@@ -491,7 +491,7 @@ hipError_t launch_stencil(const Geom &g, int vz, int t0, int t1, long long goff,
                           double inner_tol, Ctrl *ctrl, Batch bt, hipStream_t st) {
     if (t1 <= t0) return hipSuccess;
     const dim3 grid = batch_grid(t0, t1, bt);
-    MS_DISPATCH(vz, g.rows, hipLaunchKernelGGL((k_stencil<T, VZ, RR>), grid,
+    MS_DISPATCH(vz, g.rows, launch((k_stencil<T, VZ, RR>), grid,
                                                dim3(kThreads), 0, st, g, t0, goff, r, p_old,
                                                p_new, psig, prho_cur, prho_prev, prho0, active,
                                                iter, inner_tol, ctrl, bt));
@@ -506,7 +506,7 @@ hipError_t launch_update(const Geom &g, int vz, int t0, int t1, long long goff, 
     if (t1 <= t0) return hipSuccess;
     const dim3 grid = batch_grid(t0, t1, bt);
 #define MS_UPDATE(LAST, OVL)                                                                \
-    MS_DISPATCH(vz, g.rows, hipLaunchKernelGGL((k_update<T, VZ, RR, LAST, OVL>), grid,       \
+    MS_DISPATCH(vz, g.rows, launch((k_update<T, VZ, RR, LAST, OVL>), grid,       \
                                                dim3(kThreads), 0, st, g, t0, goff, r, p, d, \
                                                psig, prho_cur, prho_next, active, iter, xa, \
                                                xb, ctrl, bt))
@@ -525,12 +525,12 @@ hipError_t launch_async(const Geom &g, int vz, int grid, const double *b, double
                         double tol2, double inner_tol, Ctrl *ctrl, hipStream_t st) {
     if (grid < 1) return hipErrorInvalidValue;
     if (g.ovl) {
-        MS_DISPATCH_A(vz, g.rows, hipLaunchKernelGGL((k_async<T, VZ, RR, true>), dim3(grid),
+        MS_DISPATCH_A(vz, g.rows, launch((k_async<T, VZ, RR, true>), dim3(grid),
                                                      dim3(kAsyncThreads), 0, st, g, b, x, faces,
                                                      r, p0, p1, d, as, m, S, max_sweeps, tol2,
                                                      inner_tol, ctrl));
     } else {
-        MS_DISPATCH_A(vz, g.rows, hipLaunchKernelGGL((k_async<T, VZ, RR, false>), dim3(grid),
+        MS_DISPATCH_A(vz, g.rows, launch((k_async<T, VZ, RR, false>), dim3(grid),
                                                      dim3(kAsyncThreads), 0, st, g, b, x, faces,
                                                      r, p0, p1, d, as, m, S, max_sweeps, tol2,
                                                      inner_tol, ctrl));
@@ -554,7 +554,7 @@ hipError_t async_occupancy(int vz, int rows, int ovl, int *per_cu) {
 hipError_t launch_gcg_stencil(const Geom &g, int vz, int ntiles, const double *r,
                               const double *pold, double *pnew, double *psig, const double *scal,
                               int iter, const Ctrl *ctrl, hipStream_t st) {
-    MS_DISPATCH64(vz, g.rows, hipLaunchKernelGGL((k_gcg_stencil<VZ, RR>), dim3(ntiles),
+    MS_DISPATCH64(vz, g.rows, launch((k_gcg_stencil<VZ, RR>), dim3(ntiles),
                                                  dim3(kThreads), 0, st, g, r, pold, pnew, psig,
                                                  scal, iter, ctrl));
     return hipGetLastError();
@@ -563,7 +563,7 @@ hipError_t launch_gcg_stencil(const Geom &g, int vz, int ntiles, const double *r
 hipError_t launch_gcg_update(const Geom &g, int vz, int ntiles, double *r, const double *p,
                              double *x, double *prho, const double *scal, const Ctrl *ctrl,
                              hipStream_t st) {
-    MS_DISPATCH64(vz, g.rows, hipLaunchKernelGGL((k_gcg_update<VZ, RR>), dim3(ntiles),
+    MS_DISPATCH64(vz, g.rows, launch((k_gcg_update<VZ, RR>), dim3(ntiles),
                                                  dim3(kThreads), 0, st, g, r, p, x, prho, scal,
                                                  ctrl));
     return hipGetLastError();
@@ -572,7 +572,7 @@ hipError_t launch_gcg_update(const Geom &g, int vz, int ntiles, double *r, const
 hipError_t launch_gcg_reduce(const double *part, int ntiles, int which, double tol, int max_iters,
                              double *history, int history_cap, double *scal, Ctrl *ctrl,
                              hipStream_t st) {
-    hipLaunchKernelGGL(k_gcg_reduce, dim3(1), dim3(kThreads), 0, st, part, ntiles, which, tol,
+    launch(k_gcg_reduce, dim3(1), dim3(kThreads), 0, st, part, ntiles, which, tol,
                        max_iters, history, history_cap, scal, ctrl);
     return hipGetLastError();
 }
@@ -580,18 +580,18 @@ hipError_t launch_gcg_reduce(const double *part, int ntiles, int which, double t
 hipError_t launch_check(const double *p64, int ntiles, double tol, int final_check,
                         double *history, int history_cap, Ctrl *ctrl, Batch bt,
                         hipStream_t st) {
-    hipLaunchKernelGGL(k_check, dim3(bt.nrhs), dim3(kThreads), 0, st, p64, ntiles, tol,
+    launch(k_check, dim3(bt.nrhs), dim3(kThreads), 0, st, p64, ntiles, tol,
                        final_check, history, history_cap, ctrl, bt);
     return hipGetLastError();
 }
 
 hipError_t launch_norm(const double *p64, int ntiles, Ctrl *ctrl, hipStream_t st) {
-    hipLaunchKernelGGL(k_norm, dim3(1), dim3(kThreads), 0, st, p64, ntiles, ctrl);
+    launch(k_norm, dim3(1), dim3(kThreads), 0, st, p64, ntiles, ctrl);
     return hipGetLastError();
 }
 
 hipError_t launch_sum(const double *v, int n, double *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_sum, dim3(1), dim3(kThreads), 0, st, v, n, out);
+    launch(k_sum, dim3(1), dim3(kThreads), 0, st, v, n, out);
     return hipGetLastError();
 }
 
@@ -601,7 +601,7 @@ hipError_t launch_apply(long long nx, long long ny, long long nz, const double *
     long long grid = (n + kThreads - 1) / kThreads;
     if (grid > 65536) grid = 65536;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_apply, dim3((unsigned)grid), dim3(kThreads), 0, st, nx, ny, nz, u, y);
+    launch(k_apply, dim3((unsigned)grid), dim3(kThreads), 0, st, nx, ny, nz, u, y);
     return hipGetLastError();
 }
 

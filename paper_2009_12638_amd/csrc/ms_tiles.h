@@ -348,6 +348,276 @@ __device__ __forceinline__ T tile_update(const Tile &t, long long goff, T *__res
     return acc;
 }
 
+// ---- the two CG phases with their loads requested one plane ahead --------
+// Vector loads complete in order, so a value used in the iteration that
+// requests it makes the wavefront wait for every load issued before it.
+// These versions request, while plane i is computed, everything plane i + 1
+// needs (its x + 1 neighbour plane, its row and z neighbours held in memory,
+// and in the update phase its r and d), and take them up at the top of the
+// next iteration.  A wavefront then waits for loads that have had a whole
+// plane of compute to arrive.  Same arithmetic in the same order as
+// tile_stencil and tile_update.  Planes beyond the tile's last x + 1
+// neighbour are not requested.
+//
+// Used by the global CG, whose passes stream the whole grid from HBM
+// (measured at 512^3 FP64: update pass 1145 -> 1060 us).  The block phases
+// run on cache-sized groups whose data comes from the on-package cache at
+// lower latency; there the extra registers (lower occupancy) cost more
+// than the lookahead gains (measured: mixed sweep unchanged, FP64 sweep
+// 16.0 -> 17.9 ms), so they keep tile_stencil and tile_update.
+
+template <typename T, int VZ, int R>
+__device__ __forceinline__ T tile_stencil_pf(const Tile &t, long long goff,
+                                             const T *__restrict__ r, const T *__restrict__ pold,
+                                             T *__restrict__ pnew, T beta, bool use_old) {
+    const int bz = t.B.bz, by = t.B.by;
+    const int lim = min(t.B.bx, t.xend + 1);   // planes this tile reads
+    const long long P = (long long)by * bz;
+    const long long base = (t.B.off - goff) + (long long)t.j0 * bz + t.k;
+    const bool zm_in = t.zc > 0, zp_in = t.zc < t.tpr - 1;
+    const bool zm_sh = zm_in && t.lane > 0, zp_sh = zp_in && t.lane < 63;
+    const bool zm_mem = zm_in && !zm_sh, zp_mem = zp_in && !zp_sh;
+    const bool ym_ld = t.nrows > 0 && t.j0 > 0;
+    const bool yp_ld = t.nrows > 0 && t.j0 + t.nrows < by;
+    const bool ym_sh = t.lane >= t.tpr, yp_sh = t.lane + t.tpr < 64;
+    const bool ym_mem = ym_ld && !ym_sh, yp_mem = yp_ld && !yp_sh;
+    // p = r + beta p_old, formed where the value is used
+    auto comb = [&](T rv, T ov) -> T { return use_old ? rv + beta * ov : rv; };
+    // r and p_old of plane i on the owned rows (zero where there is none)
+    auto ld_plane = [&](int i, T(&a)[R][VZ], T(&c)[R][VZ]) {
+#pragma unroll
+        for (int rr = 0; rr < R; rr++) {
+#pragma unroll
+            for (int v = 0; v < VZ; v++) { a[rr][v] = T(0); c[rr][v] = T(0); }
+            if (rr < t.nrows && i < lim) {
+                const long long o = base + (long long)i * P + (long long)rr * bz;
+                vload<T, VZ>(r + o, a[rr]);
+                if (use_old) vload<T, VZ>(pold + o, c[rr]);
+            }
+        }
+    };
+    // row and z neighbours of plane i that come from memory
+    T yr[2][VZ], yo[2][VZ], zr[R][2], zo[R][2];
+#pragma unroll
+    for (int v = 0; v < VZ; v++) { yr[0][v] = yr[1][v] = yo[0][v] = yo[1][v] = T(0); }
+#pragma unroll
+    for (int rr = 0; rr < R; rr++) { zr[rr][0] = zr[rr][1] = zo[rr][0] = zo[rr][1] = T(0); }
+    auto ld_nbr = [&](int i) {
+        const long long o = base + (long long)i * P;
+        if (ym_mem) {
+            vload<T, VZ>(r + o - bz, yr[0]);
+            if (use_old) vload<T, VZ>(pold + o - bz, yo[0]);
+        }
+        if (yp_mem) {
+            vload<T, VZ>(r + o + (long long)t.nrows * bz, yr[1]);
+            if (use_old) vload<T, VZ>(pold + o + (long long)t.nrows * bz, yo[1]);
+        }
+#pragma unroll
+        for (int rr = 0; rr < R; rr++) {
+            if (rr >= t.nrows) continue;
+            const long long orow = o + (long long)rr * bz;
+            if (zm_mem) {
+                zr[rr][0] = r[orow - 1];
+                if (use_old) zo[rr][0] = pold[orow - 1];
+            }
+            if (zp_mem) {
+                zr[rr][1] = r[orow + VZ];
+                if (use_old) zo[rr][1] = pold[orow + VZ];
+            }
+        }
+    };
+    T pm[R][VZ], pc[R][VZ], nr[R][VZ], no[R][VZ];
+#pragma unroll
+    for (int rr = 0; rr < R; rr++)
+#pragma unroll
+        for (int v = 0; v < VZ; v++) pm[rr][v] = T(0);
+    {
+        T a[R][VZ], c[R][VZ];
+        if (t.xbeg > 0) {
+            ld_plane(t.xbeg - 1, a, c);
+#pragma unroll
+            for (int rr = 0; rr < R; rr++)
+#pragma unroll
+                for (int v = 0; v < VZ; v++) pm[rr][v] = comb(a[rr][v], c[rr][v]);
+        }
+        ld_plane(t.xbeg, a, c);
+#pragma unroll
+        for (int rr = 0; rr < R; rr++)
+#pragma unroll
+            for (int v = 0; v < VZ; v++) pc[rr][v] = comb(a[rr][v], c[rr][v]);
+    }
+    ld_plane(t.xbeg + 1, nr, no);
+    if (t.xbeg < t.xend) ld_nbr(t.xbeg);
+    T acc = T(0);
+    for (int i = t.xbeg; i < t.xend; i++) {
+        const long long o = base + (long long)i * P;
+        // take up what was requested for this plane
+        T pp[R][VZ], ym[VZ], yp[VZ], zmv[R], zpv[R];
+#pragma unroll
+        for (int rr = 0; rr < R; rr++)
+#pragma unroll
+            for (int v = 0; v < VZ; v++) pp[rr][v] = comb(nr[rr][v], no[rr][v]);
+#pragma unroll
+        for (int v = 0; v < VZ; v++) {
+            const T su = __shfl_up(pc[R - 1][v], t.tpr, 64);
+            const T sd = __shfl_down(pc[0][v], t.tpr, 64);
+            ym[v] = ym_ld ? (ym_sh ? su : comb(yr[0][v], yo[0][v])) : T(0);
+            yp[v] = yp_ld ? (yp_sh ? sd : comb(yr[1][v], yo[1][v])) : T(0);
+        }
+#pragma unroll
+        for (int rr = 0; rr < R; rr++) {
+            zmv[rr] = comb(zr[rr][0], zo[rr][0]);
+            zpv[rr] = comb(zr[rr][1], zo[rr][1]);
+        }
+        // request plane i + 1's data
+        ld_plane(i + 2, nr, no);
+        if (i + 1 < t.xend) ld_nbr(i + 1);
+#pragma unroll
+        for (int rr = 0; rr < R; rr++) {
+            const T sl = from_left(pc[rr][VZ - 1]);
+            const T sr = from_right(pc[rr][0]);
+            if (rr >= t.nrows) continue;
+            const long long orow = o + (long long)rr * bz;
+            T zm = T(0), zp = T(0);
+            if (zm_in) zm = zm_sh ? sl : zmv[rr];
+            if (zp_in) zp = zp_sh ? sr : zpv[rr];
+#pragma unroll
+            for (int v = 0; v < VZ; v++) {
+                const T left = v == 0 ? zm : pc[rr][v - 1];
+                const T right = v == VZ - 1 ? zp : pc[rr][v + 1];
+                const T up = rr == 0 ? ym[v] : pc[rr - 1][v];
+                const T down = (rr == R - 1 || rr + 1 == t.nrows) ? yp[v] : pc[rr + 1][v];
+                const T q = T(6) * pc[rr][v] - pm[rr][v] - pp[rr][v] - up - down - left - right;
+                acc += pc[rr][v] * q;
+            }
+            vstore<T, VZ>(pnew + orow, pc[rr]);
+        }
+#pragma unroll
+        for (int rr = 0; rr < R; rr++)
+#pragma unroll
+            for (int v = 0; v < VZ; v++) { pm[rr][v] = pc[rr][v]; pc[rr][v] = pp[rr][v]; }
+    }
+    return acc;
+}
+
+template <typename T, typename TD, int VZ, int R, bool OVL = false>
+__device__ __forceinline__ T tile_update_pf(const Tile &t, long long goff, T *__restrict__ r,
+                                            const T *__restrict__ p, TD *__restrict__ d, T alpha,
+                                            bool have_d) {
+    const int bz = t.B.bz, by = t.B.by;
+    const int lim = min(t.B.bx, t.xend + 1);   // planes of p this tile reads
+    const long long P = (long long)by * bz;
+    const long long base = (t.B.off - goff) + (long long)t.j0 * bz + t.k;
+    const bool zm_in = t.zc > 0, zp_in = t.zc < t.tpr - 1;
+    const bool zm_sh = zm_in && t.lane > 0, zp_sh = zp_in && t.lane < 63;
+    const bool zm_mem = zm_in && !zm_sh, zp_mem = zp_in && !zp_sh;
+    const bool ym_ld = t.nrows > 0 && t.j0 > 0;
+    const bool yp_ld = t.nrows > 0 && t.j0 + t.nrows < by;
+    const bool ym_sh = t.lane >= t.tpr, yp_sh = t.lane + t.tpr < 64;
+    const bool ym_mem = ym_ld && !ym_sh, yp_mem = yp_ld && !yp_sh;
+    // p of plane i on the owned rows (zero where there is none)
+    auto ld_p = [&](int i, T(&a)[R][VZ]) {
+#pragma unroll
+        for (int rr = 0; rr < R; rr++) {
+#pragma unroll
+            for (int v = 0; v < VZ; v++) a[rr][v] = T(0);
+            if (rr < t.nrows && i < lim)
+                vload<T, VZ>(p + base + (long long)i * P + (long long)rr * bz, a[rr]);
+        }
+    };
+    // r, d and the memory-held row and z neighbours of plane i
+    T nrv[R][VZ], yv[2][VZ], zv[R][2];
+    TD ndd[R][VZ];
+#pragma unroll
+    for (int v = 0; v < VZ; v++) { yv[0][v] = T(0); yv[1][v] = T(0); }
+#pragma unroll
+    for (int rr = 0; rr < R; rr++) {
+        zv[rr][0] = zv[rr][1] = T(0);
+#pragma unroll
+        for (int v = 0; v < VZ; v++) { nrv[rr][v] = T(0); ndd[rr][v] = TD(0); }
+    }
+    auto ld_aux = [&](int i) {
+        const long long o = base + (long long)i * P;
+        if (ym_mem) vload<T, VZ>(p + o - bz, yv[0]);
+        if (yp_mem) vload<T, VZ>(p + o + (long long)t.nrows * bz, yv[1]);
+#pragma unroll
+        for (int rr = 0; rr < R; rr++) {
+            if (rr >= t.nrows) continue;
+            const long long orow = o + (long long)rr * bz;
+            vload<T, VZ>(r + orow, nrv[rr]);
+            if (have_d) vload<TD, VZ>(d + orow, ndd[rr]);
+            if (zm_mem) zv[rr][0] = p[orow - 1];
+            if (zp_mem) zv[rr][1] = p[orow + VZ];
+        }
+    };
+    T pm[R][VZ], pc[R][VZ], pn[R][VZ];
+#pragma unroll
+    for (int rr = 0; rr < R; rr++)
+#pragma unroll
+        for (int v = 0; v < VZ; v++) pm[rr][v] = T(0);
+    if (t.xbeg > 0) ld_p(t.xbeg - 1, pm);
+    ld_p(t.xbeg, pc);
+    ld_p(t.xbeg + 1, pn);
+    if (t.xbeg < t.xend) ld_aux(t.xbeg);
+    T acc = T(0);
+    for (int i = t.xbeg; i < t.xend; i++) {
+        const long long o = base + (long long)i * P;
+        // take up what was requested for this plane
+        T pp[R][VZ], rv[R][VZ], ym[VZ], yp[VZ], zmv[R], zpv[R];
+        TD dd[R][VZ];
+#pragma unroll
+        for (int rr = 0; rr < R; rr++) {
+            zmv[rr] = zv[rr][0];
+            zpv[rr] = zv[rr][1];
+#pragma unroll
+            for (int v = 0; v < VZ; v++) {
+                pp[rr][v] = pn[rr][v];
+                rv[rr][v] = nrv[rr][v];
+                dd[rr][v] = have_d ? ndd[rr][v] : TD(0);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < VZ; v++) {
+            const T su = __shfl_up(pc[R - 1][v], t.tpr, 64);
+            const T sd = __shfl_down(pc[0][v], t.tpr, 64);
+            ym[v] = ym_ld ? (ym_sh ? su : yv[0][v]) : T(0);
+            yp[v] = yp_ld ? (yp_sh ? sd : yv[1][v]) : T(0);
+        }
+        // request plane i + 1's data
+        ld_p(i + 2, pn);
+        if (i + 1 < t.xend) ld_aux(i + 1);
+#pragma unroll
+        for (int rr = 0; rr < R; rr++) {
+            const T sl = from_left(pc[rr][VZ - 1]);
+            const T sr = from_right(pc[rr][0]);
+            if (rr >= t.nrows) continue;
+            const long long orow = o + (long long)rr * bz;
+            T zm = T(0), zp = T(0);
+            if (zm_in) zm = zm_sh ? sl : zmv[rr];
+            if (zp_in) zp = zp_sh ? sr : zpv[rr];
+#pragma unroll
+            for (int v = 0; v < VZ; v++) {
+                const T left = v == 0 ? zm : pc[rr][v - 1];
+                const T right = v == VZ - 1 ? zp : pc[rr][v + 1];
+                const T up = rr == 0 ? ym[v] : pc[rr - 1][v];
+                const T down = (rr == R - 1 || rr + 1 == t.nrows) ? yp[v] : pc[rr + 1][v];
+                T q = T(6) * pc[rr][v] - pm[rr][v] - pp[rr][v] - up - down - left - right;
+                if (OVL && axes_out(t.B, i, t.j0 + rr, t.k + v) > 1) q = T(0);
+                dd[rr][v] = dd[rr][v] + alpha * pc[rr][v];
+                rv[rr][v] = rv[rr][v] - alpha * q;
+                acc += rv[rr][v] * rv[rr][v];
+            }
+            vstore<TD, VZ>(d + orow, dd[rr]);
+            vstore<T, VZ>(r + orow, rv[rr]);
+        }
+#pragma unroll
+        for (int rr = 0; rr < R; rr++)
+#pragma unroll
+            for (int v = 0; v < VZ; v++) { pm[rr][v] = pc[rr][v]; pc[rr][v] = pp[rr][v]; }
+    }
+    return acc;
+}
+
 // Outer update on one tile (Section 3: X_i^(k) = X_i^(k-1) + correction):
 // xb = xa + d (when have_d) + alpha p (when use_p), in FP64.  xb may equal xa.
 // OVL: only the block's own cells are written (each cell takes its owner's
