@@ -165,39 +165,48 @@ def run_mode(args, torch, ms, w, mode: str):
     if kind == "gmres":
         ms.ms_reserve_krylov(h, m)
     tuned = {}
+    x = torch.zeros_like(b)
+    if kind == "batch":
+        ms.ms_reserve(h, nrhs)
     if kind in ("ovl", "batch") and args.autotune:
         from paper_2009_12638_amd import tune
         log(f"{mode}: autotuning overlap depth and m")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        best, table = tune.tune_overlap_inner(
-            shape, cuts, precision=precision, tol=w["tol"],
-            progress=lambda r: log(f"{mode}: proxy o={r['overlap']} m={r['m']}: "
-                                   f"{r['sweeps']} sweeps, {r['seconds']:.2f} s"
-                                   + (" (stopped: slower than the best)" if r["stopped"] else "")))
+
+        def show(r):
+            txt = f"{mode}: proxy o={r['overlap']} m={r['m']}: {r['sweeps']} sweeps, " \
+                  f"{r['seconds']:.2f} s"
+            if r["stopped"]:
+                txt += " (stopped: slower than the best)"
+            if "estimate" in r:
+                txt += f"; full size {r['full_ms_per_sweep']:.1f} ms per sweep, " \
+                       f"estimate {r['estimate']:.1f} s"
+            log(txt)
+
+        best, table = tune.tune_overlap_inner(shape, cuts, precision=precision, tol=w["tol"],
+                                              progress=show, full=(h, b, x))
         ov, m = best["overlap"], best["m"]
         ms.ms_set_overlap(h, ov)
+        x.zero_()
         tuned = {"overlap": ov, "inner_iters": m,
                  "tune_seconds": round(time.perf_counter() - t0, 2),
                  "table": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
                            for r in table]}
         log(f"{mode}: tuned overlap {ov}, m {m} in {tuned['tune_seconds']} s")
     NR = region_cells(shape, cuts, ov)   # cells the residual and inner kernels touch
-    x = torch.zeros_like(b)
-    if kind == "batch":
-        ms.ms_reserve(h, nrhs)
     if kind in ("ovl", "batch") and args.autotune:
-        # tile shape, then blocks per launch, on the real problem with the tuned m
-        tile, tiles = tune.tune_tiles(h, b, x, precision, m=m, sweeps=2)
-        log(f"{mode}: tiles rows {tile['rows']}, x chunk {tile['x_chunk']}: "
-            f"{tile['ms_per_sweep']:.1f} ms per sweep")
-        grp, grps = tune.tune_groups(h, b, x, precision, m=m, tile=tile)
-        log(f"{mode}: blocks per launch {grp['group_blocks']}: "
-            f"{grp['ms_per_sweep']:.1f} ms per sweep")
-        tuned.update(rows=tile["rows"], x_chunk=tile["x_chunk"],
-                     group_blocks=grp["group_blocks"],
+        # tile shape with blocks per launch, on the real problem with the tuned m
+        lay, lays = tune.tune_layout(
+            h, b, x, precision, m=m, sweeps=2,
+            progress=lambda r: log(f"{mode}: rows {r['rows']}, x chunk {r['x_chunk']}, "
+                                   f"blocks per launch {r['group_blocks']}: "
+                                   f"{r['ms_per_sweep']:.1f} ms per sweep"))
+        log(f"{mode}: layout rows {lay['rows']}, x chunk {lay['x_chunk']}, blocks per launch "
+            f"{lay['group_blocks']}: {lay['ms_per_sweep']:.1f} ms per sweep")
+        tuned.update(rows=lay["rows"], x_chunk=lay["x_chunk"], group_blocks=lay["group_blocks"],
                      layout_table=[{k: (round(v, 2) if isinstance(v, float) else v)
-                                    for k, v in r.items()} for r in tiles + grps])
+                                    for k, v in r.items()} for r in lays])
     tile_kw = {k: tuned[k] for k in ("rows", "x_chunk", "group_blocks") if k in tuned}
 
     def step(k, **kw):

@@ -97,7 +97,10 @@ typedef struct {
                              convergence flag (0 = automatic) */
     int32_t group_blocks; /* sync: blocks per launch.  0 = automatic: groups
                              whose inner vectors fill the 256 MB on-package
-                             cache; -1 = all blocks at once; > 0 = that many */
+                             cache (with several right-hand sides and CG, each
+                             launch covers as many right-hand sides of its
+                             blocks as fit); -1 = all blocks at once; > 0 =
+                             that many (every right-hand side in each launch) */
     int32_t x_chunk;      /* x planes marched per workgroup (0 = automatic) */
     int32_t profile;      /* 1: time each kernel class with HIP events */
     int32_t use_graph;    /* sync: 1 = replay sweeps from a captured HIP graph

@@ -45,6 +45,7 @@ struct Group {
     int b0, b1;     // blocks [b0, b1)
     int t0, t1;     // tiles [t0, t1)
     long long off;  // packed offset of block b0
+    int k0, k1;     // right-hand sides [k0, k1)
 };
 
 }  // namespace
@@ -378,6 +379,8 @@ Batch batch_of(const ms_handle *h, int nrhs) {
     bt.ps = h->tiles_cap;
     bt.bs = h->nblocks;
     bt.is = h->inner_n;
+    bt.k0 = 0;
+    bt.nk = nrhs;
     return bt;
 }
 
@@ -397,9 +400,35 @@ std::vector<Group> make_groups(const ms_handle *h, long long cap_cells) {
         g.b1 = b;
         g.t0 = g.t1 = 0;
         g.off = 0;
+        g.k0 = 0;
+        g.k1 = 1;
         gs.push_back(g);
     }
     return gs;
+}
+
+// (right-hand side, block) work items: every block group of `gs` is split
+// into launches of as many right-hand sides as keep the launch's inner
+// vectors within cap_cells (at least one), so a group's m inner iterations
+// re-read them from the on-package cache.  Returns the largest number of
+// right-hand sides in one launch.
+int split_rhs(const ms_handle *h, std::vector<Group> &gs, int nrhs, long long cap_cells) {
+    std::vector<Group> out;
+    int qmax = 1;
+    for (const Group &g : gs) {
+        long long cells = 0;
+        for (int b = g.b0; b < g.b1; b++) cells += block_cells(h, b);
+        const int q = (int)std::max(1ll, std::min<long long>(nrhs, cap_cells / std::max(1ll, cells)));
+        qmax = std::max(qmax, q);
+        for (int k = 0; k < nrhs; k += q) {
+            Group c = g;
+            c.k0 = k;
+            c.k1 = std::min(nrhs, k + q);
+            out.push_back(c);
+        }
+    }
+    gs.swap(out);
+    return qmax;
 }
 
 void fill_tiles(const ms_handle *h, std::vector<Group> &gs) {
@@ -481,6 +510,8 @@ ms_status enqueue_sweep(ms_handle *h, const std::vector<Group> &groups, const do
     Bufs<T> B = bufs<T>(h);
     const Faces F = faces(h);
     for (const Group &G : groups) {
+        bt.k0 = G.k0;          // this launch's right-hand sides
+        bt.nk = G.k1 - G.k0;
         {
             Prof p(h, st, MS_K_RESID);
             HIPCHK(h, ms::launch_resid<T>(g, vz, G.t0, G.t1, G.off, b, xa, F,
@@ -510,6 +541,8 @@ ms_status enqueue_sweep(ms_handle *h, const std::vector<Group> &groups, const do
             }
         }
     }
+    bt.k0 = 0;
+    bt.nk = bt.nrhs;
     {
         Prof p(h, st, MS_K_CHECK);
         HIPCHK(h, ms::launch_check(h->part64, h->ntiles, tol, final_only ? 1 : 0, h->history_d,
@@ -597,12 +630,28 @@ long long tile_capacity(const ms_handle *h) {
     return count_tiles(h, 1, kTxMin, 1, 0, h->nblocks);
 }
 
-void auto_tiling(const ms_handle *h, int vz, int nrhs, int b0, int b1, int *tx, int *rows) {
+// Tiling of the asynchronous workers (one workgroup sweeps a whole block):
+// the largest tiles that still give kMinTiles tiles in all.  Measured at
+// 512^3: within 5% of every other shape, the best without overlap.
+void async_tiling(const ms_handle *h, int vz, int nrhs, int b0, int b1, int *tx, int *rows) {
     for (int t : {32, 16, 8, 4})
         for (int r : {4, 2, 1})
             if (count_tiles(h, vz, t, r, b0, b1) * nrhs >= kMinTiles) { *tx = t; *rows = r; return; }
     *tx = kTxMin;
     *rows = 1;
+}
+
+// Tiling of the synchronous phase kernels: one row per thread and the
+// longest x march of 16, 8 or 4 planes that still gives kMinTiles
+// workgroups per launch.  Measured: rows 1 with 16 planes is the fastest
+// tile at 512^3 (mixed and FP64, with and without overlap), and larger
+// tiles (32 planes, 2 or 4 rows) were never faster, by up to 3.5x slower
+// on the uneven 16-right-hand-side workload where launches hold many tiles.
+void sync_tiling(const ms_handle *h, int vz, int nrhs, int b0, int b1, int *tx, int *rows) {
+    *rows = 1;
+    *tx = kTxMin;
+    for (int t : {16, 8, 4})
+        if (count_tiles(h, vz, t, 1, b0, b1) * nrhs >= kMinTiles) { *tx = t; return; }
 }
 
 // Inner-vector working set of one launch group: the on-package cache
@@ -693,12 +742,22 @@ ms_status solve_sync(ms_handle *h, const double *b, double *x, int nrhs, double 
         for (int bb = 0; bb < h->nblocks; bb++) mx = std::max(mx, block_cells(h, bb));
         cap_cells = mx * o.group_blocks;
     }
+    // several right-hand sides with CG inner solves and automatic groups:
+    // (right-hand side, block) launches, each within the cache budget
+    const bool rhs_items = nrhs > 1 && !gmres && o.group_blocks == 0;
+    if (rhs_items) cap_cells *= nrhs;
     std::vector<Group> groups = make_groups(h, cap_cells);
+    int per_launch = nrhs;   // right-hand sides in the largest launch
+    if (rhs_items) {
+        per_launch = split_rhs(h, groups, nrhs, cap_cells);
+    } else {
+        for (Group &G : groups) { G.k0 = 0; G.k1 = nrhs; }
+    }
     int gmax = 0;
     for (size_t q = 0; q < groups.size(); q++)
         if (groups[q].b1 - groups[q].b0 > groups[gmax].b1 - groups[gmax].b0) gmax = (int)q;
     int tx = 0, rows = 0;
-    auto_tiling(h, vz, nrhs, groups[gmax].b0, groups[gmax].b1, &tx, &rows);
+    sync_tiling(h, vz, per_launch, groups[gmax].b0, groups[gmax].b1, &tx, &rows);
     if (o.x_chunk > 0) tx = std::max(kTxMin, o.x_chunk);
     if (o.rows == 1 || o.rows == 2 || o.rows == 4) rows = o.rows;
     if (gmres) {
@@ -868,7 +927,7 @@ ms_status solve_async(ms_handle *h, const double *b, double *x, double tol, int 
                     "last ms_reserve / ms_set_overlap");
     const int vz = std::min(h->vzmax, (int)(16 / sizeof(T)));
     int tx = 0, rows = 0;
-    auto_tiling(h, vz, 1, 0, h->nblocks, &tx, &rows);
+    async_tiling(h, vz, 1, 0, h->nblocks, &tx, &rows);
     if (o.x_chunk > 0) tx = std::max(kTxMin, o.x_chunk);
     if (o.rows == 1 || o.rows == 2 || o.rows == 4) rows = o.rows;
     if (gmres) {   // GMRES tiles: one row per thread, at most gm_max_planes() planes

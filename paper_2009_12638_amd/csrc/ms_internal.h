@@ -73,9 +73,10 @@ struct Batch {
     long long ps;    // stride of per-tile partial arrays
     long long bs;    // stride of per-block arrays
     long long is;    // element stride between right-hand sides' inner vectors
+    int k0, nk;      // CG phase launches: right-hand sides [k0, k0 + nk)
 };
 
-inline Batch single_rhs() { return Batch{0, 1, 0, 0, 0, 0}; }
+inline Batch single_rhs() { return Batch{0, 1, 0, 0, 0, 0, 0, 1}; }
 
 // GMRES inner solves: per (right-hand side, block) records of the
 // Hessenberg/Givens state (doubles), per (right-hand side, tile) partial

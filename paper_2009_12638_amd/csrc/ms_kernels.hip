@@ -37,9 +37,10 @@ __global__ __launch_bounds__(kThreads) void k_resid(Geom g, int t0, long long go
                                                     Batch bt) {
     // workgroup w of the launch: right-hand side k, tile t0 + (w mod nt)
     const int w = xcd_tile(blockIdx.x, gridDim.x);
-    const int k = w / bt.nt;
+    const int kk = w / bt.nt;
+    const int k = bt.k0 + kk;
     if (ctrl && ctrl[k].done) return;
-    const int tile = t0 + (w - k * bt.nt);
+    const int tile = t0 + (w - kk * bt.nt);
     if (b) b += k * bt.vs;
     if (x) x += k * bt.vs;
     if (r) r += k * bt.is;
@@ -70,9 +71,10 @@ __global__ __launch_bounds__(kThreads) void k_stencil(Geom g, int t0, long long 
                                                       int *active, int iter, double inner_tol,
                                                       Ctrl *ctrl, Batch bt) {
     const int w = xcd_tile(blockIdx.x, gridDim.x);
-    const int k = w / bt.nt;
+    const int kk = w / bt.nt;
+    const int k = bt.k0 + kk;
     if (ctrl[k].done) return;
-    const int tile = t0 + (w - k * bt.nt);
+    const int tile = t0 + (w - kk * bt.nt);
     r += k * bt.is;
     pold += k * bt.is;
     pnew += k * bt.is;
@@ -117,10 +119,11 @@ __global__ __launch_bounds__(kThreads) void k_update(Geom g, int t0, long long g
                                                      double *__restrict__ xb, Ctrl *ctrl,
                                                      Batch bt) {
     const int w = xcd_tile(blockIdx.x, gridDim.x);
-    const int k = w / bt.nt;
+    const int kk = w / bt.nt;
+    const int k = bt.k0 + kk;
     ctrl += k;
     if (ctrl->done) return;
-    const int tile = t0 + (w - k * bt.nt);
+    const int tile = t0 + (w - kk * bt.nt);
     r += k * bt.is;
     p += k * bt.is;
     d += k * bt.is;
@@ -459,10 +462,10 @@ __global__ __launch_bounds__(kThreads) void k_apply(long long nx, long long ny, 
         default: return hipErrorInvalidValue;                         \
     }
 
-// Grid for tiles [t0, t1) of every right-hand side of the batch.
+// Grid for tiles [t0, t1) of right-hand sides [k0, k0 + nk) of the batch.
 inline dim3 batch_grid(int t0, int t1, Batch &bt) {
     bt.nt = t1 - t0;
-    return dim3((unsigned)((long long)bt.nt * bt.nrhs));
+    return dim3((unsigned)((long long)bt.nt * bt.nk));
 }
 
 template <typename T>

@@ -5,8 +5,8 @@ auto-tuning of such parameters as future work (Sections 3.2 and 5).  This
 module chooses, for one problem (grid, partition, precision, right-hand
 sides):
 
-* the tile shape (rows per thread, x chunk) and the blocks per launch by
-  timing a few sweeps of each candidate,
+* the tile shape (rows per thread, x chunk) together with the blocks per
+  launch by timing a few sweeps of each pair,
 * the overlap depth together with m by solving a smaller proxy problem
   with the same block shapes to tolerance for each pair, and
 * the number of inner CG iterations m by the residual reduction each
@@ -39,7 +39,7 @@ TILE_CANDIDATES = [(r, t) for r in (1, 2, 4) for t in (8, 16, 32)]
 INNER_CANDIDATES = (5, 10, 20, 40)
 OVERLAP_CANDIDATES = (0, 2, 4, 6, 8, 12)
 OVERLAP_INNER_CANDIDATES = (10, 20, 30, 40, 60)
-GROUP_CANDIDATES = (0, -1, 2, 4, 16)
+GROUP_CANDIDATES = (0, -1, 4, 16)
 
 
 def problem_key(shape, cuts, precision, nrhs=1) -> str:
@@ -54,46 +54,26 @@ def _run(h, b, x, sweeps, m, batch, **kw):
     return ms.ms_solve(h, b, x, 0.0, m, "sync", max_sweeps=sweeps, **kw)
 
 
-def tune_tiles(h, b, x, precision="mixed", m=10, sweeps=4, candidates=TILE_CANDIDATES):
-    """Fastest (rows, x_chunk) by wall time of `sweeps` synchronous sweeps."""
+def tune_layout(h, b, x, precision="mixed", m=10, sweeps=2, tiles=TILE_CANDIDATES,
+                groups=GROUP_CANDIDATES, progress=None):
+    """Fastest (rows, x_chunk, group_blocks) by wall time of `sweeps`
+    synchronous sweeps, over every pair of tile shape and blocks per launch
+    (the two interact: a grouping that is fast with one tile shape can be
+    slow with another).  progress, if given, is called with each result."""
     batch = b.dim() == 4
-    best = None
     results = []
-    for rows, tx in candidates:
-        kw = dict(precision=precision, rows=rows, x_chunk=tx)
-        _run(h, b, x, 1, m, batch, **kw)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _run(h, b, x, sweeps, m, batch, **kw)
-        torch.cuda.synchronize()
-        ms_sweep = 1e3 * (time.perf_counter() - t0) / sweeps
-        results.append(dict(rows=rows, x_chunk=tx, ms_per_sweep=ms_sweep))
-        if best is None or ms_sweep < best["ms_per_sweep"]:
-            best = results[-1]
-    return best, results
-
-
-def tune_groups(h, b, x, precision="mixed", m=10, sweeps=2, tile=None,
-                candidates=GROUP_CANDIDATES):
-    """Fastest blocks-per-launch setting by wall time of `sweeps` synchronous
-    sweeps with the given tile shape: 0 = launch groups whose inner vectors
-    fit the on-package cache, -1 = every block in one launch per phase,
-    k > 0 = k blocks per launch.  Small groups re-read their vectors from the
-    cache but launch more often; which wins depends on the block sizes and
-    the number of right-hand sides."""
-    batch = b.dim() == 4
-    tile = tile or {}
-    results = []
-    for g in candidates:
-        kw = dict(precision=precision, group_blocks=g,
-                  **{k: tile[k] for k in ("rows", "x_chunk") if k in tile})
-        _run(h, b, x, 1, m, batch, **kw)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _run(h, b, x, sweeps, m, batch, **kw)
-        torch.cuda.synchronize()
-        results.append(dict(group_blocks=g,
-                            ms_per_sweep=1e3 * (time.perf_counter() - t0) / sweeps))
+    for rows, tx in tiles:
+        for g in groups:
+            kw = dict(precision=precision, rows=rows, x_chunk=tx, group_blocks=g)
+            _run(h, b, x, 1, m, batch, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _run(h, b, x, sweeps, m, batch, **kw)
+            torch.cuda.synchronize()
+            results.append(dict(rows=rows, x_chunk=tx, group_blocks=g,
+                                ms_per_sweep=1e3 * (time.perf_counter() - t0) / sweeps))
+            if progress:
+                progress(results[-1])
     return min(results, key=lambda r: r["ms_per_sweep"]), results
 
 
@@ -104,7 +84,8 @@ def tune_inner(h, b, precision="mixed", candidates=INNER_CANDIDATES, warm_res=0.
     under the default m), each for about budget_s seconds."""
     batch = b.dim() == 4
     tile = tile or {}
-    kw = dict(precision=precision, **{k: tile[k] for k in ("rows", "x_chunk") if k in tile})
+    kw = dict(precision=precision,
+              **{k: tile[k] for k in ("rows", "x_chunk", "group_blocks") if k in tile})
     x0 = torch.zeros_like(b)
     if batch:
         ms.ms_solve_batch(h, b, x0, warm_res, 10, raise_on_error=False, max_sweeps=warm_max,
@@ -153,17 +134,26 @@ def proxy_problem(shape, cuts, seed=7):
 
 def tune_overlap_inner(shape, cuts, precision="mixed", overlaps=OVERLAP_CANDIDATES,
                        inners=OVERLAP_INNER_CANDIDATES, tol=1e-8, max_sweeps=20000,
-                       progress=None, cutoff=1.5, chunk=100):
+                       progress=None, cutoff=1.5, chunk=100, full=None):
     """(overlap depth, m) pair that reaches tol fastest (the paper tunes the
     overlap and the inner iterations by hand, Section 3.2).
 
     The convergence curves of different pairs cross (few inner iterations
     win early, more win late), so short rate measurements mislead; instead
     every pair solves a proxy problem with the same block shapes
-    (proxy_problem) to tol, and the pair with the shortest wall time wins.
-    A pair still running after cutoff times the best time so far cannot win
-    and is stopped (converged False, stopped True).  progress, if given, is
-    called with each pair's result as it completes.  Returns (best, results)."""
+    (proxy_problem) to tol.  A pair still running after cutoff times the
+    best time so far cannot win and is stopped (converged False, stopped
+    True).
+
+    full = (handle, b, x) of the real problem: the proxy then only supplies
+    each pair's sweep count, and the cost of a sweep is timed on the real
+    problem (two sweeps with that overlap and m; its overlap is left at the
+    last candidate).  The proxy's blocks are mostly at the grid boundary,
+    with fewer overlap slabs than interior blocks, so its own sweep times
+    understate deep overlaps.  The pair with the smallest sweeps x real
+    sweep time wins ("estimate" in the results).  Without full, the proxy's
+    wall time decides.  progress, if given, is called with each pair's
+    result as it completes.  Returns (best, results)."""
     pshape, pcuts, b_host = proxy_problem(shape, cuts)
     b = b_host.to("cuda")
     h = ms.ms_create(pshape, cuts=pcuts)
@@ -190,15 +180,27 @@ def tune_overlap_inner(shape, cuts, precision="mixed", overlaps=OVERLAP_CANDIDAT
             torch.cuda.synchronize()
             sec = time.perf_counter() - t0
             ok = s.status == ms.MS_OK
-            results.append(dict(overlap=ov, m=m, sweeps=total, seconds=sec, converged=ok,
-                                stopped=stopped))
+            r = dict(overlap=ov, m=m, sweeps=total, seconds=sec, converged=ok, stopped=stopped)
             if ok and (best_sec is None or sec < best_sec):
                 best_sec = sec
+            if full is not None and ok:
+                fh, fb, fx = full
+                ms.ms_set_overlap(fh, ov)
+                batch = fb.dim() == 4
+                _run(fh, fb, fx, 1, m, batch, precision=precision)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                _run(fh, fb, fx, 2, m, batch, precision=precision)
+                torch.cuda.synchronize()
+                r["full_ms_per_sweep"] = 1e3 * (time.perf_counter() - t1) / 2
+                r["estimate"] = total * r["full_ms_per_sweep"] / 1e3
+            results.append(r)
             if progress:
-                progress(results[-1])
+                progress(r)
     ms.ms_destroy(h)
     done = [r for r in results if r["converged"]] or results
-    best = min(done, key=lambda r: r["seconds"])
+    key = "estimate" if full is not None and all("estimate" in r for r in done) else "seconds"
+    best = min(done, key=lambda r: r[key])
     return best, results
 
 
@@ -222,13 +224,11 @@ def autotune(shape, cuts, b, precision="mixed", cache=DEFAULT_CACHE, tune_m=True
     if nrhs > 1:
         ms.ms_reserve(h, nrhs)
     x = torch.zeros_like(b)
-    tile, tile_all = tune_tiles(h, b, x, precision)
-    grp, grp_all = tune_groups(h, b, x, precision, tile=tile)
-    out = dict(rows=tile["rows"], x_chunk=tile["x_chunk"], group_blocks=grp["group_blocks"],
-               inner_iters=10, ms_per_sweep=min(tile["ms_per_sweep"], grp["ms_per_sweep"]),
-               tiles=tile_all, groups=grp_all)
+    lay, lay_all = tune_layout(h, b, x, precision)
+    out = dict(rows=lay["rows"], x_chunk=lay["x_chunk"], group_blocks=lay["group_blocks"],
+               inner_iters=10, ms_per_sweep=lay["ms_per_sweep"], layouts=lay_all)
     if tune_m:
-        inner, inner_all = tune_inner(h, b, precision, tile=tile)   # with automatic groups
+        inner, inner_all = tune_inner(h, b, precision, tile=lay)
         out["inner_iters"] = inner["m"]
         out["inner"] = inner_all
     ms.ms_destroy(h)

@@ -92,9 +92,11 @@ def test_adaptive_inner_iterations_replay(orc):
 
 def test_tune_overlap_and_inner(orc):
     """The (overlap, m) tuner solves a proxy with the same block shapes for
-    every pair and returns the fastest converged one; the proxy keeps the
-    block shapes; a solve of the real problem with the chosen pair matches
-    the oracle's overlapping block Jacobi with the same m."""
+    every pair; with the real problem given it times each pair's sweep there
+    and returns the pair with the smallest proxy sweeps x real sweep time;
+    the proxy keeps the block shapes; a solve of the real problem with the
+    chosen pair matches the oracle's overlapping block Jacobi with the same
+    m."""
     torch = torch_cuda()
     from paper_2009_12638_amd import tune
     shape, cuts = (48, 40, 36), ([0, 16, 32, 48], [0, 20, 40], [0, 12, 24, 36])
@@ -107,8 +109,17 @@ def test_tune_overlap_and_inner(orc):
     assert best["seconds"] == min(r["seconds"] for r in results if r["converged"])
     b = inputs.poisson_randn(shape, 143)
     h = ms.ms_create(shape, cuts=[list(c) for c in cuts])
-    ms.ms_set_overlap(h, best["overlap"])
     x = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    say("tune overlap and m, real sweep times")
+    best, results = tune.tune_overlap_inner(shape, cuts, precision="mixed", overlaps=(0, 2),
+                                            inners=(5, 10), tol=1e-6, full=(h, dev(b), x))
+    done = [r for r in results if r["converged"]]
+    assert best in done and all(r["full_ms_per_sweep"] > 0 for r in done)
+    assert best["estimate"] == min(r["estimate"] for r in done)
+    for r in done:
+        assert r["estimate"] == pytest.approx(r["sweeps"] * r["full_ms_per_sweep"] / 1e3)
+    ms.ms_set_overlap(h, best["overlap"])
+    x.zero_()
     st = ms.ms_solve(h, dev(b), x, 1e-8, best["m"], "sync")
     ms.ms_destroy(h)
     beff = orc.lift_bc(b, [None] * 6)
