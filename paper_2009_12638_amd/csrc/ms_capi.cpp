@@ -452,7 +452,7 @@ ms::GmArgs gm_args(const ms_handle *h) {
 }
 
 // One sweep with GMRES(m) inner solves: per group, the residual (written as
-// the first, unscaled Krylov vector), m Arnoldi steps of four launches, the
+// the first, unscaled Krylov vector), m Arnoldi steps of three launches, the
 // per-block triangular solves and x_new = x_old + V y on own cells.
 template <typename T>
 ms_status enqueue_sweep_gmres(ms_handle *h, const std::vector<Group> &groups, const double *b,
@@ -476,9 +476,9 @@ ms_status enqueue_sweep_gmres(ms_handle *h, const std::vector<Group> &groups, co
             Prof p(h, st, MS_K_HESS);
             HIPCHK(h, ms::launch_gm_init<T>(g, G.b0, G.b1, B.pT, bt, a, h->ctrl, st));
         }
-        static const int cls[4] = {MS_K_STENCIL, MS_K_HESS, MS_K_ORTH, MS_K_HESS};
+        static const int cls[3] = {MS_K_STENCIL, MS_K_ORTH, MS_K_HESS};
         for (int j = 0; j < m; j++)
-            for (int part = 0; part < 4; part++) {
+            for (int part = 0; part < 3; part++) {
                 Prof p(h, st, cls[part]);
                 HIPCHK(h, ms::launch_gm_step<T>(g, vz, G.t0, G.t1, G.b0, G.b1, G.off, V, j,
                                                 inner_tol, bt, a, h->ctrl, st, part));

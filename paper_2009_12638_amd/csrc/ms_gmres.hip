@@ -6,13 +6,14 @@
 //
 // Krylov vectors are stored unscaled: u_0 = r, u_{j+1} = A v_j minus its
 // projections, with v_i = u_i / s_i and s_i = ||u_i|| kept per block, so
-// no pass is spent normalising.  One Arnoldi step j is four launches:
+// no pass is spent normalising.  One Arnoldi step j is three launches:
 //   k_gm_apply  w = A v_j on every tile (7-point stencil, zero outside the
 //               block's box, masked outside an overlap region), stored as
 //               u_{j+1}; per-tile partials of (w, u_i), i <= j, from the w
 //               values still in registers;
-//   k_gm_coef   per block: h_ij = (w, u_i) / s_i in a fixed tile order;
-//   k_gm_orth   u_{j+1} = w - sum_i (h_ij / s_i) u_i (classical
+//   k_gm_orth   h_ij = (w, u_i) / s_i from the block's partials in a fixed
+//               tile order (each workgroup sums them itself), then
+//               u_{j+1} = w - sum_i (h_ij / s_i) u_i (classical
 //               Gram-Schmidt: all coefficients from the same w), per-tile
 //               partials of its squared norm;
 //   k_gm_norm   per block: h_{j+1,j} = s_{j+1}; the Givens rotations of
@@ -62,7 +63,7 @@ template <typename T>
 __device__ __forceinline__ double block_sum(const T *part, long long stride, int slot,
                                             int tile0, int ntiles) {
     double s = 0.0;
-    for (int t = threadIdx.x; t < ntiles; t += 64)
+    for (int t = threadIdx.x & 63; t < ntiles; t += 64)
         s += (double)part[(long long)(tile0 + t) * stride + slot];
     return wave_sum(s);
 }
@@ -373,28 +374,11 @@ __global__ __launch_bounds__(kThreads) void k_gm_apply(Geom g, int t0, long long
                                     a.gpart + ((long long)k * bt.ps + tile) * a.gstride);
 }
 
-// Arnoldi step j, part 2 (per block): h_ij = (w, u_i) / s_i, i <= j.
-template <typename T>
-__global__ __launch_bounds__(64) void k_gm_coef(const BlockInfo *blocks, int b0, int nb, int j,
-                                                Batch bt, GmArgs a, Ctrl *ctrl) {
-    const int k = blockIdx.x / nb, b = b0 + blockIdx.x % nb;
-    if (ctrl[k].done) return;
-    const GmRec R{a.M};
-    double *st = rec(a.gm, a, k, b);
-    if (st[R.active()] == 0.0) return;
-    const BlockInfo &B = blocks[b];
-    const double *part = a.gpart + (long long)k * bt.ps * a.gstride;
-    for (int i = 0; i <= j; i++) {
-        const double h = block_sum(part, a.gstride, i, B.tile0, B.ntiles) / st[R.s() + i];
-        if (threadIdx.x == 0) {
-            st[R.R() + i * a.M + j] = h;
-            st[R.coef() + i] = h / st[R.s() + i];
-        }
-    }
-}
-
-// Arnoldi step j, part 3: u_{j+1} = w - sum_i (h_ij / s_i) u_i and
-// partials of its squared norm.
+// Arnoldi step j, part 2: h_ij = (w, u_i) / s_i, i <= j, from the block's
+// tile partials (every workgroup of the block sums them in the same fixed
+// order, each wavefront every fourth coefficient; the block's first tile
+// records them), then u_{j+1} = w - sum_i (h_ij / s_i) u_i and partials of
+// its squared norm.
 template <typename T, int VZ>
 __global__ __launch_bounds__(kThreads) void k_gm_orth(Geom g, int t0, long long goff, T *V, int j,
                                                       Batch bt, GmArgs a, Ctrl *ctrl) {
@@ -404,15 +388,27 @@ __global__ __launch_bounds__(kThreads) void k_gm_orth(Geom g, int t0, long long 
     const int tile = t0 + (w - k * bt.nt);
     const Tile t = decode_tile<VZ, 1>(g, tile, threadIdx.x);
     const GmRec R{a.M};
-    const double *st = rec(a.gm, a, k, t.b);
+    double *st = rec(a.gm, a, k, t.b);
     if (st[R.active()] == 0.0) return;
-    const T acc = tile_gm_orth<T, VZ>(t, goff, V, a.kvs, (long long)k * bt.is, j,
-                                      st + R.coef());
+    __shared__ double coef[kGmMaxSteps];
+    const double *part = a.gpart + (long long)k * bt.ps * a.gstride;
+    for (int i = (int)threadIdx.x >> 6; i <= j; i += kThreads / 64) {
+        const double h = block_sum(part, a.gstride, i, t.B.tile0, t.B.ntiles) / st[R.s() + i];
+        if ((threadIdx.x & 63) == 0) {
+            coef[i] = h / st[R.s() + i];
+            if (t.first) {
+                st[R.R() + i * a.M + j] = h;
+                st[R.coef() + i] = coef[i];
+            }
+        }
+    }
+    __syncthreads();
+    const T acc = tile_gm_orth<T, VZ>(t, goff, V, a.kvs, (long long)k * bt.is, j, coef);
     const T s = wg_allsum<T, kThreads>(acc);
     if (threadIdx.x == 0) a.gpart[((long long)k * bt.ps + tile) * a.gstride + a.M + 1] = (double)s;
 }
 
-// Arnoldi step j, part 4 (per block): h_{j+1,j} = ||u_{j+1}||, Givens
+// Arnoldi step j, part 3 (per block): h_{j+1,j} = ||u_{j+1}||, Givens
 // rotations of column j, least-squares residual and the stopping rules
 // (m steps, inner_tol, an invariant Krylov space).
 __global__ __launch_bounds__(64) void k_gm_norm(const BlockInfo *blocks, int b0, int nb, int j,
@@ -615,9 +611,6 @@ hipError_t launch_gm_step(const Geom &g, int vz, int t0, int t1, int b0, int b1,
                                                0, st, g, t0, goff, V, j, bt, a, ctrl));
         }
     } else if (part == 1) {
-        launch(k_gm_coef<T>, wave_grid(b1 - b0, bt.nrhs), dim3(64), 0, st, g.blocks,
-                           b0, b1 - b0, j, bt, a, ctrl);
-    } else if (part == 2) {
         const dim3 grid = gm_batch_grid(t0, t1, bt);
         GM_DISPATCH(vz, launch((k_gm_orth<T, VZ>), grid, dim3(kThreads), 0, st, g,
                                            t0, goff, V, j, bt, a, ctrl));

@@ -192,8 +192,8 @@ hipError_t launch_sum(const double *v, int n, double *out, hipStream_t st);
 // ---- GMRES inner solves (ms_gmres.hip) ----------------------------------
 // Tiles must be one row per thread and at most gm_max_planes() x planes.
 // init: beta = ||r|| per block of [b0, b1) from the residual's region
-// partials pT.  step part 0..3 of Arnoldi step j: apply + dots, per-block
-// coefficients, orthogonalisation + norm partials, per-block norm and
+// partials pT.  step part 0..2 of Arnoldi step j: apply + dots,
+// coefficients + orthogonalisation + norm partials, per-block norm and
 // Givens rotation.  finish part 0: per-block triangular solve; part 1:
 // x_new = x_old + correction on own cells.
 template <typename T>
