@@ -44,9 +44,12 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2009_12638_amd", "csrc", f)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_bumps512_sync_mixed.json")
 HBM_PEAK_GBPS = 8000.0
 ALL_MODES = ["sync-mixed", "sync-fp64", "async-mixed", "async-fp64", "cg-fp64",
-             "batch-mixed", "batch-fp64", "gmres-mixed", "gmres-fp64", "ovl-mixed", "ovl-fp64"]
-DEFAULT_MODES = "sync-mixed,sync-fp64,async-mixed,cg-fp64,ovl-mixed,gmres-mixed,batch-mixed"
+             "batch-mixed", "batch-fp64", "gmres-mixed", "gmres-fp64", "ovl-mixed", "ovl-fp64",
+             "grad-fp64", "grad-mixed"]
+DEFAULT_MODES = ("sync-mixed,sync-fp64,async-mixed,cg-fp64,ovl-mixed,gmres-mixed,batch-mixed,"
+                 "grad-fp64")
 BATCH_WORKLOAD = "uneven384"   # batched modes: 16 right-hand sides, uneven blocks
+DIFF_WORKLOAD = "diff128"      # grad modes: forward + adjoint solve, 4^3 blocks of 32^3
 
 
 def log(*a):
@@ -145,6 +148,55 @@ def per_kernel(prof, N, byte_lists, extra=None, cells=None):
                      "unknowns_per_launch": int(round(N * passes / launches)),
                      "bytes_per_unknown": lst}
     return out
+
+
+def grad_mode(args, torch, ms, mode: str):
+    """One step = the differentiable solve of a least-squares loss: the
+    forward solve to the workload's tol and, in backward, the adjoint solve
+    (A is symmetric) to its adjoint tol, through torch.autograd."""
+    from paper_2009_12638_amd import autograd, inputs
+    precision = "mixed" if mode.endswith("mixed") else "fp64"
+    T = 4 if precision == "mixed" else 8
+    w = inputs.workload(DIFF_WORKLOAD)
+    shape, cuts = w["shape"], w["cuts"]
+    N = shape[0] * shape[1] * shape[2]
+    m = args.grad_m or w["m"]
+    ov = args.grad_overlap
+    solver = autograd.PoissonSolver(shape, cuts=[list(map(int, c)) for c in cuts], tol=w["tol"],
+                                    inner_iters=m, precision=precision,
+                                    adjoint_tol=w["adjoint_tol"], overlap=ov)
+    f = torch.tensor(w["f"], device="cuda", requires_grad=True)
+    faces = [torch.tensor(g, device="cuda", requires_grad=True) for g in w["faces"]]
+    ut = torch.tensor(w["ut"], device="cuda")
+
+    def step():
+        f.grad = None
+        for g in faces:
+            g.grad = None
+        u = solver(f, faces)
+        ((u - ut) ** 2).sum().backward()
+
+    log(f"{mode}: warmup 1")
+    step()
+    K = max(1, min(args.steps, 3))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        step()
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    fs, ad = solver.stats["forward"], solver.stats["adjoint"]
+    log(f"{mode}: {K} forward + adjoint solves in {sec:.3f} s "
+        f"({fs.sweeps} + {ad.sweeps} sweeps)")
+    NR = region_cells(shape, cuts, ov)
+    fin = dict(kernel_bytes(m, T))["final"]
+    per_sweep = (sweep_bytes(m, T, False) - fin) * NR + fin * N
+    return {"mode": mode, "workload": DIFF_WORKLOAD, "steps": K, "seconds": round(sec, 4),
+            "ms_per_step": round(1e3 * sec / K, 3), "inner_iters": m, "overlap": ov,
+            "forward_sweeps": fs.sweeps, "adjoint_sweeps": ad.sweeps,
+            "forward_rel_residual": fs.rel_residual, "adjoint_rel_residual": ad.rel_residual,
+            "tol": w["tol"], "adjoint_tol": w["adjoint_tol"],
+            "GBps": round(per_sweep * (fs.sweeps + ad.sweeps) * K / sec / 1e9, 1)}
 
 
 def run_mode(args, torch, ms, w, mode: str):
@@ -532,6 +584,9 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="ovl and batched modes: pick the overlap depth and m first "
                          "(proxy solves with the same block shapes)")
+    ap.add_argument("--grad-m", type=int, default=0,
+                    help="grad modes: inner iterations (0 = the workload's)")
+    ap.add_argument("--grad-overlap", type=int, default=0, help="grad modes: overlap depth")
     ap.add_argument("--overlap", type=int, default=0,
                     help="overlap depth of the blocks in sync, async, batch and gmres modes")
     ap.add_argument("--ovl-depth", type=int, default=2,
@@ -584,7 +639,9 @@ def main():
     results = {}
     wb = None
     for mo in modes:
-        if mo.startswith("batch"):
+        if mo.startswith("grad"):
+            results[mo] = grad_mode(args, torch, ms, mo)
+        elif mo.startswith("batch"):
             if wb is None:
                 log(f"building inputs for {BATCH_WORKLOAD}")
                 wb = inputs.workload(BATCH_WORKLOAD)

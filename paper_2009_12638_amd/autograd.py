@@ -25,13 +25,19 @@ class PoissonSolver:
     with zero boundary data for the adjoint solve.  adjoint_tol (default tol)
     is the relative residual the adjoint solve stops at: its solution can be
     far larger than its right-hand side (up to 1/lambda_min times), which
-    raises the FP64 residual floor of that solve above the forward one's."""
+    raises the FP64 residual floor of that solve above the forward one's.
+    overlap > 0 solves both on overlapping blocks of that depth.  stats holds
+    the ms.Stats of the last forward and adjoint solves."""
 
     def __init__(self, shape, blocks=None, cuts=None, tol=1e-12, inner_iters=10,
-                 precision="fp64", mode="sync", max_sweeps=200000, adjoint_tol=None):
+                 precision="fp64", mode="sync", max_sweeps=200000, adjoint_tol=None,
+                 overlap=0):
         self.shape = tuple(int(s) for s in shape)
         self.h_fwd = ms.ms_create(self.shape, blocks=blocks, cuts=cuts)
         self.h_adj = ms.ms_create(self.shape, blocks=blocks, cuts=cuts)
+        if overlap:
+            ms.ms_set_overlap(self.h_fwd, int(overlap))
+            ms.ms_set_overlap(self.h_adj, int(overlap))
         self.tol = tol
         self.adjoint_tol = tol if adjoint_tol is None else adjoint_tol
         self.m = inner_iters
@@ -39,11 +45,12 @@ class PoissonSolver:
         self.mode = mode
         self.max_sweeps = max_sweeps
         self.spacing = 1.0 / (self.shape[0] + 1)
+        self.stats = {}
 
-    def _solve(self, handle, rhs, tol):
+    def _solve(self, handle, rhs, tol, which):
         x = torch.zeros(self.shape, dtype=torch.float64, device=rhs.device)
-        ms.ms_solve(handle, rhs.contiguous(), x, tol, self.m, self.mode,
-                    precision=self.precision, max_sweeps=self.max_sweeps)
+        self.stats[which] = ms.ms_solve(handle, rhs.contiguous(), x, tol, self.m, self.mode,
+                                        precision=self.precision, max_sweeps=self.max_sweeps)
         return x
 
     def __call__(self, f, faces):
@@ -56,7 +63,7 @@ class PoissonSolve(torch.autograd.Function):
         h2 = solver.spacing ** 2
         face_list = [None if g is None else g.detach().contiguous() for g in faces]
         ms.ms_set_bc(solver.h_fwd, face_list)
-        u = solver._solve(solver.h_fwd, (h2 * f.detach()).contiguous(), solver.tol)
+        u = solver._solve(solver.h_fwd, (h2 * f.detach()).contiguous(), solver.tol, "forward")
         ctx.solver = solver
         ctx.has_face = [g is not None for g in faces]
         return u
@@ -64,7 +71,8 @@ class PoissonSolve(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_u):
         solver = ctx.solver
-        lam = solver._solve(solver.h_adj, grad_u.detach().contiguous(), solver.adjoint_tol)
+        lam = solver._solve(solver.h_adj, grad_u.detach().contiguous(), solver.adjoint_tol,
+                            "adjoint")
         h2 = solver.spacing ** 2
         grad_f = h2 * lam
         # dL/dg for the faces -x, +x, -y, +y, -z, +z

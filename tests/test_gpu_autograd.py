@@ -33,13 +33,20 @@ def _loss_and_grads(solver, f, g, ut):
     return L.item(), host(ft.grad), [host(a.grad) for a in gt], host(u)
 
 
-def test_adjoint_gradient_matches_dense_solve():
+@pytest.mark.parametrize("overlap,precision", [(0, "fp64"), (2, "fp64"), (2, "mixed")])
+def test_adjoint_gradient_matches_dense_solve(overlap, precision):
+    """Forward and adjoint solves (plain or overlapping blocks, FP64 or mixed
+    refinement) against the dense solve's gradient; the solver reports both
+    solves' stats."""
     from paper_2009_12638_amd.autograd import PoissonSolver
     n = 12
     f, g, ut = _problem(n, 50)
-    solver = PoissonSolver((n, n, n), cuts=[[0, 6, 12]] * 3, tol=1e-13, inner_iters=10)
-    say("autograd dense 12^3")
+    solver = PoissonSolver((n, n, n), cuts=[[0, 6, 12]] * 3, tol=1e-13, inner_iters=10,
+                           overlap=overlap, precision=precision)
+    say("autograd dense 12^3", overlap, precision)
     L, gf, gg, u = _loss_and_grads(solver, f, g, ut)
+    assert set(solver.stats) == {"forward", "adjoint"}
+    assert all(st.status == 0 and st.rel_residual <= 1e-13 for st in solver.stats.values())
     # dense reference
     A = dense_laplacian(n, n, n)
     h2 = (1.0 / (n + 1)) ** 2
