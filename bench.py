@@ -260,6 +260,8 @@ def run_mode(args, torch, ms, w, mode: str):
                      layout_table=[{k: (round(v, 2) if isinstance(v, float) else v)
                                     for k, v in r.items()} for r in lays])
     tile_kw = {k: tuned[k] for k in ("rows", "x_chunk", "group_blocks") if k in tuned}
+    if args.inner_tol > 0 and kind in ("sync", "async", "ovl", "batch"):
+        tile_kw["inner_tol"] = args.inner_tol
 
     def step(k, **kw):
         if kind == "cg":
@@ -271,7 +273,7 @@ def run_mode(args, torch, ms, w, mode: str):
             return ms.ms_solve(h, b, x, 0.0, m, "sync", max_sweeps=k, precision=precision,
                                inner="gmres", **kw)
         return ms.ms_solve(h, b, x, 0.0, m, "sync" if kind == "ovl" else kind, max_sweeps=k,
-                           precision=precision, **kw)
+                           precision=precision, **tile_kw, **kw)
 
     log(f"{mode}: warmup {args.warmup}")
     if args.warmup > 0:
@@ -284,6 +286,8 @@ def run_mode(args, torch, ms, w, mode: str):
     log(f"{mode}: {args.steps} steps in {sec:.3f} s")
     res = {"mode": mode, "steps": args.steps, "seconds": round(sec, 4),
            "ms_per_step": round(1e3 * sec / args.steps, 4), "nrhs": nrhs, "inner_iters": m}
+    if args.inner_tol > 0:
+        res["inner_tol"] = args.inner_tol   # GBps assume m iterations: an upper bound here
     if ov:
         res["overlap"] = ov
         res["region_cells"] = NR
@@ -347,14 +351,15 @@ def run_mode(args, torch, ms, w, mode: str):
         else:
             # in chunks so progress is printed; a sweep resumed from x is the
             # same sweep (the whole outer state is x)
-            total = 0
-            extra = {"inner": "gmres"} if kind == "gmres" else {}
+            total = inner_total = 0
+            extra = {"inner": "gmres"} if kind == "gmres" else dict(tile_kw)
             while True:
                 fs = ms.ms_solve(h, b, x, w["tol"], m,
                                  "sync" if kind in ("gmres", "ovl") else kind,
                                  precision=precision, max_sweeps=args.chunk,
                                  raise_on_error=False, **extra)
                 total += fs.sweeps
+                inner_total += fs.inner_iters
                 if fs.status == ms.MS_OK:
                     break
                 if fs.status != ms.MS_ERR_NOT_CONVERGED or total > 200000:
@@ -364,6 +369,9 @@ def run_mode(args, torch, ms, w, mode: str):
         torch.cuda.synchronize()
         res["time_to_tol_s"] = round(time.perf_counter() - t0, 3)
         res["sweeps_to_tol"] = total
+        if kind in ("sync", "async", "ovl") and total > 0:
+            nb = (len(cuts[0]) - 1) * (len(cuts[1]) - 1) * (len(cuts[2]) - 1)
+            res["mean_inner_iters"] = round(inner_total / (total * nb), 2)
         if kind == "batch":
             rels = [ms.ms_residual(h, b[k].contiguous(), x[k].contiguous())[0] for k in range(nrhs)]
             rel = max(rels)
@@ -584,6 +592,9 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="ovl and batched modes: pick the overlap depth and m first "
                          "(proxy solves with the same block shapes)")
+    ap.add_argument("--inner-tol", type=float, default=0.0,
+                    help="sync, async, ovl and batch modes: also stop a block's CG once its "
+                         "residual fell by this factor (with --m as the cap)")
     ap.add_argument("--grad-m", type=int, default=0,
                     help="grad modes: inner iterations (0 = the workload's)")
     ap.add_argument("--grad-overlap", type=int, default=0, help="grad modes: overlap depth")

@@ -105,7 +105,9 @@ typedef struct {
     int32_t profile;      /* 1: time each kernel class with HIP events */
     int32_t use_graph;    /* sync: 1 = replay sweeps from a captured HIP graph
                              (default 1) */
-    int32_t rows;         /* y rows each thread owns: 1, 2 or 4 (0 = automatic) */
+    int32_t rows;         /* y rows each thread owns: 1, 2 or 4 (0 = automatic);
+                             asynchronous CG workers take at most 2 (1 with
+                             4-cell z vectors) */
     int32_t workers;      /* async: persistent workgroups, each sweeping one block
                              at a time (0 = automatic) */
     int32_t inner_solver; /* ms_inner (default MS_INNER_CG).  MS_INNER_GMRES

@@ -630,13 +630,21 @@ long long tile_capacity(const ms_handle *h) {
     return count_tiles(h, 1, kTxMin, 1, 0, h->nblocks);
 }
 
-// Tiling of the asynchronous workers (one workgroup sweeps a whole block):
-// the largest tiles that still give kMinTiles tiles in all.  Measured at
-// 512^3: within 5% of every other shape, the best without overlap.
+// Rows per thread the asynchronous CG worker fits in the 128 registers a
+// 1024-thread workgroup allows: 2 with 2-cell z vectors, 1 with wider ones.
+int async_max_rows(int vz) { return vz >= 4 ? 1 : 2; }
+
+// Tiling of the asynchronous CG workers (one workgroup sweeps a whole
+// block): the largest tiles within async_max_rows that still give
+// kMinTiles tiles in all.
 void async_tiling(const ms_handle *h, int vz, int nrhs, int b0, int b1, int *tx, int *rows) {
     for (int t : {32, 16, 8, 4})
-        for (int r : {4, 2, 1})
-            if (count_tiles(h, vz, t, r, b0, b1) * nrhs >= kMinTiles) { *tx = t; *rows = r; return; }
+        for (int r : {2, 1})
+            if (r <= async_max_rows(vz) && count_tiles(h, vz, t, r, b0, b1) * nrhs >= kMinTiles) {
+                *tx = t;
+                *rows = r;
+                return;
+            }
     *tx = kTxMin;
     *rows = 1;
 }
@@ -929,7 +937,7 @@ ms_status solve_async(ms_handle *h, const double *b, double *x, double tol, int 
     int tx = 0, rows = 0;
     async_tiling(h, vz, 1, 0, h->nblocks, &tx, &rows);
     if (o.x_chunk > 0) tx = std::max(kTxMin, o.x_chunk);
-    if (o.rows == 1 || o.rows == 2 || o.rows == 4) rows = o.rows;
+    if (o.rows == 1 || o.rows == 2 || o.rows == 4) rows = std::min(o.rows, async_max_rows(vz));
     if (gmres) {   // GMRES tiles: one row per thread, at most gm_max_planes() planes
         rows = 1;
         tx = std::min(tx, ms::gm_max_planes());

@@ -163,13 +163,16 @@ struct AsyncShared {
 // eligible right now, -2 once the worker should exit (stop flag, or every
 // block reached the launch's sweep limit).  sh.gap: the largest version gap
 // to a neighbour this sweep will see.
+// NT: threads of the calling workgroup (at most kAsyncThreads).
+template <int NT>
 __device__ __forceinline__ int async_claim(const Geom &g, AsyncState as, int S, int max_sweeps,
                                            Ctrl *ctrl, AsyncShared &sh) {
+    static_assert(NT <= kAsyncThreads && NT % 64 == 0, "workgroup size");
     const int tid = threadIdx.x;
     const int nb = g.nblocks;
     // ---- the eligible unclaimed block with the lowest version ----
     unsigned long long best = ~0ull;
-    for (int c = tid; c < nb; c += kAsyncThreads) {
+    for (int c = tid; c < nb; c += NT) {
         const int blk = (c + (int)blockIdx.x * 7) % nb;   // spread the start per worker
         if (__hip_atomic_load(&as.claim[blk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) continue;
         const int v = __hip_atomic_load(&as.version[blk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -193,7 +196,7 @@ __device__ __forceinline__ int async_claim(const Geom &g, AsyncState as, int S, 
     __syncthreads();
     if (tid == 0) {
         unsigned long long k = ~0ull;
-        for (int w = 0; w < kAsyncThreads / 64; w++) k = sh.key[w] < k ? sh.key[w] : k;
+        for (int w = 0; w < NT / 64; w++) k = sh.key[w] < k ? sh.key[w] : k;
         int pick = -1;
         if (__hip_atomic_load(&ctrl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
             k = ~0ull;       // the residual estimate is below tol: start nothing new

@@ -459,18 +459,18 @@ __global__ __launch_bounds__(kThreads) void k_gm_final(Geom g, int t0, long long
 // asynchronous sweeps with GMRES inner solves
 // ----------------------------------------------------------------------
 
-// Persistent worker (kAsyncThreads threads): takes one block at a time like
+// Persistent worker (kAsyncGmThreads threads): takes one block at a time like
 // the CG worker (staleness-bounded, latest values in memory, Sections 2.1
 // and 2.3), runs a GMRES(m) cycle on it with the Arnoldi dots reduced inside
 // the workgroup, and updates the block's own cells of x in place.  Block
 // records of right-hand side 0 hold the Hessenberg/Givens state.
 template <typename T, int VZ, bool OVL>
-__global__ __launch_bounds__(kAsyncThreads) void k_async_gmres(
+__global__ __launch_bounds__(kAsyncGmThreads) void k_async_gmres(
     Geom g, const double *__restrict__ b, double *x, Faces F, T *V, AsyncState as, int m, int S,
     int max_sweeps, double tol2, double inner_tol, GmArgs a, Ctrl *ctrl) {
-    constexpr int kSubs = kAsyncThreads / kThreads;
+    constexpr int kSubs = kAsyncGmThreads / kThreads;
     __shared__ AsyncShared sh;
-    __shared__ T red[kAsyncThreads / 64][kDotBatch];
+    __shared__ T red[kAsyncGmThreads / 64][kDotBatch];
     __shared__ double sdot[kGmMaxSteps + 2];
     __shared__ double scoef[kGmMaxSteps + 1];
     __shared__ int sflag;
@@ -480,7 +480,7 @@ __global__ __launch_bounds__(kAsyncThreads) void k_async_gmres(
     const int nb = g.nblocks;
     const GmRec R{a.M};
     for (;;) {
-        const int blk = async_claim(g, as, S, max_sweeps, ctrl, sh);
+        const int blk = async_claim<kAsyncGmThreads>(g, as, S, max_sweeps, ctrl, sh);
         if (blk == -2) return;
         if (blk < 0) {
             __builtin_amdgcn_s_sleep(2);
@@ -495,8 +495,8 @@ __global__ __launch_bounds__(kAsyncThreads) void k_async_gmres(
             const Tile t = decode_tile<VZ, 1>(g, B.tile0 + lt, ltid);
             tile_resid<T, VZ, 1, true, OVL>(g, t, 0, b, x, F, V, acc64, accT);
         }
-        const double res2 = wg_allsum<double, kAsyncThreads>(acc64);
-        const double beta = sqrt((double)wg_allsum<T, kAsyncThreads>(accT));
+        const double res2 = wg_allsum<double, kAsyncGmThreads>(acc64);
+        const double beta = sqrt((double)wg_allsum<T, kAsyncGmThreads>(accT));
         if (tid == 0) {
             __hip_atomic_store(&as.board[blk], res2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             st[R.s()] = beta;
@@ -524,7 +524,7 @@ __global__ __launch_bounds__(kAsyncThreads) void k_async_gmres(
                 if (live)
                     tile_gm_apply<T, VZ, OVL>(t, 0, V + (long long)j * a.kvs,
                                               V + (long long)(j + 1) * a.kvs, inv_s, wv);
-                gm_dots<T, VZ, kAsyncThreads, true>(t, live, 0, V, a.kvs, 0, j, wv, red, sdot);
+                gm_dots<T, VZ, kAsyncGmThreads, true>(t, live, 0, V, a.kvs, 0, j, wv, red, sdot);
             }
             if (tid == 0)
                 for (int i = 0; i <= j; i++) {
@@ -539,7 +539,7 @@ __global__ __launch_bounds__(kAsyncThreads) void k_async_gmres(
                 const Tile t = decode_tile<VZ, 1>(g, B.tile0 + lt, ltid);
                 nacc += tile_gm_orth<T, VZ>(t, 0, V, a.kvs, 0, j, scoef);
             }
-            const double hn = sqrt((double)wg_allsum<T, kAsyncThreads>(nacc));
+            const double hn = sqrt((double)wg_allsum<T, kAsyncGmThreads>(nacc));
             if (tid == 0) sflag = gm_givens(st, R, a.M, j, hn, inner_tol) > 0 ? 1 : 0;
             __syncthreads();
         }
@@ -652,11 +652,11 @@ hipError_t launch_async_gmres(const Geom &g, int vz, int grid, const double *b, 
         return hipErrorInvalidValue;
     if (g.ovl) {
         GM_DISPATCH(vz, launch((k_async_gmres<T, VZ, true>), dim3(grid),
-                                           dim3(kAsyncThreads), 0, st, g, b, x, faces, V, as, m,
+                                           dim3(kAsyncGmThreads), 0, st, g, b, x, faces, V, as, m,
                                            S, max_sweeps, tol2, inner_tol, a, ctrl));
     } else {
         GM_DISPATCH(vz, launch((k_async_gmres<T, VZ, false>), dim3(grid),
-                                           dim3(kAsyncThreads), 0, st, g, b, x, faces, V, as, m,
+                                           dim3(kAsyncGmThreads), 0, st, g, b, x, faces, V, as, m,
                                            S, max_sweeps, tol2, inner_tol, a, ctrl));
     }
     return hipGetLastError();
@@ -667,10 +667,10 @@ hipError_t async_gmres_occupancy(int vz, int ovl, int *per_cu) {
     *per_cu = 0;
     if (ovl) {
         GM_DISPATCH(vz, return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                            per_cu, (const void *)k_async_gmres<T, VZ, true>, kAsyncThreads, 0));
+                            per_cu, (const void *)k_async_gmres<T, VZ, true>, kAsyncGmThreads, 0));
     } else {
         GM_DISPATCH(vz, return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                            per_cu, (const void *)k_async_gmres<T, VZ, false>, kAsyncThreads, 0));
+                            per_cu, (const void *)k_async_gmres<T, VZ, false>, kAsyncGmThreads, 0));
     }
     return hipSuccess;
 }

@@ -8,7 +8,9 @@
 namespace ms {
 
 constexpr int kThreads = 256;       // threads per workgroup in the tiled kernels
-constexpr int kAsyncThreads = 512;  // threads per persistent asynchronous worker
+constexpr int kAsyncThreads = 1024;   // threads per persistent asynchronous CG worker
+constexpr int kAsyncGmThreads = 512;  // threads per asynchronous GMRES worker (its w tiles
+                                      // need more than the 128 registers 1024 threads allow)
 
 // One block of the partition (Section 3: the unknowns X_i of one block).
 // The box [i0, i0+bx) x [j0, j0+by) x [k0, k0+bz) is the block's inner-solve

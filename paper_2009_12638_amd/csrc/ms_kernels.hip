@@ -292,7 +292,7 @@ __global__ __launch_bounds__(kAsyncThreads) void k_async(Geom g, const double *_
     const int ltid = tid % kThreads;
     const int nb = g.nblocks;
     for (;;) {
-        const int blk = async_claim(g, as, S, max_sweeps, ctrl, sh);
+        const int blk = async_claim<kAsyncThreads>(g, as, S, max_sweeps, ctrl, sh);
         if (blk == -2) return;                      // stop flag, or every block finished
         if (blk < 0) {                              // nothing eligible right now
             __builtin_amdgcn_s_sleep(2);
