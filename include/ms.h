@@ -102,7 +102,10 @@ typedef struct {
                              blocks as fit); -1 = all blocks at once; > 0 =
                              that many (every right-hand side in each launch) */
     int32_t x_chunk;      /* x planes marched per workgroup (0 = automatic) */
-    int32_t profile;      /* 1: time each kernel class with HIP events */
+    int32_t profile;      /* 1: time every launch with HIP events attached to
+                             its dispatch (kernel time alone), summed per
+                             kernel class into ms_stats; sweeps are then
+                             launched one by one instead of from a graph */
     int32_t use_graph;    /* sync: 1 = replay sweeps from a captured HIP graph
                              (default 1) */
     int32_t rows;         /* y rows each thread owns: 1, 2 or 4 (0 = automatic);
@@ -128,8 +131,9 @@ enum {
                          (GMRES: x_new = x + V y)                        */
     MS_K_CHECK = 4,   /* global residual sum and convergence test          */
     MS_K_OTHER = 5,
-    MS_K_ORTH = 6,    /* GMRES: Gram-Schmidt orthogonalisation + norm     */
-    MS_K_HESS = 7,    /* GMRES: per-block Hessenberg, Givens and solve     */
+    MS_K_ORTH = 6,    /* GMRES: Hessenberg column, Gram-Schmidt
+                         orthogonalisation and norm                        */
+    MS_K_HESS = 7,    /* GMRES: per-block start, Givens rotations, solve   */
     MS_K_COUNT = 8
 };
 
