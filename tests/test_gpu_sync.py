@@ -397,27 +397,31 @@ def test_profile_times_every_launch(orc):
     assert torch.equal(x1, x2)
 
 
-@pytest.mark.parametrize("precision,chunks", [("fp64", 4), ("mixed", 2)])
-def test_batch_rhs_groups_match_single_solves(precision, chunks):
+@pytest.mark.parametrize("precision,overlap,chunks", [("fp64", 0, 4), ("mixed", 0, 2),
+                                                       ("mixed", 2, 2)])
+def test_batch_rhs_groups_match_single_solves(precision, overlap, chunks):
     """Automatic grouping with several right-hand sides launches (right-hand
     side, block) groups within the cache budget: 4 right-hand sides of 192^3
     (7.1M cells each) make launches of one right-hand side per phase in
     FP64 (a budget of 8.4M cells of inner vectors) and of two in mixed
     precision (16.8M).  Every right-hand side is bitwise the single-right-
     hand-side sweep with the same tiling, and equals the all-in-one-launch
-    grouping."""
+    grouping.  With overlap 2 the regions hold 7.7M cells per right-hand
+    side, which still splits the mixed launches in two."""
     torch = torch_cuda()
     n = 192
     shape, cuts = (n, n, n), [inputs.uniform_cuts(n, 2)] * 3
     bs = [inputs.poisson_randn(shape, 170 + k) for k in range(4)]
     h = ms.ms_create(shape, cuts=[list(map(int, c)) for c in cuts])
     ms.ms_reserve(h, 4)
+    if overlap:
+        ms.ms_set_overlap(h, overlap)
     B = torch.stack([dev(b) for b in bs]).contiguous()
     X = torch.zeros_like(B)
     X2 = torch.zeros_like(B)
     K, m = 4, 5
     kw = dict(precision=precision, rows=1, x_chunk=16)
-    say("batch rhs groups", precision)
+    say("batch rhs groups", precision, overlap)
     sts = ms.ms_solve_batch(h, B, X, 0.0, m, max_sweeps=K, profile=True, **kw)
     assert sts[0].kernel_launches["resid"] == (K + 1) * chunks, sts[0].kernel_launches
     ms.ms_solve_batch(h, B, X2, 0.0, m, max_sweeps=K, group_blocks=-1, **kw)
