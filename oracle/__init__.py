@@ -22,6 +22,10 @@ approach to solving linear systems using two-stage multisplitting":
 * ``block_jacobi_async``: a bounded-delay model of the asynchronous outer
   iteration (Sections 2.1 and 2.3: blocks use the latest received, possibly
   old, neighbour values); deterministic for a given delay table.
+* ``async_replay``: the asynchronous outer iteration replayed from a schedule
+  of block sweeps, each naming the version of every neighbour block it reads
+  (Section 2.3: the latest values received, of any age); reproduces a
+  recorded asynchronous run exactly when the recorded reads are whole.
 * ``cg``: the conventional global Krylov solver the paper compares against
   (Section 4), here CG.
 * ``block_jacobi_ovl`` / ``ovl_sweep_some`` / ``overlap_cells``: overlapping
@@ -59,11 +63,18 @@ def lib_path(mutant: int = 0) -> str:
     return os.path.join(HERE, name)
 
 
-def build(mutant: int = 0, out: str | None = None) -> str:
-    """Compile the oracle with gcc (mutant > 0 plants a known mistake)."""
+SANITIZE = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+            "-fno-sanitize-recover=all"]
+
+
+def build(mutant: int = 0, out: str | None = None, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (mutant > 0 plants a known mistake;
+    sanitize: AddressSanitizer + UndefinedBehaviorSanitizer build, loaded only
+    by a process that preloads their runtimes)."""
     out = out or lib_path(mutant)
     tmp = out + f".tmp{os.getpid()}"
-    cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+    opt = SANITIZE if sanitize else ["-O2"]
+    cmd = ["gcc"] + opt + ["-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
            "-std=c99", f"-DORACLE_MUTANT={int(mutant)}", SRC, "-o", tmp, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, out)
@@ -114,6 +125,9 @@ class Oracle:
                                                [C.c_int, C.c_int, _dp, _dp, C.c_int, _ip,
                                                 C.c_int, C.c_double, _dp])
         L.or_multisplit_sweep_some.restype = C.c_int
+        L.or_async_replay.argtypes = ([C.c_long] * 3 + [C.c_int] * 3 + [_ip] * 3 +
+                                      [_dp, _dp, C.c_int, C.c_int, C.c_int, _ip, _ip, _ip])
+        L.or_async_replay.restype = C.c_int
         L.or_num_threads.argtypes = []
         L.or_num_threads.restype = C.c_int
         self.L = L
@@ -291,6 +305,25 @@ class Oracle:
                                           pcx, pcy, pcz, self._d(beff), self._d(x), tol, m,
                                           max_sweeps, S, pd, self._d(hist), C.byref(sw))
         return st, x, sw.value, hist[: sw.value + 1]
+
+    def async_replay(self, beff, x0, cuts, m, events, seen, precision=0):
+        """Asynchronous block sweeps replayed from a schedule: event e sweeps
+        block events[e] once from its own latest values, reading the
+        neighbour across face f at that block's version seen[e, f].
+        Returns (status, x, sweeps per block)."""
+        beff = np.ascontiguousarray(beff, dtype=np.float64)
+        x = np.array(x0, dtype=np.float64, order="C", copy=True)
+        nx, ny, nz = x.shape
+        cx, pcx = self._i(cuts[0]); cy, pcy = self._i(cuts[1]); cz, pcz = self._i(cuts[2])
+        nb = (len(cx) - 1) * (len(cy) - 1) * (len(cz) - 1)
+        ev, pev = self._i(events)
+        sn, psn = self._i(np.asarray(seen).reshape(-1, 6))
+        assert sn.shape == (len(ev), 6)
+        sw, psw = self._i(np.zeros(nb))
+        st = self.L.or_async_replay(nx, ny, nz, len(cx) - 1, len(cy) - 1, len(cz) - 1,
+                                    pcx, pcy, pcz, self._d(beff), self._d(x), int(m),
+                                    int(precision), len(ev), pev, psn, psw)
+        return st, x, sw
 
     def cg(self, beff, x0, tol, max_iters=100000):
         """Global CG.  Returns (status, x, iters, history)."""

@@ -140,6 +140,9 @@ double or_residual(long nx, long ny, long nz, const double *beff,
 double or_norm2(long n, const double *v)
 {
     double s = 0.0;
+#if ORACLE_MUTANT == 18
+    n += 1;   /* planted mistake: reads one element past the end */
+#endif
     for (long t = 0; t < n; t++) s += v[t] * v[t];
     return sqrt(s);
 }
@@ -267,7 +270,11 @@ static int block_cg_f(int bx, int by, int bz, float *r, float *d, float *p,
         it++;
         float rho_new = dot_f(n, r, r);
         if (inner_tol > 0.0 && sqrtf(rho_new) <= (float)inner_tol * sqrtf(rho0)) break;
+#if ORACLE_MUTANT == 16
+        float beta = rho / rho_new;   /* planted mistake: FP32 beta inverted */
+#else
         float beta = rho_new / rho;
+#endif
         for (long t = 0; t < n; t++) p[t] = r[t] + beta * p[t];
         rho = rho_new;
     }
@@ -611,6 +618,9 @@ int or_block_jacobi_async(long nx, long ny, long nz, int gx, int gy, int gz,
                     if (dl < 0) dl = 0;
                     if (dl > S) dl = S;
                     if (dl > s) dl = s;
+#if ORACLE_MUTANT == 15
+                    dl = 0;   /* planted mistake: the delay table is ignored */
+#endif
                     src[f] = hist[(s - dl) % ring];
                 }
                 for (int i = 0; i < bx; i++)
@@ -646,6 +656,186 @@ int or_block_jacobi_async(long nx, long ny, long nz, int gx, int gy, int gz,
     for (int t = 0; t < ring; t++) free(hist[t]);
     free(hist); free(r); free(xn);
     if (sweeps_out) *sweeps_out = s;
+    return status;
+}
+
+/*
+ * Asynchronous outer iterations replayed from a schedule of block sweeps
+ * (Section 2.3: a block's next inner solve uses the latest neighbour
+ * values it has received, whatever their age; Section 2.1: a process goes
+ * on with whatever halo values it holds).  Event e sweeps block
+ * ev_block[e] once, starting from that block's own latest values; the
+ * values of the neighbour block across face f (-x,+x,-y,+y,-z,+z) are that
+ * block's iterate after ev_seen[6e + f] of its own sweeps (entries for
+ * faces without a neighbour are ignored).  The sweep is the synchronous
+ * one restricted to the block: residual with the global operator, at most
+ * m inner CG iterations (FP64, or FP32 storage and accumulation when
+ * precision = 1), x_i += d.  Every version of every block is kept.
+ * Returns OR_ARG when an event names a version that an earlier event has
+ * not produced.  x: initial iterate in (version 0 of every block), every
+ * block's latest version out.  sweeps_out (nullable, nb entries): sweeps
+ * applied to each block.
+ *
+ * An event's result depends only on the versions it names, so events are
+ * computed level by level (an event's level is one more than the levels of
+ * the events that produced its inputs) with the events of one level in
+ * parallel; the arithmetic of each event is the same as in schedule order.
+ */
+int or_async_replay(long nx, long ny, long nz, int gx, int gy, int gz,
+                    const int *cx, const int *cy, const int *cz,
+                    const double *beff, double *x, int m, int precision,
+                    int nev, const int *ev_block, const int *ev_seen, int *sweeps_out)
+{
+    part_t P = {nx, ny, nz, gx, gy, gz, cx, cy, cz};
+    if (nx < 1 || ny < 1 || nz < 1 || m < 1 || nev < 0) return OR_ARG;
+    if (!check_cuts(cx, gx, nx) || !check_cuts(cy, gy, ny) || !check_cuts(cz, gz, nz))
+        return OR_ARG;
+    int nb = gx * gy * gz;
+    long vmax = max_block_volume(&P);
+    /* pass 1, in schedule order: validate, number the versions, levels */
+    int *ver = (int *)calloc((size_t)nb, sizeof(int));
+    int *ev_ver = (int *)malloc(sizeof(int) * (size_t)(nev > 0 ? nev : 1));
+    int *level = (int *)malloc(sizeof(int) * (size_t)(nev > 0 ? nev : 1));
+    int *nbrs = (int *)malloc(sizeof(int) * 6 * (size_t)(nev > 0 ? nev : 1));
+    long total_versions = nb;
+    int status = OR_OK;
+    for (int e = 0; e < nev; e++) {
+        int b = ev_block[e];
+        if (b < 0 || b >= nb) { status = OR_ARG; break; }
+        int bk = b % gz, bj = (b / gz) % gy, bi = b / (gz * gy);
+        int nbr[6] = {bi > 0 ? b - gy * gz : -1, bi < gx - 1 ? b + gy * gz : -1,
+                      bj > 0 ? b - gz : -1, bj < gy - 1 ? b + gz : -1,
+                      bk > 0 ? b - 1 : -1, bk < gz - 1 ? b + 1 : -1};
+        for (int f = 0; f < 6; f++) {
+            nbrs[6L * e + f] = nbr[f];
+            if (nbr[f] >= 0) {
+                int w = ev_seen[6L * e + f];
+                if (w < 0 || w > ver[nbr[f]]) status = OR_ARG;
+            }
+        }
+        if (status != OR_OK) break;
+        ev_ver[e] = ver[b]++;
+        total_versions++;
+    }
+    int *vcount = (int *)malloc(sizeof(int) * (size_t)nb);
+    for (int b = 0; b < nb; b++) vcount[b] = ver[b] + 1;
+    /* hist[b][v]: block b after v of its sweeps; prod[b][v]: the event that
+     * produced it (-1 for the initial values) */
+    double ***hist = (double ***)calloc((size_t)nb, sizeof(double **));
+    int **prod = (int **)calloc((size_t)nb, sizeof(int *));
+    for (int b = 0; b < nb && status == OR_OK; b++) {
+        hist[b] = (double **)calloc((size_t)vcount[b], sizeof(double *));
+        prod[b] = (int *)malloc(sizeof(int) * (size_t)vcount[b]);
+        prod[b][0] = -1;
+        int i0, j0, k0, bx, by, bz;
+        block_range(&P, b, &i0, &j0, &k0, &bx, &by, &bz);
+        for (int v = 0; v < vcount[b]; v++)
+            hist[b][v] = (double *)malloc(sizeof(double) * (size_t)bx * by * bz);
+        gather(&P, b, x, hist[b][0]);
+    }
+    int maxlvl = 0;
+    for (int e = 0; e < nev && status == OR_OK; e++) {
+        int b = ev_block[e];
+        prod[b][ev_ver[e] + 1] = e;
+        int lv = 0, q = prod[b][ev_ver[e]];
+        if (q >= 0 && level[q] + 1 > lv) lv = level[q] + 1;
+        for (int f = 0; f < 6; f++) {
+            int j = nbrs[6L * e + f];
+            if (j < 0) continue;
+            q = prod[j][ev_seen[6L * e + f]];
+            if (q >= 0 && level[q] + 1 > lv) lv = level[q] + 1;
+        }
+        level[e] = lv;
+        if (lv > maxlvl) maxlvl = lv;
+    }
+    /* pass 2: the sweeps, level by level */
+    for (int lv = 0; lv <= maxlvl && status == OR_OK && nev > 0; lv++) {
+#pragma omp parallel
+        {
+            double *lr = (double *)malloc(sizeof(double) * (size_t)vmax);
+            double *ld = (double *)malloc(sizeof(double) * (size_t)vmax);
+            double *lp = (double *)malloc(sizeof(double) * (size_t)vmax);
+            double *lq = (double *)malloc(sizeof(double) * (size_t)vmax);
+            float *fr = (float *)malloc(sizeof(float) * (size_t)vmax);
+            float *fd = (float *)malloc(sizeof(float) * (size_t)vmax);
+            float *fp = (float *)malloc(sizeof(float) * (size_t)vmax);
+            float *fq = (float *)malloc(sizeof(float) * (size_t)vmax);
+#pragma omp for schedule(dynamic, 1)
+            for (int e = 0; e < nev; e++) {
+                if (level[e] != lv) continue;
+                int b = ev_block[e];
+                const double *src[6] = {NULL, NULL, NULL, NULL, NULL, NULL};
+                int src_b[6];
+                for (int f = 0; f < 6; f++) {
+                    src_b[f] = nbrs[6L * e + f];
+                    if (src_b[f] < 0) continue;
+                    int w = ev_seen[6L * e + f];
+#if ORACLE_MUTANT == 17
+                    w = vcount[src_b[f]] - 1;   /* planted mistake: the newest version */
+#endif
+                    src[f] = hist[src_b[f]][w];
+                }
+                int i0, j0, k0, bx, by, bz;
+                block_range(&P, b, &i0, &j0, &k0, &bx, &by, &bz);
+                const double *own = hist[b][ev_ver[e]];
+                for (int i = 0; i < bx; i++)
+                    for (int j = 0; j < by; j++)
+                        for (int k = 0; k < bz; k++) {
+                            long I = i0 + i, J = j0 + j, K = k0 + k;
+                            long c = ((long)i * by + j) * bz + k;
+                            double v = 6.0 * own[c];
+                            /* in-block neighbours from the block's own values */
+                            if (i > 0) v -= own[c - (long)by * bz];
+                            if (j > 0) v -= own[c - bz];
+                            if (k > 0) v -= own[c - 1];
+                            if (i < bx - 1) v -= own[c + (long)by * bz];
+                            if (j < by - 1) v -= own[c + bz];
+                            if (k < bz - 1) v -= own[c + 1];
+                            /* off-block neighbours from the scheduled versions;
+                             * (I2,J2,K2) is the neighbour cell, local to block f */
+                            for (int f = 0; f < 6; f++) {
+                                int out = (f == 0 && i == 0 && I > 0) ||
+                                          (f == 1 && i == bx - 1 && I < nx - 1) ||
+                                          (f == 2 && j == 0 && J > 0) ||
+                                          (f == 3 && j == by - 1 && J < ny - 1) ||
+                                          (f == 4 && k == 0 && K > 0) ||
+                                          (f == 5 && k == bz - 1 && K < nz - 1);
+                                if (!out) continue;
+                                long I2 = I - (f == 0) + (f == 1);
+                                long J2 = J - (f == 2) + (f == 3);
+                                long K2 = K - (f == 4) + (f == 5);
+                                int n0, n1, n2, ex, ey, ez;
+                                block_range(&P, src_b[f], &n0, &n1, &n2, &ex, &ey, &ez);
+                                v -= src[f][((I2 - n0) * ey + (J2 - n1)) * ez + (K2 - n2)];
+                            }
+                            lr[c] = beff[IDX(I, J, K)] - v;
+                        }
+                long vol = (long)bx * by * bz;
+                if (precision == 1) {
+                    for (long t = 0; t < vol; t++) fr[t] = (float)lr[t];
+                    block_cg_f(bx, by, bz, fr, fd, fp, fq, m, 0.0);
+                    for (long t = 0; t < vol; t++) ld[t] = (double)fd[t];
+                } else {
+                    block_cg(bx, by, bz, lr, ld, lp, lq, m, 0.0);
+                }
+                double *dst = hist[b][ev_ver[e] + 1];
+                for (long t = 0; t < vol; t++) dst[t] = own[t] + ld[t];
+            }
+            free(lr); free(ld); free(lp); free(lq); free(fr); free(fd); free(fp); free(fq);
+        }
+    }
+    if (status == OR_OK)
+        for (int b = 0; b < nb; b++) scatter(&P, b, hist[b][ver[b]], x);
+    if (sweeps_out)
+        for (int b = 0; b < nb; b++) sweeps_out[b] = ver[b];
+    for (int b = 0; b < nb; b++) {
+        if (hist[b])
+            for (int v = 0; v < vcount[b]; v++) free(hist[b][v]);
+        free(hist[b]);
+        free(prod[b]);
+    }
+    free(hist); free(prod); free(vcount); free(ver); free(ev_ver); free(level); free(nbrs);
+    (void)total_versions;
     return status;
 }
 

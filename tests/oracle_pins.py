@@ -311,6 +311,247 @@ def pin_single_block_is_global_cg(o):
         assert np.array_equal(xb, xc), m
 
 
+def _block_coords(cuts):
+    """(bi, bj, bk) of every block in the library's block order."""
+    gx, gy, gz = (len(c) - 1 for c in cuts)
+    return [(a, b, c) for a in range(gx) for b in range(gy) for c in range(gz)]
+
+
+def _face_neighbours(cuts):
+    """nbr[i][f]: the block across face f (-x,+x,-y,+y,-z,+z) of block i, or -1."""
+    g = [len(c) - 1 for c in cuts]
+    coords = _block_coords(cuts)
+    index = {c: n for n, c in enumerate(coords)}
+    out = []
+    for (a, b, c) in coords:
+        row = []
+        for ax, step in ((0, -1), (0, 1), (1, -1), (1, 1), (2, -1), (2, 1)):
+            q = [a, b, c]
+            q[ax] += step
+            row.append(index[tuple(q)] if 0 <= q[ax] < g[ax] else -1)
+        out.append(row)
+    return out
+
+
+def _steepest_step(Ab, r):
+    """One CG step from 0 on Ab d = r in closed form: d = (r.r / r.Ab r) r."""
+    rr = float(r @ r)
+    if rr == 0.0:
+        return np.zeros_like(r)
+    return (rr / float(r @ (Ab @ r))) * r
+
+
+def _delayed_reference(shape, cuts, beff, K, S, delays, block_solve):
+    """Section 2.3's bounded-delay iteration written with dense matrices: in
+    sweep s block i solves with its own sweep-s values and the values of the
+    neighbour across face f from sweep s - min(delay, s)."""
+    A = dense_laplacian(*shape)
+    sets = block_index_sets(shape, cuts)
+    nbr = _face_neighbours(cuts)
+    bf = beff.ravel()
+    X = [np.zeros(A.shape[0])]
+    for s in range(K):
+        xn = X[s].copy()
+        for i, Si in enumerate(sets):
+            rhs = bf[Si] - A[np.ix_(Si, Si)] @ X[s][Si]
+            for f in range(6):
+                j = nbr[i][f]
+                if j < 0:
+                    continue
+                d = min(int(delays[s, i, f]), S, s)
+                rhs = rhs - A[np.ix_(Si, sets[j])] @ X[s - d][sets[j]]
+            xn[Si] = X[s][Si] + block_solve(A[np.ix_(Si, Si)], rhs)
+        X.append(xn)
+    return X[K].reshape(shape)
+
+
+def pin_async_delay_table(o):
+    """The bounded-delay model follows its delay table: with exact block
+    solves (2x2x2 blocks, 4 CG steps) and with one CG step on 1x1x2 blocks
+    (the closed-form steepest-descent step), K sweeps under seeded nonzero
+    delays equal the dense iteration that reads each neighbour from the
+    sweep its delay names; the synchronous iterate differs from both."""
+    rng = np.random.default_rng(31)
+    cases = [((4, 4, 2), [np.array([0, 2, 4]), np.array([0, 2, 4]), np.array([0, 2])], 4,
+              lambda Ab, r: np.linalg.solve(Ab, r)),
+             ((2, 2, 6), [np.array([0, 1, 2]), np.array([0, 1, 2]), np.array([0, 2, 4, 6])], 1,
+              _steepest_step)]
+    for shape, cuts, m, solve in cases:
+        beff = rng.standard_normal(shape)
+        nb = (len(cuts[0]) - 1) * (len(cuts[1]) - 1) * (len(cuts[2]) - 1)
+        K, S = 9, 2
+        D = rng.integers(0, S + 1, size=(K, nb, 6)).astype(np.int32)
+        st, xa, sw, _ = o.block_jacobi_async(beff, np.zeros(shape), cuts, tol=0.0, m=m,
+                                             max_sweeps=K, S=S, delays=D)
+        assert st == 0 and sw == K
+        want = _delayed_reference(shape, cuts, beff, K, S, D, solve)
+        assert rel(xa, want) < 1e-12, rel(xa, want)
+        _, xs, _, _, _ = o.block_jacobi(beff, np.zeros(shape), cuts, tol=0.0, m=m, max_sweeps=K)
+        assert rel(xs, want) > 1e-6, rel(xs, want)
+
+
+def pin_fp32_inner_cg(o):
+    """The FP32 inner stage (mixed precision) is CG: on 2x2x2 blocks four
+    FP32 steps solve each block to single-precision accuracy (Section 3's
+    block formula with dense inverses, in FP64), and on 4x4x4 blocks m FP32
+    steps agree with m FP64 CG steps on the dense block to ~1e-6; FP32 and
+    FP64 runs are not bitwise equal, so the FP32 path really ran."""
+    rng = np.random.default_rng(32)
+    shape = (4, 6, 4)
+    cuts = [np.arange(0, n + 1, 2) for n in shape]
+    beff = rng.standard_normal(shape)
+    x0 = rng.standard_normal(shape)
+    A = dense_laplacian(*shape)
+    sets = block_index_sets(shape, cuts)
+    bf, xr = beff.ravel(), x0.ravel()
+    want = xr.copy()
+    for S in sets:
+        want[S] = np.linalg.solve(A[np.ix_(S, S)], bf[S] - A[S] @ xr + A[np.ix_(S, S)] @ xr[S])
+    _, x32, _, _, _ = o.block_jacobi(beff, x0, cuts, tol=0.0, m=4, max_sweeps=1, precision=1)
+    _, x64, _, _, _ = o.block_jacobi(beff, x0, cuts, tol=0.0, m=4, max_sweeps=1)
+    e32 = rel(x32.ravel() - xr, want - xr)
+    assert e32 < 2e-6, e32
+    assert rel(x64.ravel() - xr, want - xr) < 1e-13
+    assert not np.array_equal(x32, x64)
+    # larger blocks, inexact: m FP32 CG steps against m FP64 CG steps on the
+    # dense block (the textbook recurrences in NumPy)
+    shape = (8, 4, 4)
+    cuts = [np.array([0, 4, 8]), np.array([0, 4]), np.array([0, 4])]
+    beff = rng.standard_normal(shape)
+    A = dense_laplacian(*shape)
+    m = 5
+    want = np.zeros(A.shape[0])
+    for S in block_index_sets(shape, cuts):
+        Ab = A[np.ix_(S, S)]
+        r = beff.ravel()[S].copy()
+        d, p, rho = np.zeros_like(r), r.copy(), float(r @ r)
+        for _ in range(m):
+            q = Ab @ p
+            a = rho / float(p @ q)
+            d += a * p
+            r -= a * q
+            rn = float(r @ r)
+            p = r + (rn / rho) * p
+            rho = rn
+        want[S] = d
+    _, x32, _, _, _ = o.block_jacobi(beff, np.zeros(shape), cuts, tol=0.0, m=m, max_sweeps=1,
+                                     precision=1)
+    assert rel(x32.ravel(), want) < 5e-6, rel(x32.ravel(), want)
+
+
+def _replay_reference(shape, cuts, beff, x0, events, seen, block_solve):
+    """A schedule of block sweeps written with dense matrices: event e solves
+    block events[e] from its own latest values and the neighbour across face
+    f at that block's version seen[e, f]."""
+    A = dense_laplacian(*shape)
+    sets = block_index_sets(shape, cuts)
+    nbr = _face_neighbours(cuts)
+    bf = beff.ravel()
+    hist = [[x0.ravel()[S].copy()] for S in sets]
+    for e, i in enumerate(events):
+        Si = sets[i]
+        own = hist[i][-1]
+        rhs = bf[Si] - A[np.ix_(Si, Si)] @ own
+        for f in range(6):
+            j = nbr[i][f]
+            if j >= 0:
+                rhs = rhs - A[np.ix_(Si, sets[j])] @ hist[j][int(seen[e][f])]
+        hist[i].append(own + block_solve(A[np.ix_(Si, Si)], rhs))
+    x = np.zeros(A.shape[0])
+    for S, h in zip(sets, hist):
+        x[S] = h[-1]
+    return x.reshape(shape), [len(h) - 1 for h in hist]
+
+
+def _latest_schedule(nbr, order):
+    """seen versions for an event order in which every sweep reads the
+    neighbours' latest versions."""
+    ver = [0] * len(nbr)
+    seen = []
+    for i in order:
+        seen.append([ver[j] if j >= 0 else -1 for j in nbr[i]])
+        ver[i] += 1
+    return seen
+
+
+def pin_async_replay(o):
+    """The schedule replay: (i) lockstep sweeps that read version s of every
+    neighbour are Section 3's block Jacobi with dense inverses (2x2x2 blocks,
+    exact 4-step CG); (ii) red blocks then black blocks, each reading the
+    latest values, is block Gauss-Seidel in red-black order (dense); (iii) a
+    seeded random schedule with reads up to two versions old, one CG step on
+    1x1x2 blocks (closed-form step) and on 2x2x2 blocks with exact solves,
+    equals the dense replay; in FP32 (mixed precision) it agrees to ~1e-6."""
+    rng = np.random.default_rng(33)
+    shape = (4, 4, 4)
+    cuts = [np.array([0, 2, 4])] * 3
+    nb = 8
+    beff = rng.standard_normal(shape)
+    x0 = rng.standard_normal(shape)
+    exact = lambda Ab, r: np.linalg.solve(Ab, r)   # noqa: E731
+    # (i) lockstep = block Jacobi
+    K = 5
+    events = [b for s in range(K) for b in range(nb)]
+    seen = [[s] * 6 for s in range(K) for b in range(nb)]
+    st, x, sw = o.async_replay(beff, x0, cuts, 4, events, seen)
+    assert st == 0 and list(sw) == [K] * nb
+    A = dense_laplacian(*shape)
+    sets = block_index_sets(shape, cuts)
+    xr, bf = x0.ravel().copy(), beff.ravel()
+    for _ in range(K):
+        xn = xr.copy()
+        for S in sets:
+            xn[S] = np.linalg.solve(A[np.ix_(S, S)], bf[S] - A[S] @ xr + A[np.ix_(S, S)] @ xr[S])
+        xr = xn
+    assert rel(x.ravel(), xr) < 1e-12, rel(x.ravel(), xr)
+    # (ii) red-black block Gauss-Seidel
+    nbr = _face_neighbours(cuts)
+    coords = _block_coords(cuts)
+    red = [b for b, c in enumerate(coords) if sum(c) % 2 == 0]
+    black = [b for b, c in enumerate(coords) if sum(c) % 2 == 1]
+    order = [b for _ in range(K) for b in red + black]
+    st, x, _ = o.async_replay(beff, x0, cuts, 4, order, _latest_schedule(nbr, order))
+    assert st == 0
+    xr = x0.ravel().copy()
+    for _ in range(K):
+        for colour in (red, black):
+            for b in colour:
+                S = sets[b]
+                xr[S] = np.linalg.solve(A[np.ix_(S, S)],
+                                        bf[S] - A[S] @ xr + A[np.ix_(S, S)] @ xr[S])
+    assert rel(x.ravel(), xr) < 1e-12, rel(x.ravel(), xr)
+    # (iii) random schedules with stale reads
+    for shape, cuts, m, solve in (
+            ((2, 2, 6), [np.array([0, 1, 2]), np.array([0, 1, 2]), np.array([0, 2, 4, 6])], 1,
+             _steepest_step),
+            ((4, 4, 4), [np.array([0, 2, 4])] * 3, 4, exact)):
+        nbr = _face_neighbours(cuts)
+        nb = len(nbr)
+        beff = rng.standard_normal(shape)
+        x0 = rng.standard_normal(shape)
+        ver = [0] * nb
+        events, seen = [], []
+        for _ in range(12 * nb):
+            i = int(rng.integers(nb))
+            events.append(i)
+            seen.append([max(0, ver[j] - int(rng.integers(3))) if j >= 0 else -1
+                         for j in nbr[i]])
+            ver[i] += 1
+        st, x, sw = o.async_replay(beff, x0, cuts, m, events, seen)
+        assert st == 0 and list(sw) == ver
+        want, vers = _replay_reference(shape, cuts, beff, x0, events, seen, solve)
+        assert vers == ver
+        assert rel(x, want) < 1e-12, rel(x, want)
+        latest, _ = _replay_reference(shape, cuts, beff, x0, events,
+                                      _latest_schedule(nbr, events), solve)
+        assert rel(latest, want) > 1e-6
+        st, x32, _ = o.async_replay(beff, x0, cuts, m, events, seen, precision=1)
+        assert st == 0 and rel(x32, want) < 1e-5, rel(x32, want)
+    # a version that no earlier event produced
+    st, _, _ = o.async_replay(beff, x0, cuts, 1, [0], [[1] * 6])
+    assert st != 0
+
+
 # ----------------------------------------------------------------------
 # overlapping blocks (Section 3.2: block overlap; Section 2.3: weights D_i)
 # ----------------------------------------------------------------------
@@ -573,7 +814,10 @@ ALL_PINS = [
     pin_cg_dense,
     pin_analytic_solution,
     pin_async_zero_delay,
+    pin_async_delay_table,
+    pin_async_replay,
     pin_mixed_reference,
+    pin_fp32_inner_cg,
     pin_sweep_semantics,
     pin_block_sweep_some,
     pin_single_block_is_global_cg,

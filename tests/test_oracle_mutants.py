@@ -5,8 +5,10 @@ update, a replace-instead-of-add outer update, a periodic instead of zero
 block boundary, a residual that skips neighbour blocks (no halo), swapped
 boundary faces, an overlap region grown into edges and corners, and overlap
 corrections added without the owner weights, GMRES least squares without
-the earlier Givens rotations, and a Gram-Schmidt step that skips the newest
-basis vector."""
+the earlier Givens rotations, a Gram-Schmidt step that skips the newest
+basis vector, an asynchronous model that ignores its delays, an FP32 inner
+CG with beta inverted, and a schedule replay that reads the latest
+neighbour versions instead of the scheduled ones."""
 import os
 import tempfile
 
@@ -29,6 +31,9 @@ MUTANTS = {
     12: "overlap corrections added without weights",
     13: "GMRES without the earlier Givens rotations",
     14: "GMRES Gram-Schmidt skips the newest vector",
+    15: "asynchronous model ignores its delay table",
+    16: "FP32 inner CG beta inverted",
+    17: "schedule replay reads the latest neighbour version, not the scheduled one",
 }
 
 
