@@ -89,8 +89,11 @@ typedef struct {
 typedef struct {
     int32_t max_sweeps;   /* outer sweeps before MS_ERR_NOT_CONVERGED (default 100000) */
     double inner_tol;     /* > 0: also stop a block's CG once ||r_i|| <= inner_tol*||r_i^0|| */
-    int32_t staleness;    /* async: a block may run at most this many sweeps
-                             ahead of any neighbour (default 2, >= 0) */
+    int32_t staleness;    /* async (>= 1, default 2): a block starts sweep v+1
+                             only when every face neighbour has finished at
+                             least v+1-staleness sweeps, so the neighbour data
+                             it starts from is at most staleness-1 sweeps
+                             older than its own (sync ignores it) */
     int32_t precision;    /* ms_precision (default MS_FP64) */
     void *stream;         /* hipStream_t used for all work; NULL = null stream */
     int32_t check_every;  /* sync: sweeps enqueued between host reads of the
@@ -119,6 +122,20 @@ typedef struct {
                              or 8 (0 = automatic: 16 bytes; at most 32 bytes,
                              16 with GMRES, 4 cells with overlap; nz and every
                              z cut must be multiples of it) */
+    /* Debugging aids of asynchronous mode (Section 5: tolerance of slow
+     * processes; Section 2.3: bounded delays). */
+    int32_t slow_block;   /* block whose worker waits before each of its sweeps
+                             (< 0: none; default -1) */
+    int32_t slow_sleep;   /* that wait: this many s_sleep(127) instructions,
+                             about 8000 cycles each (0: off; at most 100000) */
+    int32_t *trace;       /* DEVICE buffer (or NULL) of trace_cap records of 8
+                             int32, one per block sweep started, in start
+                             order: block, the block's version (sweeps it had
+                             finished), then the versions of its -x,+x,-y,+y,
+                             -z,+z neighbours read when it started (-1: no
+                             neighbour).  Sweeps beyond trace_cap are counted
+                             in ms_stats.trace_len but not written */
+    int32_t trace_cap;
 } ms_opts;
 
 /* Kernel classes reported by the profile counters of ms_stats. */
@@ -142,7 +159,8 @@ typedef struct {
     int64_t inner_iters;       /* CG iterations summed over blocks and sweeps */
     double rel_residual;       /* true FP64 relative residual of returned x  */
     double seconds;            /* wall time of the call                      */
-    int32_t max_staleness_seen;/* async: largest version gap observed        */
+    int32_t max_staleness_seen;/* async: largest version gap to a neighbour
+                                  a block sweep started from (<= staleness-1) */
     int32_t relaunches;        /* async: relaunches after a failed verification */
     int32_t history_len;       /* entries written to history                 */
     double *history;           /* HOST buffer supplied by the caller (or NULL):
@@ -150,6 +168,12 @@ typedef struct {
     int32_t history_cap;       /* its capacity                               */
     double kernel_ms[MS_K_COUNT];       /* profile=1: summed event time      */
     int64_t kernel_launches[MS_K_COUNT];/* profile=1: launches timed         */
+    int32_t trace_len;         /* async with opts->trace: block sweeps started  */
+    int32_t *block_sweeps;     /* HOST buffer supplied by the caller (or NULL)
+                                  of block_sweeps_cap entries: sweeps applied
+                                  to each block, in block order (sync: all
+                                  equal to sweeps) */
+    int32_t block_sweeps_cap;
 } ms_stats;
 
 typedef struct ms_handle ms_handle;

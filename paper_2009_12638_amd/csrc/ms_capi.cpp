@@ -80,7 +80,8 @@ struct ms_handle {
     int *cg_tiles_d = nullptr;
     int cg_cap = 0, cg_ntiles = 0, cg_vz = 0, cg_tx = 0, cg_rows = 0;
     // asynchronous sweeps
-    int *version_d = nullptr, *claim_d = nullptr, *nbr_d = nullptr, *finished_d = nullptr;
+    int *version_d = nullptr, *claim_d = nullptr, *nbr_d = nullptr;
+    int *finished_d = nullptr;  // [0]: blocks at the launch's sweep limit; [1]: sweeps started
     double *board_d = nullptr;
     int num_cu = 0;
     // right-hand sides the per-RHS buffers hold (ms_reserve grows it)
@@ -96,7 +97,7 @@ struct ms_handle {
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
-    unsigned char graph_key[128] = {0};
+    unsigned char graph_key[256] = {0};
     // profiling
     std::vector<hipEvent_t> ev;
     std::vector<int> ev_class;
@@ -237,6 +238,12 @@ Faces faces(const ms_handle *h) {
     return f;
 }
 
+void drop_graph(ms_handle *h);
+
+// Copies the boundary faces into handle-owned buffers (a NULL face frees its
+// buffer).  Faces whose buffer stays put are overwritten in place, which a
+// captured sweep graph sees on its next replay; a face buffer that is
+// allocated or freed invalidates the graph.
 ms_status copy_bc(ms_handle *h, const ms_bc *bc) {
     const long long sz[6] = {h->ny * h->nz, h->ny * h->nz, h->nx * h->nz,
                              h->nx * h->nz, h->nx * h->ny, h->nx * h->ny};
@@ -249,10 +256,19 @@ ms_status copy_bc(ms_handle *h, const ms_bc *bc) {
     for (int t = 0; t < 6; t++) {
         const double *src = bc ? bc->face[t] : nullptr;
         if (!src) {
-            if (h->faces_d[t]) { (void)hipFree(h->faces_d[t]); h->faces_d[t] = nullptr; }
+            if (h->faces_d[t]) {
+                // a captured sweep graph holds this face pointer: drop it
+                // before the buffer goes
+                drop_graph(h);
+                (void)hipFree(h->faces_d[t]);
+                h->faces_d[t] = nullptr;
+            }
             continue;
         }
-        if (!h->faces_d[t]) HIPCHK(h, hipMalloc(&h->faces_d[t], sizeof(double) * sz[t]));
+        if (!h->faces_d[t]) {
+            drop_graph(h);   // the graph was captured with this face absent
+            HIPCHK(h, hipMalloc(&h->faces_d[t], sizeof(double) * sz[t]));
+        }
         HIPCHK(h, hipMemcpy(h->faces_d[t], src, sizeof(double) * sz[t], hipMemcpyDeviceToDevice));
     }
     return MS_OK;
@@ -673,10 +689,12 @@ constexpr long long kGroupBytes = 256ll << 20;
 struct GraphKey {
     const double *b;
     double *x;
+    const double *faces[6];   // boundary buffers the captured kernels read
     double tol, inner_tol;
     long long cap_cells;
     int m, tsize, vz, tx, rows, nrhs, overlap, inner;
 };
+static_assert(sizeof(GraphKey) <= sizeof(ms_handle::graph_key), "graph key storage");
 
 void drop_graph(ms_handle *h) {
     if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
@@ -809,7 +827,8 @@ ms_status solve_sync(ms_handle *h, const double *b, double *x, int nrhs, double 
     if (graph) {
         GraphKey key;
         memset(&key, 0, sizeof(key));
-        key.b = b; key.x = x; key.tol = tol; key.inner_tol = o.inner_tol; key.cap_cells = cap_cells;
+        key.b = b; key.x = x; key.tol = tol;
+        for (int t = 0; t < 6; t++) key.faces[t] = h->faces_d[t]; key.inner_tol = o.inner_tol; key.cap_cells = cap_cells;
         key.m = m; key.tsize = (int)sizeof(T); key.vz = vz; key.tx = tx; key.rows = rows;
         key.nrhs = nrhs;
         key.overlap = h->overlap;
@@ -863,6 +882,9 @@ ms_status solve_sync(ms_handle *h, const double *b, double *x, int nrhs, double 
         for (int k = 0; k < nrhs; k++) {
             ms_stats &S = stats[k];
             S.sweeps = c[k].final_sweep;
+            if (S.block_sweeps)
+                for (int q = 0; q < std::min(h->nblocks, S.block_sweeps_cap); q++)
+                    S.block_sweeps[q] = c[k].final_sweep;
             S.inner_iters = (int64_t)c[k].inner_snap;
             S.rel_residual = nbeff[k] == 0.0 ? 0.0 : c[k].last_res;
             if (S.history && S.history_cap > 0) {
@@ -909,16 +931,21 @@ ms_status residual_norms(ms_handle *h, const double *b, const double *x, hipStre
 
 // ---- asynchronous solve ----------------------------------------------------
 
-__global__ void k_async_reset(int *version, int *claim, double *board, int nb, int *finished,
+// counters[0]: blocks at the launch's sweep limit; counters[1]: block sweeps
+// started (trace records)
+__global__ void k_async_reset(int *version, int *claim, double *board, int nb, int *counters,
                               int already, Ctrl *c, int full) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += gridDim.x * blockDim.x) {
         if (full) { version[i] = 0; claim[i] = 0; }
         board[i] = INFINITY;   // a block counts as unconverged until it publishes
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        *finished = already;   // blocks already at the sweep limit of this launch
+        counters[0] = already;   // blocks already at the sweep limit of this launch
         c->stop = 0;
-        if (full) { c->work_items = 0ull; c->inner_iters = 0ull; c->max_stale = 0; }
+        if (full) {
+            c->work_items = 0ull; c->inner_iters = 0ull; c->max_stale = 0;
+            counters[1] = 0;
+        }
     }
 }
 
@@ -977,6 +1004,11 @@ ms_status solve_async(ms_handle *h, const double *b, double *x, double tol, int 
     as.board = h->board_d;
     as.nbr = h->nbr_d;
     as.finished = h->finished_d;
+    as.trace = o.trace_cap > 0 ? o.trace : nullptr;
+    as.trace_n = h->finished_d + 1;
+    as.trace_cap = o.trace_cap;
+    as.slow_block = o.slow_sleep > 0 ? o.slow_block : -1;
+    as.slow_sleep = o.slow_sleep;
     Bufs<T> B = bufs<T>(h);
     std::vector<int> ver(nbk, 0);
     int maxv = 0, minv = 0, relaunches = 0;
@@ -1038,7 +1070,13 @@ ms_status solve_async(ms_handle *h, const double *b, double *x, double tol, int 
     }
     Ctrl c;
     HIPCHK(h, hipMemcpy(&c, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    int started = 0;
+    HIPCHK(h, hipMemcpy(&started, h->finished_d + 1, sizeof(int), hipMemcpyDeviceToHost));
     if (stats) {
+        stats->trace_len = as.trace ? started : 0;
+        if (stats->block_sweeps)
+            for (int q = 0; q < std::min(nbk, stats->block_sweeps_cap); q++)
+                stats->block_sweeps[q] = ver[q];
         stats->sweeps = (int)((c.work_items + nbk / 2) / nbk);
         stats->inner_iters = (int64_t)c.inner_iters;
         stats->rel_residual = rel;
@@ -1200,6 +1238,10 @@ void ms_default_opts(ms_opts *o) {
     o->workers = 0;
     o->inner_solver = MS_INNER_CG;
     o->z_vector = 0;
+    o->slow_block = -1;
+    o->slow_sleep = 0;
+    o->trace = nullptr;
+    o->trace_cap = 0;
 }
 
 const char *ms_status_string(ms_status s) {
@@ -1382,6 +1424,13 @@ static ms_status check_solve(ms_handle *h, const double *b, double *x, long long
     if (o.inner_solver != MS_INNER_CG && o.inner_solver != MS_INNER_GMRES)
         return fail(h, MS_ERR_ARG, "unknown inner solver");
     if (o.z_vector < 0) return fail(h, MS_ERR_ARG, "z_vector must be >= 0");
+    if (o.slow_sleep < 0 || o.slow_sleep > 100000)
+        return fail(h, MS_ERR_ARG, "slow_sleep must be in [0, 100000]");
+    if (o.slow_sleep > 0 && o.slow_block >= h->nblocks)
+        return fail(h, MS_ERR_ARG, "slow_block is not a block of the partition");
+    if (o.trace_cap < 0) return fail(h, MS_ERR_ARG, "trace_cap must be >= 0");
+    if (o.trace_cap > 0 && (!o.trace || !dev_range_ok(o.trace, sizeof(int32_t) * 8 * (size_t)o.trace_cap)))
+        return fail(h, MS_ERR_ARG, "trace is not a device buffer of trace_cap records");
     return MS_OK;
 }
 
@@ -1389,9 +1438,13 @@ static void reset_stats(ms_stats *stats, int n) {
     for (int k = 0; stats && k < n; k++) {
         double *hist = stats[k].history;
         const int cap = stats[k].history_cap;
+        int32_t *bsw = stats[k].block_sweeps;
+        const int bcap = stats[k].block_sweeps_cap;
         memset(&stats[k], 0, sizeof(ms_stats));
         stats[k].history = hist;
         stats[k].history_cap = cap;
+        stats[k].block_sweeps = bsw;
+        stats[k].block_sweeps_cap = bcap;
     }
 }
 
@@ -1604,13 +1657,7 @@ ms_status ms_cg(ms_handle *h, const double *b, double *x, double tol, int32_t ma
     if (bb < xx + bytes && xx < bb + bytes) return fail(h, MS_ERR_ARG, "b and x overlap");
     if (max_iters < 0) return fail(h, MS_ERR_ARG, "max_iters must be >= 0");
     if (std::isnan(tol)) return fail(h, MS_ERR_ARG, "tol is NaN");
-    if (stats) {
-        double *hist = stats->history;
-        const int cap = stats->history_cap;
-        memset(stats, 0, sizeof(*stats));
-        stats->history = hist;
-        stats->history_cap = cap;
-    }
+    reset_stats(stats, 1);
     s = solve_cg(h, b, x, tol, max_iters, o, stats, (hipStream_t)o.stream);
     if (stats)
         stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();

@@ -154,6 +154,7 @@ __device__ __forceinline__ int axes_out(const BlockInfo &B, int i, int j, int k)
 struct AsyncShared {
     int blk;
     int gap;
+    int ver;      // version of the claimed block when it was claimed
     unsigned long long key[kAsyncThreads / 64];
 };
 
@@ -205,32 +206,60 @@ __device__ __forceinline__ int async_claim(const Geom &g, AsyncState as, int S, 
             const int cand = (int)(k & 0xffffffffu);
             int zero = 0;
             if (__hip_atomic_compare_exchange_strong(&as.claim[cand], &zero, 1, __ATOMIC_ACQUIRE,
-                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                pick = cand;
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                // The scan above read versions before the claim: another
+                // worker may have swept and released the block since.  With
+                // the claim held the block's version is fixed, so test the
+                // rule again on fresh values and give the block back if it
+                // no longer holds.  The largest version gap to a neighbour
+                // this sweep will see is then at most S - 1.
+                const int v = __hip_atomic_load(&as.version[cand], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                bool ok = v < max_sweeps;
+                int gap = 0;
+                int seen[6];
+                for (int f = 0; f < 6; f++) {
+                    const int nbk = as.nbr[cand * 6 + f];
+                    seen[f] = -1;
+                    if (nbk < 0) continue;
+                    const int vn = __hip_atomic_load(&as.version[nbk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    seen[f] = vn;
+                    ok = ok && vn >= v + 1 - S;
+                    gap = max(gap, v - vn);
+                }
+                if (ok) {
+                    pick = cand;
+                    sh.gap = gap;
+                    sh.ver = v;
+                    if (as.trace) {
+                        const int slot = atomicAdd(as.trace_n, 1);
+                        if (slot < as.trace_cap) {
+                            int *rec = as.trace + (long long)slot * kTraceInts;
+                            rec[0] = cand;
+                            rec[1] = v;
+                            for (int f = 0; f < 6; f++) rec[2 + f] = seen[f];
+                        }
+                    }
+                    // acquire the neighbours' published x values
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                } else {
+                    __hip_atomic_store(&as.claim[cand], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
         }
         if (pick < 0) {
             const bool stop = __hip_atomic_load(&ctrl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
             const int fin = __hip_atomic_load(as.finished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (stop || fin >= nb) pick = -2;
-        } else {
-            // staleness this sweep will see, then acquire the neighbours'
-            // published x values
-            const int v = __hip_atomic_load(&as.version[pick], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            int gap = 0;
-            for (int f = 0; f < 6; f++) {
-                const int nbk = as.nbr[pick * 6 + f];
-                if (nbk < 0) continue;
-                const int vn = __hip_atomic_load(&as.version[nbk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                gap = max(gap, v - vn);
-            }
-            sh.gap = gap;
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         sh.blk = pick;
     }
     __syncthreads();
     const int blk = sh.blk;
     __syncthreads();
+    // debugging aid: a slow block (a bounded wait before each of its sweeps,
+    // so its neighbours run ahead up to the staleness bound)
+    if (blk >= 0 && blk == as.slow_block)
+        for (int q = 0; q < as.slow_sleep; q++) __builtin_amdgcn_s_sleep(127);
     return blk;
 }
 

@@ -101,7 +101,15 @@ struct AsyncState {
     double *board;       // latest published ||r_i||^2 of the block
     const int *nbr;      // 6 neighbour blocks per block (-1 = none)
     int *finished;       // blocks that reached the sweep limit this launch
+    // debugging aids (off when trace is null / slow_sleep is 0)
+    int *trace;          // kTraceInts ints per started block sweep: block,
+                         // its version, the 6 neighbours' versions (-1 = none)
+    int *trace_n;        // block sweeps started (records beyond trace_cap are not written)
+    int trace_cap;
+    int slow_block;      // block whose worker waits before each of its sweeps
+    int slow_sleep;      // ... this many s_sleep(127) instructions
 };
+constexpr int kTraceInts = 8;
 
 // ---- kernel launches ------------------------------------------------------
 // Profiling: the host sets events that the next launch of this thread

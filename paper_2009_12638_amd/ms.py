@@ -50,7 +50,9 @@ class ms_opts(C.Structure):
                 ("stream", C.c_void_p), ("check_every", C.c_int32),
                 ("group_blocks", C.c_int32), ("x_chunk", C.c_int32),
                 ("profile", C.c_int32), ("use_graph", C.c_int32), ("rows", C.c_int32),
-                ("workers", C.c_int32), ("inner_solver", C.c_int32), ("z_vector", C.c_int32)]
+                ("workers", C.c_int32), ("inner_solver", C.c_int32), ("z_vector", C.c_int32),
+                ("slow_block", C.c_int32), ("slow_sleep", C.c_int32),
+                ("trace", C.c_void_p), ("trace_cap", C.c_int32)]
 
 
 class ms_stats(C.Structure):
@@ -59,7 +61,8 @@ class ms_stats(C.Structure):
                 ("max_staleness_seen", C.c_int32), ("relaunches", C.c_int32),
                 ("history_len", C.c_int32), ("history", C.POINTER(C.c_double)),
                 ("history_cap", C.c_int32), ("kernel_ms", C.c_double * 8),
-                ("kernel_launches", C.c_int64 * 8)]
+                ("kernel_launches", C.c_int64 * 8), ("trace_len", C.c_int32),
+                ("block_sweeps", C.POINTER(C.c_int32)), ("block_sweeps_cap", C.c_int32)]
 
 
 _L = None
@@ -161,10 +164,11 @@ def _stream(stream):
 class Handle:
     """Owns one ms_handle (plus the host cut arrays it was made from)."""
 
-    def __init__(self, raw: C.c_void_p, shape, cuts):
+    def __init__(self, raw: C.c_void_p, shape, cuts, nblocks: int):
         self.raw = raw
         self.shape = tuple(shape)
         self.cuts = cuts
+        self.nblocks = nblocks
 
     def __del__(self):
         try:
@@ -196,18 +200,21 @@ def ms_create(shape, blocks=None, cuts=None, faces=None) -> Handle:
     nx, ny, nz = (int(v) for v in shape)
     g = ms_grid(nx, ny, nz)
     keep = []
+    nblocks = 1
     if cuts is not None:
         arrs = []
         for c in cuts:
             a = (C.c_int32 * len(c))(*[int(v) for v in c])
             arrs.append(a)
         keep = arrs
+        nblocks = (len(cuts[0]) - 1) * (len(cuts[1]) - 1) * (len(cuts[2]) - 1)
         bl = ms_blocks(len(cuts[0]) - 1, len(cuts[1]) - 1, len(cuts[2]) - 1,
                        C.cast(arrs[0], C.POINTER(C.c_int32)),
                        C.cast(arrs[1], C.POINTER(C.c_int32)),
                        C.cast(arrs[2], C.POINTER(C.c_int32)))
     else:
         gx, gy, gz = blocks
+        nblocks = int(gx) * int(gy) * int(gz)
         bl = ms_blocks(gx, gy, gz, None, None, None)
     bc = ms_bc()
     for t, f in enumerate(faces or [None] * 6):
@@ -216,7 +223,7 @@ def ms_create(shape, blocks=None, cuts=None, faces=None) -> Handle:
     st = lib().ms_create(C.byref(g), C.byref(bl), C.byref(bc), C.byref(raw))
     if st != MS_OK:
         raise MsError(st, (lib().ms_last_error(None) or b"").decode())
-    return Handle(raw, (nx, ny, nz), keep)
+    return Handle(raw, (nx, ny, nz), keep, nblocks)
 
 
 def ms_set_bc(h: Handle, faces) -> None:
@@ -249,11 +256,14 @@ class Stats:
     history: list = field(default_factory=list)
     kernel_ms: dict = field(default_factory=dict)
     kernel_launches: dict = field(default_factory=dict)
+    trace_len: int = 0
+    block_sweeps: list = field(default_factory=list)
 
 
 def _opts(precision="fp64", max_sweeps=100000, inner_tol=0.0, staleness=2, stream=None,
           check_every=0, group_blocks=0, x_chunk=0, profile=False, use_graph=True,
-          rows=0, workers=0, inner="cg", z_vector=0) -> ms_opts:
+          rows=0, workers=0, inner="cg", z_vector=0, slow_block=-1, slow_sleep=0,
+          trace=None) -> ms_opts:
     o = ms_default_opts()
     o.max_sweeps = int(max_sweeps)
     o.inner_tol = float(inner_tol)
@@ -271,16 +281,28 @@ def _opts(precision="fp64", max_sweeps=100000, inner_tol=0.0, staleness=2, strea
     o.inner_solver = {"cg": MS_INNER_CG, "gmres": MS_INNER_GMRES}[inner] \
         if isinstance(inner, str) else int(inner)
     o.z_vector = int(z_vector)
+    o.slow_block = int(slow_block)
+    o.slow_sleep = int(slow_sleep)
+    if trace is not None:
+        # an int32 device tensor of shape [cap, 8]
+        o.trace = _ptr(trace)
+        o.trace_cap = int(trace.shape[0]) if hasattr(trace, "shape") else 0
     return o
 
 
-def _stats_of(st: int, s: ms_stats, hist) -> Stats:
+def _stats_of(st: int, s: ms_stats, hist, bsw=None) -> Stats:
     return Stats(status=st, sweeps=s.sweeps, inner_iters=s.inner_iters,
                  rel_residual=s.rel_residual, seconds=s.seconds,
                  max_staleness_seen=s.max_staleness_seen, relaunches=s.relaunches,
                  history=list(hist[: s.history_len]) if hist is not None else [],
                  kernel_ms={KERNEL_CLASSES[i]: s.kernel_ms[i] for i in range(8)},
-                 kernel_launches={KERNEL_CLASSES[i]: s.kernel_launches[i] for i in range(8)})
+                 kernel_launches={KERNEL_CLASSES[i]: s.kernel_launches[i] for i in range(8)},
+                 trace_len=s.trace_len,
+                 block_sweeps=list(bsw) if bsw is not None else [])
+
+
+def _nblocks(h) -> int:
+    return h.nblocks
 
 
 def ms_solve(h: Handle, b, x, tol: float, inner_iters: int, mode="sync", history=0,
@@ -296,10 +318,14 @@ def ms_solve(h: Handle, b, x, tol: float, inner_iters: int, mode="sync", history
         hist = (C.c_double * int(history))()
         s.history = C.cast(hist, C.POINTER(C.c_double))
         s.history_cap = int(history)
+    nb = _nblocks(h)
+    bsw = (C.c_int32 * nb)()
+    s.block_sweeps = C.cast(bsw, C.POINTER(C.c_int32))
+    s.block_sweeps_cap = nb
     md = {"sync": MS_SYNC, "async": MS_ASYNC}[mode] if isinstance(mode, str) else int(mode)
     st = lib().ms_solve(h.raw, _vec(h, b, "b"), _vec(h, x, "x"), float(tol), int(inner_iters), md,
                         C.byref(o), C.byref(s))
-    out = _stats_of(st, s, hist)
+    out = _stats_of(st, s, hist, bsw)
     if raise_on_error and st != MS_OK:
         _check(h, st)
     return out

@@ -4,6 +4,7 @@ touching the device, and the Python binding mirrors the header's structs."""
 import ctypes as C
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -33,15 +34,50 @@ def test_exports_every_declared_symbol(L):
         assert hasattr(L, n), f"libms.so does not export {n}"
 
 
-def test_struct_sizes_match_c_layout():
-    # sizes fixed by the C rules for the header's member lists
-    assert C.sizeof(ms.ms_grid) == 24
-    assert C.sizeof(ms.ms_blocks) == 12 + 4 + 24
-    assert C.sizeof(ms.ms_bc) == 48
-    # max_sweeps, pad, inner_tol, staleness, precision, stream, five int32
-    # options, rows, workers, inner_solver, z_vector, tail padding to 8
-    assert C.sizeof(ms.ms_opts) == 4 + 4 + 8 + 4 + 4 + 8 + 4 * 5 + 4 + 4 + 4 + 4 + 4
-    assert C.sizeof(ms.ms_stats) == 4 + 4 + 8 + 8 + 8 + 4 + 4 + 4 + 4 + 8 + 4 + 4 + 64 + 64
+STRUCTS = ["ms_grid", "ms_blocks", "ms_bc", "ms_opts", "ms_stats"]
+
+
+def c_layout(tmp_path):
+    """sizeof and offsetof of every member of the header's structs, as gcc
+    lays them out (a small C program that includes ms.h)."""
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "ms.h"', "int main(void) {"]
+    for name in STRUCTS:
+        cls = getattr(ms, name)
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{name} {fname} %zu\\n", offsetof({name}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-I", os.path.join(ROOT, "include"), str(src),
+                    "-o", str(exe)], check=True, capture_output=True, text=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    table = {}
+    for ln in out.splitlines():
+        sname, field, val = ln.split()
+        table[(sname, field)] = int(val)
+    return table
+
+
+def test_struct_layouts_match_gcc(tmp_path):
+    # the binding's ctypes structs name every header member, in order, at
+    # gcc's offsets and with gcc's sizes
+    table = c_layout(tmp_path)
+    for name in STRUCTS:
+        cls = getattr(ms, name)
+        assert C.sizeof(cls) == table[(name, "size")], name
+        for fname, _ in cls._fields_:
+            assert getattr(cls, fname).offset == table[(name, fname)], f"{name}.{fname}"
+    # and no header member is missing from the binding
+    text = open(os.path.join(ROOT, "include", "ms.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    for name in STRUCTS:
+        body = re.search(r"typedef struct \{([^{}]*)\}\s*" + name + r"\s*;", text, flags=re.S)
+        assert body, name
+        decl = re.sub(r"\[[^\]]*\]", "", body.group(1))
+        members = re.findall(r"\*?\s*([a-z_][a-z0-9_]*)\s*(?=[,;])", decl)
+        assert sorted(members) == sorted(f for f, _ in getattr(ms, name)._fields_), name
 
 
 def test_status_strings(L):

@@ -43,7 +43,7 @@ def test_async_converges_within_kappa_bound(laplace32, S, precision):
     relr, _ = ms.ms_residual(h, dev(w["b"]), x)
     assert relr <= 1e-8
     assert rel(host(x), xstar) <= kappa(32) * 1e-8
-    assert 0 <= st.max_staleness_seen <= S
+    assert 0 <= st.max_staleness_seen <= S - 1
     print(f"async S={S} {precision}: ~{st.sweeps} sweeps/block, staleness {st.max_staleness_seen},"
           f" relaunches {st.relaunches}")
 
@@ -67,7 +67,7 @@ def test_async_fixed_sweeps_do_the_requested_work(orc, shape, cuts):
     nb = (len(cuts[0]) - 1) * (len(cuts[1]) - 1) * (len(cuts[2]) - 1)
     assert st.status == 0 and st.sweeps == K
     assert st.inner_iters == K * nb * m
-    assert st.max_staleness_seen <= 2
+    assert st.max_staleness_seen <= 1
     beff = orc.lift_bc(b, faces)
     r0 = np.linalg.norm(beff)
     assert orc.residual(beff, host(x)) < 0.5 * r0
@@ -89,7 +89,7 @@ def test_async_uneven_blocks_reach_tolerance(orc):
     beff = orc.lift_bc(b, [None] * 6)
     _, xstar, _, _, _ = orc.block_jacobi(beff, np.zeros(shape), cuts, tol=1e-13, m=20)
     assert rel(host(x), xstar) <= kappa(max(shape)) * 1e-9
-    assert st.max_staleness_seen <= 3
+    assert st.max_staleness_seen <= 2
 
 
 def test_async_not_converged_and_zero_rhs():

@@ -1,0 +1,228 @@
+"""Asynchronous sweeps under a slow block, with the per-sweep trace.
+
+Section 5 names tolerance of slow processes as a reason for asynchronous
+block Jacobi: the other blocks keep iterating on the latest values they
+have (Sections 2.1 and 2.3) instead of waiting.  Here one block's worker
+waits a fixed, bounded time before each of its sweeps (a debugging option
+of the library; every kernel still exits normally), so its neighbours run
+ahead until the staleness bound S stops them.  The library records, for
+every block sweep it starts, the block, its version and the versions of
+its six neighbours it read; the host checks that record against the bound
+and against the sweep counts, and the oracle checks the result.
+"""
+import numpy as np
+import pytest
+
+from paper_2009_12638_amd import inputs, ms
+from gpu_util import dev, host, rel, say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def kappa(n):
+    """condition number of the 7-point operator on an n^3 grid (closed form)"""
+    c = np.cos(np.pi / (n + 1))
+    return (2 + 2 * c) / (2 - 2 * c)
+
+
+def neighbours(g):
+    """face neighbours of every block of a g[0] x g[1] x g[2] block grid, in
+    the order -x,+x,-y,+y,-z,+z (-1: none)"""
+    gx, gy, gz = g
+    nb = np.full((gx * gy * gz, 6), -1, dtype=np.int64)
+    for i in range(gx):
+        for j in range(gy):
+            for k in range(gz):
+                b = (i * gy + j) * gz + k
+                if i > 0:
+                    nb[b, 0] = b - gy * gz
+                if i < gx - 1:
+                    nb[b, 1] = b + gy * gz
+                if j > 0:
+                    nb[b, 2] = b - gz
+                if j < gy - 1:
+                    nb[b, 3] = b + gz
+                if k > 0:
+                    nb[b, 4] = b - 1
+                if k < gz - 1:
+                    nb[b, 5] = b + 1
+    return nb
+
+
+def check_trace(rec, block_sweeps, nbr, S):
+    """Invariants of a recorded asynchronous run.  rec: [n, 8] records
+    (block, version, 6 neighbour versions).  Returns, per record, the gap
+    version - neighbour version on every face (-inf where no neighbour)."""
+    nbk = nbr.shape[0]
+    blk, ver, seen = rec[:, 0], rec[:, 1], rec[:, 2:]
+    assert ((blk >= 0) & (blk < nbk)).all()
+    # every block sweep ran exactly once: block b recorded versions 0..v_b-1
+    for b in range(nbk):
+        vs = np.sort(ver[blk == b])
+        assert np.array_equal(vs, np.arange(block_sweeps[b])), b
+    # neighbours recorded where they exist, and only there
+    has = nbr[blk] >= 0
+    assert ((seen >= 0) == has).all()
+    # the bound: a block starts sweep v+1 only when every neighbour has
+    # finished at least v+1-S sweeps
+    gap = np.where(has, ver[:, None] - seen, -np.inf)
+    assert (gap <= S - 1).all(), gap.max()
+    # a neighbour's version read is one it reached
+    final = np.asarray(block_sweeps)
+    assert (np.where(has, seen <= final[np.maximum(nbr[blk], 0)], True)).all()
+    # per block, the neighbour versions read never go backwards
+    for b in range(nbk):
+        sel = np.nonzero(blk == b)[0]
+        order = sel[np.argsort(ver[sel])]
+        s = seen[order]
+        assert (np.diff(s, axis=0) >= 0).all(), b
+    return gap
+
+
+@pytest.mark.parametrize("S,precision", [(2, "fp64"), (3, "fp64"), (2, "mixed")])
+def test_slow_block_neighbours_hit_the_bound(orc, S, precision):
+    """64 blocks of 16^3 (one worker each); block (1,1,1) waits ~0.1 ms
+    before each sweep.  Its neighbours reach a version gap of exactly S-1 to
+    it and never more, the solve still converges (verified residual, kappa
+    bound) and the slow block sweeps fewer times than the others."""
+    torch = torch_cuda()
+    n, g = 64, 4
+    shape = (n, n, n)
+    cuts = [inputs.uniform_cuts(n, g)] * 3
+    bh = inputs.poisson_randn(shape, 210)
+    h = ms.ms_create(shape, cuts=[list(map(int, c)) for c in cuts], faces=None)
+    b = dev(bh)
+    x = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    slow = (1 * g + 1) * g + 1
+    cap = 400000
+    trace = torch.full((cap, 8), -7, dtype=torch.int32, device="cuda")
+    tol = 1e-8
+    say("async slow block", S, precision)
+    st = ms.ms_solve(h, b, x, tol, 10, "async", staleness=S, precision=precision,
+                     slow_block=slow, slow_sleep=30, trace=trace)
+    assert st.status == 0
+    assert 0 < st.trace_len <= cap
+    rec = trace[: st.trace_len].cpu().numpy().astype(np.int64)
+    bs = np.asarray(st.block_sweeps)
+    assert len(bs) == g ** 3 and bs.sum() == st.trace_len
+    nbr = neighbours((g, g, g))
+    gap = check_trace(rec, bs, nbr, S)
+    assert st.max_staleness_seen == S - 1
+    # the slow block's neighbours ran ahead of it by the whole bound
+    ahead = [gap[i, f] for i in range(len(rec)) for f in range(6)
+             if nbr[rec[i, 0], f] == slow]
+    assert max(ahead) == S - 1
+    assert bs[slow] < bs.max()
+    # adjacent blocks end at most S sweeps apart
+    for blk_ in range(g ** 3):
+        for f in range(6):
+            if nbr[blk_, f] >= 0:
+                assert abs(bs[blk_] - bs[nbr[blk_, f]]) <= S
+    # the result, checked by the oracle: residual and distance to x*
+    beff = orc.lift_bc(bh, [None] * 6)
+    assert orc.residual(beff, host(x)) / np.linalg.norm(beff) <= tol * (1 + 1e-9)
+    _, xstar, _, _ = orc.cg(beff, np.zeros(shape), tol=1e-13, max_iters=20000)
+    err = rel(host(x), xstar)
+    assert err <= kappa(n) * tol
+    print(f"slow block S={S} {precision}: sweeps per block {bs.min()}..{bs.max()} "
+          f"(slow block {bs[slow]}), {st.trace_len} block sweeps, staleness "
+          f"{st.max_staleness_seen}, relaunches {st.relaunches}, error to x* {err:.2e}")
+
+
+def test_trace_without_slow_block_and_sync_block_counts():
+    """Without a slow block the trace still satisfies the bound; a trace
+    smaller than the run keeps its first records and counts the rest; the
+    synchronous solve reports every block at the same sweep count."""
+    torch = torch_cuda()
+    n, g = 48, 3
+    shape = (n, n, n)
+    cuts = [inputs.uniform_cuts(n, g)] * 3
+    h = ms.ms_create(shape, cuts=[list(map(int, c)) for c in cuts], faces=None)
+    b = dev(inputs.poisson_randn(shape, 211))
+    x = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    K = 15
+    cap = 100
+    trace = torch.full((cap, 8), -7, dtype=torch.int32, device="cuda")
+    say("async trace, fixed sweeps")
+    st = ms.ms_solve(h, b, x, 0.0, 6, "async", max_sweeps=K, staleness=2, trace=trace)
+    assert st.status == 0 and st.trace_len == K * g ** 3
+    assert list(st.block_sweeps) == [K] * g ** 3
+    rec = trace.cpu().numpy().astype(np.int64)
+    assert (rec[:, 0] >= 0).all() and (rec[:, 1] >= 0).all() and (rec[:, 1] < K).all()
+    assert st.max_staleness_seen <= 1
+    x.zero_()
+    say("sync block sweep counts")
+    st = ms.ms_solve(h, b, x, 1e-6, 6, "sync")
+    assert list(st.block_sweeps) == [st.sweeps] * g ** 3
+    # bad debugging arguments are argument errors
+    for kw in (dict(slow_block=g ** 3, slow_sleep=1), dict(slow_sleep=-1),
+               dict(slow_sleep=100001)):
+        with pytest.raises(ms.MsError) as e:
+            ms.ms_solve(h, b, x, 1e-6, 6, "async", **kw)
+        assert e.value.status == ms.MS_ERR_ARG
+
+
+def test_async_fullsize_launch_shape(orc):
+    """The asynchronous workers in their full-size launch shape: 256^3,
+    4x4x4 blocks of 64^3 (the one-GPU share of the 512^3 problem), mixed
+    precision, a fixed number of sweeps.  Every block does exactly that many
+    sweeps, the trace satisfies the bound, and the oracle's residual of the
+    result is of the quality of the synchronous method after as many
+    sweeps (the oracle's)."""
+    torch = torch_cuda()
+    w = inputs.workload("poisson256")
+    shape, cuts = w["shape"], w["cuts"]
+    g = len(cuts[0]) - 1
+    h = ms.ms_create(shape, cuts=[list(map(int, c)) for c in cuts], faces=None)
+    b = dev(w["b"])
+    x = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    K = 40
+    cap = K * g ** 3
+    trace = torch.full((cap, 8), -7, dtype=torch.int32, device="cuda")
+    say("async 256^3 fixed sweeps, mixed")
+    st = ms.ms_solve(h, b, x, 0.0, w["m"], "async", max_sweeps=K, staleness=2,
+                     precision="mixed", trace=trace)
+    assert st.status == 0 and st.sweeps == K and st.trace_len == cap
+    bs = np.asarray(st.block_sweeps)
+    assert (bs == K).all()
+    assert st.inner_iters == K * g ** 3 * w["m"]
+    rec = trace.cpu().numpy().astype(np.int64)
+    check_trace(rec, bs, neighbours((g, g, g)), 2)
+    xa = host(x)
+    del x, b, trace
+    ms.ms_destroy(h)
+    torch.cuda.empty_cache()
+    beff = orc.lift_bc(w["b"], [None] * 6)
+    nb = np.linalg.norm(beff)
+    ra = orc.residual(beff, xa) / nb
+    _, _, _, _, hs = orc.block_jacobi(beff, np.zeros(shape), cuts, tol=0.0, m=w["m"],
+                                      max_sweeps=K)
+    assert np.isfinite(xa).all()
+    assert ra < 0.5 * hs[0]
+    assert ra <= 10.0 * hs[K], (ra, hs[K])
+    print(f"async 256^3 mixed, {K} sweeps: oracle residual {ra:.3e}, synchronous {hs[K]:.3e}, "
+          f"staleness {st.max_staleness_seen}")
+
+
+def test_async_c5_shape_to_tolerance(orc):
+    """128^3 with 4x4x4 blocks of 32^3, mixed precision, solved to 1e-8 in
+    asynchronous mode: the oracle's FP64 residual of the result meets the
+    tolerance and the distance to x* (oracle CG) is within kappa * tol."""
+    torch = torch_cuda()
+    n = 128
+    shape = (n, n, n)
+    cuts = [inputs.uniform_cuts(n, 4)] * 3
+    bh = inputs.poisson_randn(shape, 212)
+    h = ms.ms_create(shape, cuts=[list(map(int, c)) for c in cuts], faces=None)
+    x = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    say("async 128^3 to 1e-8, mixed")
+    st = ms.ms_solve(h, dev(bh), x, 1e-8, 10, "async", staleness=2, precision="mixed")
+    assert st.status == 0
+    beff = orc.lift_bc(bh, [None] * 6)
+    xa = host(x)
+    assert orc.residual(beff, xa) / np.linalg.norm(beff) <= 1e-8 * (1 + 1e-9)
+    _, xstar, _, _ = orc.cg(beff, np.zeros(shape), tol=1e-13, max_iters=20000)
+    err = rel(xa, xstar)
+    assert err <= kappa(n) * 1e-8
+    print(f"async 128^3 mixed: ~{st.sweeps} sweeps per block, error to x* {err:.2e}, "
+          f"staleness {st.max_staleness_seen}")

@@ -216,6 +216,6 @@ def test_gmres_async_converges(orc, ov, S, precision):
     ms.ms_destroy(h)
     assert st.status == 0 and st.rel_residual <= 1e-8 and relr <= 1e-8
     assert rel(host(x), xstar) <= _kappa(shape) * 1e-8
-    assert 0 <= st.max_staleness_seen <= S and st.inner_iters > 0
+    assert 0 <= st.max_staleness_seen <= S - 1 and st.inner_iters > 0
     print(f"gmres async o={ov} S={S} {precision}: ~{st.sweeps} sweeps/block, "
           f"staleness {st.max_staleness_seen}, relaunches {st.relaunches}")

@@ -336,6 +336,40 @@ def test_graph_replay_equals_eager(precision):
         ms.ms_solve(h, b, torch.zeros_like(xg), 0.0, 3, "sync", max_sweeps=2, precision=other)
 
 
+def test_set_bc_between_graph_solves(orc):
+    """New boundary data between solves into the same b and x buffers (which
+    a captured sweep graph is keyed on): a face switched off, back on,
+    rewritten in place and every face off.  Graph replays equal eager
+    launches bitwise and the oracle's iterate after the same sweeps."""
+    torch = torch_cuda()
+    shape = (24, 20, 32)
+    cuts = [[0, 12, 24], [0, 20], [0, 16, 32]]
+    faces = inputs.random_faces(*shape, seed=140)
+    bh = inputs.poisson_randn(shape, 141)
+    h, _ = make(ms, shape, cuts, faces)
+    b = dev(bh)
+    x = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    K, m = 8, 6
+
+    def run(graph):
+        x.zero_()
+        ms.ms_solve(h, b, x, 0.0, m, "sync", max_sweeps=K, use_graph=graph, check_every=4)
+        torch.cuda.synchronize()
+        return x.clone()
+
+    steps = [faces, [None] + faces[1:], faces, [2.0 * f for f in faces], [None] * 6,
+             [None] * 5 + [faces[5]]]
+    for q, fs in enumerate(steps):
+        say("set_bc between graph solves, step", q)
+        ms.ms_set_bc(h, [dev(f) for f in fs])
+        xg = run(True)
+        xe = run(False)
+        assert torch.equal(xg, xe), q
+        beff = orc.lift_bc(bh, fs)
+        _, xo, _, _, _ = orc.block_jacobi(beff, np.zeros(shape), cuts, tol=0.0, m=m, max_sweeps=K)
+        assert rel(host(xg), xo) <= 1e-10, (q, rel(host(xg), xo))
+
+
 @pytest.mark.parametrize("precision,widths", [("fp64", [1, 2, 4]), ("mixed", [1, 2, 4, 8])])
 def test_z_vector_widths(orc, precision, widths):
     """Every z access width gives the oracle's iterate (FP64: to 1e-10;
