@@ -290,6 +290,21 @@ ms_status ms_solve_batch(ms_handle *h, int32_t nrhs, const double *b, double *x,
 ms_status ms_residual(ms_handle *h, const double *b, const double *x,
                       double *rel_out, double *abs_out, void *stream);
 
+/* ms_residual for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * it allocates nothing and uses no work buffer of the handle.  Its tile
+ * partials and sums live in a static device array of the library (one per
+ * GPU, 1 MiB, held until the process ends) that holds the partials of at
+ * most 65536 tiles; a handle whose current tiling has more tiles is
+ * rejected (MS_ERR_ARG).  Every call on a GPU shares that GPU's array: calls
+ * that overlap in time on one GPU (other threads, other streams) race and
+ * may return wrong values.  Nothing in the array needs clearing between
+ * calls (every slot a call reads, it writes first).  The current device
+ * must be the handle's (MS_ERR_ARG otherwise).  Arguments, result and
+ * blocking as ms_residual. */
+ms_status ms_residual_noalloc(ms_handle *h, const double *b, const double *x,
+                              double *rel_out, double *abs_out, void *stream);
+
 /* y = A u with zero values outside the interior (the Section 2.1 stencil,
  * boundary data not applied).  u, y device FP64, must not alias.  Enqueued on
  * stream (hipStream_t or NULL); not blocking. */

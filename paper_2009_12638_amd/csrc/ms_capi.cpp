@@ -23,6 +23,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -75,6 +76,7 @@ struct ms_handle {
     double *history_d = nullptr;
     double *faces_d[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     double *scal_d = nullptr;
+    double *scratch_d = nullptr;    // static scratch of the handle's device (ms_residual_noalloc)
     // global CG: the whole grid as a single block
     BlockInfo *cg_block_d = nullptr;
     int *cg_tiles_d = nullptr;
@@ -911,21 +913,59 @@ ms_status solve_sync(ms_handle *h, const double *b, double *x, int nrhs, double 
 
 // ---- residual of an iterate, FP64, without touching the control block ----
 
-ms_status residual_norms(ms_handle *h, const double *b, const double *x, hipStream_t st,
-                         double *nbeff, double *absres) {
+// p64 / pT: per-tile partials (ntiles each; pT takes the region sums of
+// overlap tiles, unused here); sums: two doubles.  Every tile writes its
+// slots, so nothing needs clearing first.
+ms_status residual_norms_in(ms_handle *h, const double *b, const double *x, hipStream_t st,
+                            double *p64, double *pT, double *sums, double *nbeff,
+                            double *absres) {
     const Geom g = geom(h);
-    double *pT = (double *)h->partT;   // region sums (unused here)
     HIPCHK(h, ms::launch_resid<double>(g, h->cur_vz, 0, h->ntiles, 0, b, nullptr, faces(h),
-                                       nullptr, h->part64, pT, nullptr, ms::single_rhs(), st));
-    HIPCHK(h, ms::launch_sum(h->part64, h->ntiles, h->scal_d, st));
+                                       nullptr, p64, pT, nullptr, ms::single_rhs(), st));
+    HIPCHK(h, ms::launch_sum(p64, h->ntiles, sums, st));
     HIPCHK(h, ms::launch_resid<double>(g, h->cur_vz, 0, h->ntiles, 0, b, x, faces(h), nullptr,
-                                       h->part64, pT, nullptr, ms::single_rhs(), st));
-    HIPCHK(h, ms::launch_sum(h->part64, h->ntiles, h->scal_d + 1, st));
+                                       p64, pT, nullptr, ms::single_rhs(), st));
+    HIPCHK(h, ms::launch_sum(p64, h->ntiles, sums + 1, st));
     double ss[2] = {0.0, 0.0};
-    HIPCHK(h, hipMemcpyAsync(ss, h->scal_d, sizeof(ss), hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipMemcpyAsync(ss, sums, sizeof(ss), hipMemcpyDeviceToHost, st));
     HIPCHK(h, hipStreamSynchronize(st));
     *nbeff = std::sqrt(ss[0]);
     *absres = std::sqrt(ss[1]);
+    return MS_OK;
+}
+
+ms_status residual_norms(ms_handle *h, const double *b, const double *x, hipStream_t st,
+                         double *nbeff, double *absres) {
+    return residual_norms_in(h, b, x, st, h->part64, (double *)h->partT, h->scal_d, nbeff,
+                             absres);
+}
+
+// ---- static scratch of the allocation-free residual ------------------------
+// Tile partials (two arrays of kScratchTiles) and two sums.  Each GPU the
+// library runs on holds its own copy until the process ends; host code
+// reaches it only through the address hipGetSymbolAddress returns for the
+// current device, recorded once per device by ms_create.
+constexpr int kScratchTiles = 1 << 16;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) double scratch[2 * kScratchTiles + 32];
+double *g_scratch[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// The scratch address on device dev (which must be current).
+ms_status scratch_setup(int dev, double **out) {
+    *out = nullptr;
+    if (dev < 0 || dev >= kMaxDevices) return MS_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return MS_ERR_HIP;
+        }
+        g_scratch[dev] = (double *)ptr;
+    }
+    *out = g_scratch[dev];
     return MS_OK;
 }
 
@@ -1373,6 +1413,10 @@ ms_status ms_create(const ms_grid *grid, const ms_blocks *blocks, const ms_bc *b
         if (e == hipSuccess) e = hipDeviceGetAttribute(&h->num_cu, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) s = hip_fail(h, e, "ms_create setup");
     }
+    if (s == MS_OK) {
+        s = scratch_setup(dev, &h->scratch_d);
+        if (s != MS_OK) s = fail(h, s, "hipGetSymbolAddress of the static scratch failed");
+    }
     if (s != MS_OK) {
         g_create_error = h->err;
         free_all(h);
@@ -1622,6 +1666,36 @@ ms_status ms_residual(ms_handle *h, const double *b, const double *x, double *re
     hipStream_t st = (hipStream_t)stream;
     double nbeff = 0.0, a = 0.0;
     s = residual_norms(h, b, x, st, &nbeff, &a);
+    if (s != MS_OK) return s;
+    if (abs_out) *abs_out = a;
+    *rel_out = nbeff > 0.0 ? a / nbeff : 0.0;
+    return MS_OK;
+}
+
+ms_status ms_residual_noalloc(ms_handle *h, const double *b, const double *x, double *rel_out,
+                              double *abs_out, void *stream) {
+    if (!h) return fail(nullptr, MS_ERR_ARG, "handle is NULL");
+    if (!rel_out) return fail(h, MS_ERR_ARG, "rel_out is NULL");
+    ms_status s = check_vec(h, b, "b");
+    if (s != MS_OK) return s;
+    s = check_vec(h, x, "x");
+    if (s != MS_OK) return s;
+    if (h->ntiles > kScratchTiles)
+        return fail(h, MS_ERR_ARG, "the handle's tiling has " + std::to_string(h->ntiles) +
+                                       " tiles; the static scratch holds " +
+                                       std::to_string(kScratchTiles));
+    if (!h->scratch_d) return fail(h, MS_ERR_HIP, "static scratch not set up");
+    int dev = -1;
+    HIPCHK(h, hipGetDevice(&dev));
+    bool same = false;
+    if (dev >= 0 && dev < kMaxDevices) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        same = g_scratch[dev] == h->scratch_d;
+    }
+    if (!same) return fail(h, MS_ERR_ARG, "the current device is not the handle's device");
+    double *p64 = h->scratch_d, *pT = p64 + kScratchTiles, *sums = p64 + 2 * kScratchTiles;
+    double nbeff = 0.0, a = 0.0;
+    s = residual_norms_in(h, b, x, (hipStream_t)stream, p64, pT, sums, &nbeff, &a);
     if (s != MS_OK) return s;
     if (abs_out) *abs_out = a;
     *rel_out = nbeff > 0.0 ? a / nbeff : 0.0;

@@ -94,6 +94,9 @@ def lib() -> C.CDLL:
         L.ms_residual.argtypes = [H, C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
                                   C.POINTER(C.c_double), C.c_void_p]
         L.ms_residual.restype = C.c_int
+        L.ms_residual_noalloc.argtypes = [H, C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
+                                          C.POINTER(C.c_double), C.c_void_p]
+        L.ms_residual_noalloc.restype = C.c_int
         L.ms_apply.argtypes = [H, C.c_void_p, C.c_void_p, C.c_void_p]
         L.ms_apply.restype = C.c_int
         L.ms_cg.argtypes = [H, C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
@@ -378,6 +381,16 @@ def ms_residual(h: Handle, b, x, stream=None):
     ab = C.c_double()
     _check(h, lib().ms_residual(h.raw, _vec(h, b, "b"), _vec(h, x, "x"), C.byref(rel), C.byref(ab),
                                 _stream(stream)))
+    return rel.value, ab.value
+
+
+def ms_residual_noalloc(h: Handle, b, x, stream=None):
+    """(relative, absolute) FP64 residual of x, computed in the library's
+    static scratch (no allocation, no handle work buffers)."""
+    rel = C.c_double()
+    ab = C.c_double()
+    _check(h, lib().ms_residual_noalloc(h.raw, _vec(h, b, "b"), _vec(h, x, "x"), C.byref(rel),
+                                        C.byref(ab), _stream(stream)))
     return rel.value, ab.value
 
 
