@@ -14,11 +14,15 @@ kernels that make up a sweep (kernel_bytes).  The same line carries the FP64
 and asynchronous sweeps, the global CG baseline, sweeps on overlapping blocks
 (ovl-*, depth --ovl-depth), sweeps with GMRES inner solves (gmres-*), the
 16-right-hand-side batched workload (batch-*), per-kernel event timings, the
-dominant kernel's fraction of the 8 TB/s HBM peak beside a measured device
-copy, and the CPU oracle timed on this host over a bounded sample of the same
+dominant kernel's fraction of the 8 TB/s HBM peak beside two measured
+ceilings (a device copy through HBM, and a copy of buffers that stay in the
+256 MB on-package cache) with the HBM-streaming kernels listed apart, and
+the CPU oracle timed on this host over a bounded sample of the same
 workload (the only use of the oracle here).  After the timed region one
-configuration (overlap 6, m = 30, mixed by default) is solved to the 1e-8
-relative residual and timed (time_to_tol; --no-tol-solve skips it).  With
+configuration (overlap 6, m = 30) is solved to the 1e-8 relative residual in
+mixed precision and in plain FP64 and timed (time_to_tol; --no-tol-solve
+skips it); the oracle then evaluates the FP64 residual of both final
+iterates on the host, as part of the CPU-baseline leg.  With
 --full-solve every mode is also run to 1e-8 and timed; the final residuals are
 the library's own FP64 evaluation.
 
@@ -428,23 +432,24 @@ def overlap_study(args, torch, ms, inputs):
     return out
 
 
-def tol_solve(args, torch, ms, w):
+def tol_solve(args, torch, ms, w, precision: str):
     """Time to the workload's tolerance for one configuration (synchronous,
-    overlap --tol-overlap, m = --tol-m, --tol-precision), from x = 0."""
+    overlap --tol-overlap, m = --tol-m, given precision), from x = 0.
+    Returns (record, final iterate on the host or None)."""
     shape, cuts = w["shape"], w["cuts"]
     b = torch.from_numpy(w["b"]).to("cuda")
     h = ms.ms_create(shape, cuts=[list(map(int, c)) for c in cuts], faces=None)
     if args.tol_overlap:
         ms.ms_set_overlap(h, args.tol_overlap)
     x = torch.zeros_like(b)
-    ms.ms_solve(h, b, x, 0.0, args.tol_m, "sync", max_sweeps=2, precision=args.tol_precision)
+    ms.ms_solve(h, b, x, 0.0, args.tol_m, "sync", max_sweeps=2, precision=precision)
     x.zero_()
-    log(f"time to {w['tol']}: overlap {args.tol_overlap}, m {args.tol_m}, {args.tol_precision}")
+    log(f"time to {w['tol']}: overlap {args.tol_overlap}, m {args.tol_m}, {precision}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     total = 0
     while True:
-        fs = ms.ms_solve(h, b, x, w["tol"], args.tol_m, "sync", precision=args.tol_precision,
+        fs = ms.ms_solve(h, b, x, w["tol"], args.tol_m, "sync", precision=precision,
                          max_sweeps=200, raise_on_error=False)
         total += fs.sweeps
         if fs.status == ms.MS_OK:
@@ -455,14 +460,16 @@ def tol_solve(args, torch, ms, w):
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     rel, _ = ms.ms_residual(h, b, x)
-    out = {"mode": f"sync-{args.tol_precision}", "overlap": args.tol_overlap,
+    out = {"mode": f"sync-{precision}", "overlap": args.tol_overlap,
            "inner_iters": args.tol_m, "tol": w["tol"], "sweeps": total,
-           "seconds": round(sec, 3), "final_rel_residual_gpu": rel}
-    log(f"time to tol: {total} sweeps, {sec:.2f} s, residual {rel:.3e}")
+           "seconds": round(sec, 3), "ms_per_sweep": round(1e3 * sec / max(total, 1), 3),
+           "final_rel_residual_gpu": rel}
+    log(f"time to tol ({precision}): {total} sweeps, {sec:.2f} s, residual {rel:.3e}")
+    xh = None if args.no_cpu else x.cpu().numpy()
     ms.ms_destroy(h)
     del x, b
     torch.cuda.empty_cache()
-    return out
+    return out, xh
 
 
 def layout_study(args, torch, ms, inputs):
@@ -541,6 +548,30 @@ def copy_peak(torch, gib: int = 1, reps: int = 5) -> float:
     return round(gbps, 1)
 
 
+def cache_copy_peak(torch, mib: int = 48, reps: int = 60) -> float:
+    """Measured copy bandwidth (read + write bytes / time) of a buffer pair
+    that fits in the 256 MB on-package cache but not in the L2s (8 x 4 MB),
+    copied back and forth `reps` times: the streaming ceiling of data that
+    the inner iterations re-read from that cache."""
+    n = (mib << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    c = torch.empty_like(a)
+    for _ in range(4):
+        c.copy_(a)
+        a.copy_(c)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps // 2):
+        c.copy_(a)
+        a.copy_(c)
+    e1.record()
+    torch.cuda.synchronize()
+    gbps = 2 * 8 * n * (reps // 2 * 2) / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, c
+    torch.cuda.empty_cache()
+    return round(gbps, 1)
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -552,20 +583,32 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(w, m: int, sweeps: int):
+def cpu_baseline(w, m: int, sweeps: int, to_tol, finals, tol_overlap: int, tol_m: int,
+                 ovl_sweeps: int):
     """The CPU oracle (test infrastructure, used here only as the reported
-    baseline) timed on this host over `sweeps` FP64 sweeps of the workload."""
+    baseline and as the independent check of the GPU's final iterates) on
+    this host: `sweeps` FP64 sweeps of the workload with m inner iterations;
+    `ovl_sweeps` FP64 sweeps of the time-to-tolerance configuration, whose
+    per-sweep time times the GPU's FP64 sweep count is the oracle's
+    extrapolated time to tolerance; and the oracle's FP64 relative residual
+    of each final GPU iterate in `finals` (written into to_tol)."""
     import numpy as np
     import oracle
     o = oracle.load()
     beff = o.lift_bc(w["b"], [None] * 6)
+    nb = float(np.linalg.norm(beff))
     shape, cuts = w["shape"], w["cuts"]
     N = shape[0] * shape[1] * shape[2]
+    for prec, xh in finals.items():
+        if xh is not None and prec in to_tol:
+            to_tol[prec]["final_rel_residual_oracle"] = o.residual(beff, xh) / nb
+            log(f"cpu oracle: residual of the GPU's {prec} iterate "
+                f"{to_tol[prec]['final_rel_residual_oracle']:.4e}")
     log(f"cpu oracle: {sweeps} FP64 sweeps on {o.num_threads()} threads")
     t0 = time.perf_counter()
     o.block_jacobi(beff, np.zeros(shape), cuts, tol=0.0, m=m, max_sweeps=sweeps)
     sec = time.perf_counter() - t0
-    return {
+    out = {
         "value": round(sweep_bytes(m, 8) * N * sweeps / sec / 1e9, 2),
         "unit": "GB/s",
         "cores": o.num_threads(),
@@ -575,6 +618,19 @@ def cpu_baseline(w, m: int, sweeps: int):
                   f"(m={m}): {sec:.2f} s, {1e3 * sec / sweeps:.0f} ms per sweep",
         "ms_per_sweep": round(1e3 * sec / sweeps, 1),
     }
+    if ovl_sweeps > 0 and "fp64" in to_tol:
+        log(f"cpu oracle: {ovl_sweeps} FP64 sweeps with overlap {tol_overlap}, m {tol_m}")
+        t0 = time.perf_counter()
+        o.multisplit(beff, np.zeros(shape), cuts, tol=0.0, m=tol_m, overlap=tol_overlap,
+                     max_sweeps=ovl_sweeps)
+        per = (time.perf_counter() - t0) / ovl_sweeps
+        gs = to_tol["fp64"]["sweeps"]
+        out["time_to_tol_extrapolated_s"] = round(per * gs, 1)
+        out["time_to_tol_extrapolation"] = (
+            f"extrapolated, not run: {ovl_sweeps} oracle FP64 sweeps with overlap {tol_overlap}, "
+            f"m {tol_m} took {per:.2f} s each; times the {gs} sweeps the GPU's FP64 solve "
+            f"needed to reach {to_tol['fp64']['tol']}")
+    return out
 
 
 def main():
@@ -618,7 +674,11 @@ def main():
                     help="skip the time-to-tolerance solve of the default line")
     ap.add_argument("--tol-overlap", type=int, default=6)
     ap.add_argument("--tol-m", type=int, default=30)
-    ap.add_argument("--tol-precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--tol-precision", default="mixed,fp64",
+                    help="comma list of precisions solved to tolerance (mixed, fp64)")
+    ap.add_argument("--cpu-ovl-sweeps", type=int, default=2,
+                    help="oracle sweeps of the time-to-tolerance configuration timed for its "
+                         "extrapolated time to tolerance (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for hardware counters)")
     args = ap.parse_args()
@@ -660,11 +720,18 @@ def main():
             results[mo] = run_mode(args, torch, ms, wb, mo)
         else:
             results[mo] = run_mode(args, torch, ms, w, mo)
-    to_tol = None if args.no_tol_solve else tol_solve(args, torch, ms, w)
+    to_tol, finals = {}, {}
+    if not args.no_tol_solve:
+        for prec in [p for p in args.tol_precision.split(",") if p]:
+            to_tol[prec], finals[prec] = tol_solve(args, torch, ms, w, prec)
+        if "mixed" in to_tol and "fp64" in to_tol:
+            to_tol["fp64_over_mixed_time"] = round(to_tol["fp64"]["seconds"] /
+                                                   to_tol["mixed"]["seconds"], 3)
     study = overlap_study(args, torch, ms, inputs) if args.overlap_study else None
     layouts = layout_study(args, torch, ms, inputs) if args.layout_study else None
-    log("copy probe: device copy bandwidth")
+    log("copy probe: device copy bandwidth (HBM) and cache-resident copy bandwidth")
     copy_gbps = copy_peak(torch)
+    cache_gbps = cache_copy_peak(torch)
     head = results[modes[0]]
     roof = None
     if "kernels" in head and head["kernels"]:
@@ -674,13 +741,34 @@ def main():
         roof = {"bound": "hbm", "kernel": f"k_{dom_name} ({head['mode']})",
                 "achieved": dom["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(dom["GBps"] / HBM_PEAK_GBPS, 4),
-                "copy_GBps": copy_gbps,
-                "frac_of_copy": round(dom["GBps"] / copy_gbps, 4),
                 "traffic": None if tb is None else round(tb / (dom["avg_us"] * 1e-6) / 1e9, 1),
                 "algorithmic_bytes_per_launch": dom["bytes_per_launch"],
                 "traffic_bytes_per_launch": None if tb is None else int(tb),
-                "unknowns_per_launch": dom["unknowns_per_launch"]}
-    cpu = None if args.no_cpu else cpu_baseline(w, args.m, args.cpu_sweeps)
+                "unknowns_per_launch": dom["unknowns_per_launch"],
+                "served_from": ("the inner-iteration kernels (stencil, update) re-read their "
+                                "launch group's vectors, sized to fit the 256 MB on-package "
+                                "cache, so part of their traffic is served by that cache, not "
+                                "HBM; traffic counts L2 misses (cache hits included); DRAM-side "
+                                "bytes are not measured"),
+                "ceilings": {"hbm_copy_GBps": copy_gbps, "cache_resident_copy_GBps": cache_gbps},
+                "frac_of_cache_resident_copy": round(dom["GBps"] / cache_gbps, 4),
+                "frac_of_hbm_copy": round(dom["GBps"] / copy_gbps, 4)}
+        # the kernels that stream from HBM: outer residual, final update, global CG
+        streaming = {}
+        for mo, res in results.items():
+            for kname in ("resid", "final") if mo == head["mode"] else ():
+                k = res.get("kernels", {}).get(kname)
+                if k:
+                    streaming[f"k_{kname} ({mo})"] = k["GBps"]
+            if mo.startswith("cg-"):
+                for kname, k in res.get("kernels", {}).items():
+                    streaming[f"k_gcg_{kname} ({mo})"] = k["GBps"]
+        roof["hbm_streaming"] = {k: {"achieved": v, "frac_of_hbm_copy": round(v / copy_gbps, 4),
+                                     "frac": round(v / HBM_PEAK_GBPS, 4)}
+                                 for k, v in streaming.items()}
+    cpu = None if args.no_cpu else cpu_baseline(w, args.m, args.cpu_sweeps, to_tol, finals,
+                                                 args.tol_overlap, args.tol_m, args.cpu_ovl_sweeps)
+    finals.clear()
     kind, prec = modes[0].split("-")
     if kind == "batch":
         w = wb

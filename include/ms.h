@@ -305,6 +305,26 @@ ms_status ms_residual(ms_handle *h, const double *b, const double *x,
 ms_status ms_residual_noalloc(ms_handle *h, const double *b, const double *x,
                               double *rel_out, double *abs_out, void *stream);
 
+/* Right-hand side assembly (Section 2.1: the Dirichlet data of boundary
+ * neighbours moved to the right-hand side): b_eff = s * f + sum over each
+ * cell's boundary neighbours of the handle's face values.  For -lap u = f
+ * with spacing h, s = h*h gives the system the solver works on.  f, b_eff:
+ * device FP64, nx*ny*nz; they may be the same buffer (in place) but must not
+ * otherwise overlap.  Enqueued on stream (hipStream_t or NULL); not
+ * blocking.  Errors: MS_ERR_ARG, MS_ERR_HIP. */
+ms_status ms_lift(ms_handle *h, const double *f, double s, double *b_eff, void *stream);
+
+/* Transpose of ms_lift, the last step of an adjoint (backward) solve: with
+ * lambda = A^-1 g for an incoming gradient g (A is symmetric), the gradient
+ * of a loss with respect to f is s * lambda and with respect to face t it is
+ * lambda at the interior cells next to that face (edge and corner nodes do
+ * not enter the 7-point stencil).  grad_f: device FP64 nx*ny*nz or NULL (may
+ * be lambda itself); grad_face: NULL, or six device pointers (each NULL or a
+ * buffer of the face's size, layout as ms_bc).  Enqueued on stream; not
+ * blocking.  Errors: MS_ERR_ARG, MS_ERR_HIP. */
+ms_status ms_lift_adjoint(ms_handle *h, const double *lambda, double s, double *grad_f,
+                          double *const grad_face[6], void *stream);
+
 /* y = A u with zero values outside the interior (the Section 2.1 stencil,
  * boundary data not applied).  u, y device FP64, must not alias.  Enqueued on
  * stream (hipStream_t or NULL); not blocking. */

@@ -11,7 +11,10 @@ gives lambda = A^{-1} dL/du, and
   face, because every face value enters b_eff exactly once, at its
   neighbouring cell (the 7-point stencil never touches edge or corner nodes).
 
-All solves run on the GPU through the C ABI; this module only moves tensors.
+All arithmetic runs on the GPU through the C ABI (the solves, the source
+scaling h^2 f through ms_lift on the handle with zero boundary data, and the
+parameter gradients through ms_lift_adjoint); this module only allocates and
+moves tensors.
 """
 from __future__ import annotations
 
@@ -63,7 +66,10 @@ class PoissonSolve(torch.autograd.Function):
         h2 = solver.spacing ** 2
         face_list = [None if g is None else g.detach().contiguous() for g in faces]
         ms.ms_set_bc(solver.h_fwd, face_list)
-        u = solver._solve(solver.h_fwd, (h2 * f.detach()).contiguous(), solver.tol, "forward")
+        rhs = torch.empty(solver.shape, dtype=torch.float64, device=f.device)
+        # h^2 f (the adjoint handle has zero boundary data, so nothing is lifted)
+        ms.ms_lift(solver.h_adj, f.detach().contiguous(), h2, rhs)
+        u = solver._solve(solver.h_fwd, rhs, solver.tol, "forward")
         ctx.solver = solver
         ctx.has_face = [g is not None for g in faces]
         return u
@@ -74,9 +80,11 @@ class PoissonSolve(torch.autograd.Function):
         lam = solver._solve(solver.h_adj, grad_u.detach().contiguous(), solver.adjoint_tol,
                             "adjoint")
         h2 = solver.spacing ** 2
-        grad_f = h2 * lam
-        # dL/dg for the faces -x, +x, -y, +y, -z, +z
-        cells = [lam[0, :, :], lam[-1, :, :], lam[:, 0, :], lam[:, -1, :],
-                 lam[:, :, 0], lam[:, :, -1]]
-        grad_g = [c.contiguous() if has else None for c, has in zip(cells, ctx.has_face)]
+        nx, ny, nz = solver.shape
+        face_shapes = [(ny, nz), (ny, nz), (nx, nz), (nx, nz), (nx, ny), (nx, ny)]
+        grad_f = torch.empty_like(lam)
+        # dL/dg for the faces -x, +x, -y, +y, -z, +z (those that were given)
+        grad_g = [torch.empty(fs, dtype=torch.float64, device=lam.device) if has else None
+                  for fs, has in zip(face_shapes, ctx.has_face)]
+        ms.ms_lift_adjoint(solver.h_adj, lam, h2, grad_f, grad_g)
         return (None, grad_f, *grad_g)

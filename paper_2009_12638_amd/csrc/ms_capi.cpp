@@ -1702,6 +1702,49 @@ ms_status ms_residual_noalloc(ms_handle *h, const double *b, const double *x, do
     return MS_OK;
 }
 
+ms_status ms_lift(ms_handle *h, const double *f, double s, double *b_eff, void *stream) {
+    if (!h) return fail(nullptr, MS_ERR_ARG, "handle is NULL");
+    ms_status st = check_vec(h, f, "f");
+    if (st != MS_OK) return st;
+    st = check_vec(h, b_eff, "b_eff");
+    if (st != MS_OK) return st;
+    if (!std::isfinite(s)) return fail(h, MS_ERR_ARG, "scale is not finite");
+    const char *ff = (const char *)f, *bb = (const char *)b_eff;
+    const size_t bytes = sizeof(double) * (size_t)h->N;
+    if (ff != bb && ff < bb + bytes && bb < ff + bytes)
+        return fail(h, MS_ERR_ARG, "f and b_eff overlap without being the same buffer");
+    HIPCHK(h, ms::launch_lift(h->nx, h->ny, h->nz, f, s, faces(h), b_eff, (hipStream_t)stream));
+    return MS_OK;
+}
+
+ms_status ms_lift_adjoint(ms_handle *h, const double *lambda, double s, double *grad_f,
+                          double *const grad_face[6], void *stream) {
+    if (!h) return fail(nullptr, MS_ERR_ARG, "handle is NULL");
+    ms_status st = check_vec(h, lambda, "lambda");
+    if (st != MS_OK) return st;
+    if (grad_f) {
+        st = check_vec(h, grad_f, "grad_f");
+        if (st != MS_OK) return st;
+        const char *ll = (const char *)lambda, *gg = (const char *)grad_f;
+        const size_t bytes = sizeof(double) * (size_t)h->N;
+        if (ll != gg && ll < gg + bytes && gg < ll + bytes)
+            return fail(h, MS_ERR_ARG, "lambda and grad_f overlap without being the same buffer");
+    }
+    if (!std::isfinite(s)) return fail(h, MS_ERR_ARG, "scale is not finite");
+    const long long sz[6] = {h->ny * h->nz, h->ny * h->nz, h->nx * h->nz,
+                             h->nx * h->nz, h->nx * h->ny, h->nx * h->ny};
+    double *gfaces[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    for (int t = 0; grad_face && t < 6; t++) {
+        gfaces[t] = grad_face[t];
+        if (gfaces[t] && !dev_range_ok(gfaces[t], sizeof(double) * (size_t)sz[t]))
+            return fail(h, MS_ERR_ARG, "grad_face " + std::to_string(t) +
+                                           " is not a device buffer of the face's size");
+    }
+    HIPCHK(h, ms::launch_lift_adjoint(h->nx, h->ny, h->nz, lambda, s, grad_f, gfaces,
+                                      (hipStream_t)stream));
+    return MS_OK;
+}
+
 ms_status ms_apply(ms_handle *h, const double *u, double *y, void *stream) {
     if (!h) return fail(nullptr, MS_ERR_ARG, "handle is NULL");
     ms_status s = check_vec(h, u, "u");

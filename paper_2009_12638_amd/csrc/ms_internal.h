@@ -196,6 +196,14 @@ hipError_t launch_norm(const double *p64, int ntiles, Ctrl *ctrl, hipStream_t st
 hipError_t launch_apply(long long nx, long long ny, long long nz, const double *u,
                         double *y, hipStream_t st);
 
+// out = s f + boundary values of the faces F (the lifted right-hand side).
+hipError_t launch_lift(long long nx, long long ny, long long nz, const double *f, double s,
+                       Faces F, double *out, hipStream_t st);
+// Transpose of launch_lift: gf = s lam (when gf != null) and, for every
+// non-null gfaces[t], lam at the interior cells next to face t.
+hipError_t launch_lift_adjoint(long long nx, long long ny, long long nz, const double *lam,
+                               double s, double *gf, double *const gfaces[6], hipStream_t st);
+
 // Fixed-order sum of n doubles into *out (device).
 hipError_t launch_sum(const double *v, int n, double *out, hipStream_t st);
 

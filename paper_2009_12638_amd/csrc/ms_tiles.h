@@ -149,6 +149,151 @@ __device__ __forceinline__ void tile_resid(const Geom &g, const Tile &t, long lo
     }
 }
 
+// The outer residual with its loads requested one plane ahead (as the CG
+// phases below): while plane i is computed, plane i + 2 of x (plane i + 1's
+// x + 1 neighbour), plane i + 1 of b and plane i + 1's row and z neighbours
+// that sit in memory are requested, and taken up at the top of the next
+// iteration.  Same arithmetic in the same order as tile_resid.  The residual
+// streams x and b from HBM (neither is re-read within a sweep), which is
+// where the lookahead pays.
+template <typename T, int VZ, int R, bool STORE, bool OVL = false>
+__device__ __forceinline__ void tile_resid_pf(const Geom &g, const Tile &t, long long goff,
+                                              const double *__restrict__ b, const double *x,
+                                              const Faces &F, T *__restrict__ r, double &acc64,
+                                              T &accT) {
+    const long long nx = g.nx, ny = g.ny, nz = g.nz;
+    const long long J0 = t.B.j0 + t.j0, K = t.B.k0 + t.k;
+    const long long P = (long long)t.B.by * t.B.bz;
+    auto gidx = [&](long long I, int rr) { return (I * ny + J0 + rr) * nz + K; };
+    const bool zm_in = K > 0, zp_in = K + VZ < nz;
+    const bool zm_sh = t.zc > 0 && t.lane > 0;
+    const bool zp_sh = t.zc < t.tpr - 1 && t.lane < 63;
+    const bool ym_ld = t.nrows > 0 && J0 > 0;
+    const bool yp_ld = t.nrows > 0 && J0 + t.nrows < ny;
+    const bool ym_sh = t.j0 > 0 && t.lane >= t.tpr;
+    const bool yp_sh = t.j0 + t.nrows < t.B.by && t.lane + t.tpr < 64;
+    const bool have_x = x != nullptr;
+    const bool ym_mem = have_x && ym_ld && !ym_sh, yp_mem = have_x && yp_ld && !yp_sh;
+    const bool zm_mem = have_x && zm_in && !zm_sh, zp_mem = have_x && zp_in && !zp_sh;
+    const int lim = t.xend + 1;   // tile-local planes of x this tile reads end here
+    // x of tile-local plane i on the owned rows (zero outside the grid)
+    auto ld_x = [&](int i, double(&a)[R][VZ]) {
+        const long long I = t.B.i0 + i;
+#pragma unroll
+        for (int rr = 0; rr < R; rr++) {
+#pragma unroll
+            for (int v = 0; v < VZ; v++) a[rr][v] = 0.0;
+            if (have_x && rr < t.nrows && i < lim && I >= 0 && I < nx)
+                vload<double, VZ>(x + gidx(I, rr), a[rr]);
+        }
+    };
+    // b and the memory-held row and z neighbours of plane i
+    double nb[R][VZ], yv[2][VZ], zv[R][2];
+#pragma unroll
+    for (int v = 0; v < VZ; v++) { yv[0][v] = 0.0; yv[1][v] = 0.0; }
+#pragma unroll
+    for (int rr = 0; rr < R; rr++) {
+        zv[rr][0] = zv[rr][1] = 0.0;
+#pragma unroll
+        for (int v = 0; v < VZ; v++) nb[rr][v] = 0.0;
+    }
+    auto ld_aux = [&](int i) {
+        const long long I = t.B.i0 + i;
+        if (ym_mem) vload<double, VZ>(x + gidx(I, -1), yv[0]);
+        if (yp_mem) vload<double, VZ>(x + gidx(I, t.nrows), yv[1]);
+#pragma unroll
+        for (int rr = 0; rr < R; rr++) {
+            if (rr >= t.nrows) continue;
+            const long long c = gidx(I, rr);
+            if (b) vload<double, VZ>(b + c, nb[rr]);
+            if (zm_mem) zv[rr][0] = x[c - 1];
+            if (zp_mem) zv[rr][1] = x[c + VZ];
+        }
+    };
+    double xm[R][VZ], xc[R][VZ], xn[R][VZ];
+    ld_x(t.xbeg - 1, xm);
+    ld_x(t.xbeg, xc);
+    ld_x(t.xbeg + 1, xn);
+    if (t.xbeg < t.xend) ld_aux(t.xbeg);
+    for (int i = t.xbeg; i < t.xend; i++) {
+        const long long I = t.B.i0 + i;
+        // take up what was requested for this plane
+        double xp[R][VZ], bb[R][VZ], ym[VZ], yp[VZ], zmv[R], zpv[R];
+#pragma unroll
+        for (int rr = 0; rr < R; rr++) {
+            zmv[rr] = zv[rr][0];
+            zpv[rr] = zv[rr][1];
+#pragma unroll
+            for (int v = 0; v < VZ; v++) { xp[rr][v] = xn[rr][v]; bb[rr][v] = nb[rr][v]; }
+        }
+#pragma unroll
+        for (int v = 0; v < VZ; v++) {
+            const double su = __shfl_up(xc[R - 1][v], t.tpr, 64);
+            const double sd = __shfl_down(xc[0][v], t.tpr, 64);
+            ym[v] = (have_x && ym_ld) ? (ym_sh ? su : yv[0][v]) : 0.0;
+            yp[v] = (have_x && yp_ld) ? (yp_sh ? sd : yv[1][v]) : 0.0;
+        }
+        // request plane i + 1's data
+        ld_x(i + 2, xn);
+        if (i + 1 < t.xend) ld_aux(i + 1);
+#pragma unroll
+        for (int rr = 0; rr < R; rr++) {
+            const double sl = from_left(xc[rr][VZ - 1]);
+            const double sr = from_right(xc[rr][0]);
+            if (rr >= t.nrows) continue;
+            double zm = 0.0, zp = 0.0;
+            if (have_x && zm_in) zm = zm_sh ? sl : zmv[rr];
+            if (have_x && zp_in) zp = zp_sh ? sr : zpv[rr];
+            const long long J = J0 + rr;
+            // Dirichlet lifting: boundary neighbours' g moved to the right
+            if (I == 0 && F.f[0]) {
+#pragma unroll
+                for (int v = 0; v < VZ; v++) bb[rr][v] += F.f[0][J * nz + K + v];
+            }
+            if (I == nx - 1 && F.f[1]) {
+#pragma unroll
+                for (int v = 0; v < VZ; v++) bb[rr][v] += F.f[1][J * nz + K + v];
+            }
+            if (J == 0 && F.f[2]) {
+#pragma unroll
+                for (int v = 0; v < VZ; v++) bb[rr][v] += F.f[2][I * nz + K + v];
+            }
+            if (J == ny - 1 && F.f[3]) {
+#pragma unroll
+                for (int v = 0; v < VZ; v++) bb[rr][v] += F.f[3][I * nz + K + v];
+            }
+            if (K == 0 && F.f[4]) bb[rr][0] += F.f[4][I * ny + J];
+            if (K + VZ == nz && F.f[5]) bb[rr][VZ - 1] += F.f[5][I * ny + J];
+            T out[VZ];
+#pragma unroll
+            for (int v = 0; v < VZ; v++) {
+                const double left = v == 0 ? zm : xc[rr][v - 1];
+                const double right = v == VZ - 1 ? zp : xc[rr][v + 1];
+                const double up = rr == 0 ? ym[v] : xc[rr - 1][v];
+                const double down = (rr == R - 1 || rr + 1 == t.nrows) ? yp[v] : xc[rr + 1][v];
+                const double ax = 6.0 * xc[rr][v] - xm[rr][v] - xp[rr][v] - up - down - left - right;
+                double rv = bb[rr][v] - ax;
+                if (OVL) {
+                    const int n = axes_out(t.B, i, t.j0 + rr, t.k + v);
+                    if (n > 1) rv = 0.0;
+                    if (n == 0) acc64 += rv * rv;
+                } else {
+                    acc64 += rv * rv;
+                }
+                out[v] = (T)rv;
+                accT += out[v] * out[v];
+            }
+            if (STORE)
+                vstore<T, VZ>(r + (t.B.off - goff) + (long long)i * P +
+                                  (long long)(t.j0 + rr) * t.B.bz + t.k, out);
+        }
+#pragma unroll
+        for (int rr = 0; rr < R; rr++)
+#pragma unroll
+            for (int v = 0; v < VZ; v++) { xm[rr][v] = xc[rr][v]; xc[rr][v] = xp[rr][v]; }
+    }
+}
+
 // Inner CG phase 1 on one tile (Section 3: the inner Krylov solve of a
 // block on A_ii, here CG): p_new = r + beta p_old (p_new = r when !use_old),
 // returns the thread's part of p_new . A_ii p_new (zero outside the block).

@@ -97,6 +97,11 @@ def lib() -> C.CDLL:
         L.ms_residual_noalloc.argtypes = [H, C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
                                           C.POINTER(C.c_double), C.c_void_p]
         L.ms_residual_noalloc.restype = C.c_int
+        L.ms_lift.argtypes = [H, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]
+        L.ms_lift.restype = C.c_int
+        L.ms_lift_adjoint.argtypes = [H, C.c_void_p, C.c_double, C.c_void_p,
+                                      C.POINTER(C.c_void_p), C.c_void_p]
+        L.ms_lift_adjoint.restype = C.c_int
         L.ms_apply.argtypes = [H, C.c_void_p, C.c_void_p, C.c_void_p]
         L.ms_apply.restype = C.c_int
         L.ms_cg.argtypes = [H, C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
@@ -392,6 +397,38 @@ def ms_residual_noalloc(h: Handle, b, x, stream=None):
     _check(h, lib().ms_residual_noalloc(h.raw, _vec(h, b, "b"), _vec(h, x, "x"), C.byref(rel),
                                         C.byref(ab), _stream(stream)))
     return rel.value, ab.value
+
+
+def ms_lift(h: Handle, f, s: float, b_eff, stream=None) -> None:
+    """b_eff = s * f + the handle's boundary values next to each cell."""
+    _check(h, lib().ms_lift(h.raw, _vec(h, f, "f"), float(s), _vec(h, b_eff, "b_eff"),
+                            _stream(stream)))
+
+
+def _face_ptr(h, t, g):
+    if g is None:
+        return None
+    if hasattr(g, "data_ptr"):
+        import torch
+        nx, ny, nz = h.shape
+        want = [(ny, nz), (ny, nz), (nx, nz), (nx, nz), (nx, ny), (nx, ny)][t]
+        if g.dtype != torch.float64 or not g.is_cuda or not g.is_contiguous() \
+                or tuple(g.shape) != want:
+            raise MsError(MS_ERR_ARG, f"face {t} must be a contiguous float64 GPU tensor "
+                                      f"of shape {want}")
+        return g.data_ptr()
+    return int(g)
+
+
+def ms_lift_adjoint(h: Handle, lam, s: float, grad_f=None, grad_faces=None, stream=None) -> None:
+    """grad_f = s * lam; grad_faces[t] = lam at the cells next to face t
+    (entries None are skipped)."""
+    arr = None
+    if grad_faces is not None:
+        arr = (C.c_void_p * 6)(*[_face_ptr(h, t, g) for t, g in enumerate(grad_faces)])
+    _check(h, lib().ms_lift_adjoint(h.raw, _vec(h, lam, "lambda"), float(s),
+                                    None if grad_f is None else _vec(h, grad_f, "grad_f"),
+                                    arr, _stream(stream)))
 
 
 def ms_apply(h: Handle, u, y, stream=None) -> None:

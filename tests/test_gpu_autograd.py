@@ -195,3 +195,42 @@ def test_diff128_adjoint_matches_finite_differences(orc, chunk):
         assert bound <= 5e-2 * abs(ad), (j, bound, ad)
     print(f"diff128 chunk {chunk}: worst relative |fd - ad| / |ad| = {worst:.2e}, "
           f"sweeps {max(t.sweeps for t in stats)}")
+
+
+@pytest.mark.parametrize("shape", [(20, 12, 16), (7, 9, 5)])
+def test_lift_and_its_adjoint(orc, shape):
+    """ms_lift against the oracle's right-hand side assembly, and
+    ms_lift_adjoint as its transpose: <lift(f, g), lam> equals
+    <f, grad_f> + sum_t <g_t, grad_face_t> for random f, g, lam, with each
+    face gradient the slice of lam next to that face."""
+    torch = torch_cuda()
+    from paper_2009_12638_amd import ms
+    rng = np.random.default_rng(60)
+    f = rng.standard_normal(shape)
+    g = inputs.random_faces(*shape, seed=61)
+    lam = rng.standard_normal(shape)
+    s = 0.37
+    h = ms.ms_create(shape, blocks=(1, 1, 1), faces=[dev(a) for a in g])
+    out = torch.empty(shape, dtype=torch.float64, device="cuda")
+    say("ms_lift", shape)
+    ms.ms_lift(h, dev(f), s, out)
+    want = orc.lift_bc(s * f, g)
+    np.testing.assert_allclose(host(out), want, rtol=2e-15, atol=0)
+    gf = torch.empty(shape, dtype=torch.float64, device="cuda")
+    gfaces = [torch.empty(a.shape, dtype=torch.float64, device="cuda") for a in g]
+    gfaces[3] = None   # a face that is not wanted stays out
+    say("ms_lift_adjoint", shape)
+    ms.ms_lift_adjoint(h, dev(lam), s, gf, gfaces)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(host(gf), s * lam)
+    slices = [lam[0], lam[-1], lam[:, 0], lam[:, -1], lam[:, :, 0], lam[:, :, -1]]
+    for t in range(6):
+        if gfaces[t] is not None:
+            np.testing.assert_array_equal(host(gfaces[t]), slices[t])
+    lhs = float((want * lam).sum())
+    rhs = float((f * host(gf)).sum()) + sum(float((g[t] * slices[t]).sum()) for t in range(6))
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + 1.0)
+    # in place: b_eff over f
+    fin = dev(f)
+    ms.ms_lift(h, fin, s, fin)
+    np.testing.assert_allclose(host(fin), want, rtol=2e-15, atol=0)
