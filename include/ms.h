@@ -136,7 +136,25 @@ typedef struct {
                              neighbour).  Sweeps beyond trace_cap are counted
                              in ms_stats.trace_len but not written */
     int32_t trace_cap;
+    int32_t engine;       /* how CG inner solves run (ms_engine, default
+                             MS_ENGINE_AUTO) */
 } ms_opts;
+
+/* Kernels that carry out the CG inner solves.
+ *   MS_ENGINE_PHASE: each CG phase is a launch over a group of blocks whose
+ *     inner vectors stay in the 256 MB on-package cache (synchronous mode);
+ *     one persistent workgroup per block being swept (asynchronous mode).
+ *   MS_ENGINE_TEAM: a team of workgroups of one XCD solves one block at a
+ *     time with the block's inner vectors held in registers and LDS for all
+ *     inner iterations (synchronous and asynchronous mode, single
+ *     right-hand side).  Needs every block's box to fit: with 512-thread
+ *     workgroups of 160 KB LDS, about 20K cells per workgroup (FP32 inner)
+ *     or 10K (FP64), a team being at most 32 workgroups.
+ *   MS_ENGINE_AUTO: TEAM when it fits, else PHASE; setting any tiling
+ *     option of the phase engine (group_blocks, x_chunk, rows, z_vector,
+ *     workers) selects PHASE.
+ * GMRES inner solves and several right-hand sides always use PHASE. */
+typedef enum { MS_ENGINE_AUTO = 0, MS_ENGINE_PHASE = 1, MS_ENGINE_TEAM = 2 } ms_engine;
 
 /* Kernel classes reported by the profile counters of ms_stats. */
 enum {
@@ -147,7 +165,8 @@ enum {
     MS_K_FINAL = 3,   /* last inner step fused with x_new = x + d
                          (GMRES: x_new = x + V y)                        */
     MS_K_CHECK = 4,   /* global residual sum and convergence test          */
-    MS_K_OTHER = 5,
+    MS_K_OTHER = 5,   /* persistent asynchronous workers; resident-team
+                         sweeps (MS_ENGINE_TEAM)                           */
     MS_K_ORTH = 6,    /* GMRES: Hessenberg column, Gram-Schmidt
                          orthogonalisation and norm                        */
     MS_K_HESS = 7,    /* GMRES: per-block start, Givens rotations, solve   */

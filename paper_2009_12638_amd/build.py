@@ -30,23 +30,31 @@ COMMON = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
 SOURCES = [
     ("ms_kernels.hip", []),
     ("ms_gmres.hip", []),
+    ("ms_team.hip", []),
     ("ms_capi.cpp", ["-x", "hip"]),
 ]
 
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
+    objs, procs = [], []
+    # the translation units compile in parallel
     for src, extra in SOURCES:
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
         cmd = [HIPCC, "-c"] + extra + [os.path.join(CSRC, src)] + COMMON + ["-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            sys.stderr.write(r.stdout + r.stderr)
-            raise RuntimeError(f"hipcc failed on {src}")
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE,
+                                            text=True)))
         objs.append(obj)
+    failed = []
+    for src, pr in procs:
+        out, err = pr.communicate()
+        if pr.returncode != 0:
+            sys.stderr.write(out + err)
+            failed.append(src)
+    if failed:
+        raise RuntimeError(f"hipcc failed on {', '.join(failed)}")
     tmp = OUT + f".tmp{os.getpid()}"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH] + objs + ["-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -77,6 +77,11 @@ struct ms_handle {
     double *faces_d[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     double *scal_d = nullptr;
     double *scratch_d = nullptr;    // static scratch of the handle's device (ms_residual_noalloc)
+    // resident-team solves: team memory (sized by team_alloc for the
+    // current geometry) and counters ([0] next block, [1] error code)
+    char *team_mem = nullptr;
+    size_t team_mem_bytes = 0;
+    int *team_ctr = nullptr;
     // global CG: the whole grid as a single block
     BlockInfo *cg_block_d = nullptr;
     int *cg_tiles_d = nullptr;
@@ -280,7 +285,8 @@ void free_all(ms_handle *h) {
     void *ps[] = {h->blocks_d, h->tile_block_d, h->x1, h->r, h->d, h->p0, h->p1, h->part64,
                   h->partT, h->psig, h->prhoA, h->prhoB, h->active, h->ctrl, h->history_d,
                   h->scal_d, h->cg_block_d, h->cg_tiles_d, h->version_d, h->claim_d,
-                  h->nbr_d, h->finished_d, h->board_d, h->V, h->gpart, h->gm};
+                  h->nbr_d, h->finished_d, h->board_d, h->V, h->gpart, h->gm, h->team_mem,
+                  h->team_ctr};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     for (int t = 0; t < 6; t++)
@@ -731,12 +737,277 @@ ms_status sweep_pair_graph(ms_handle *h, const GraphKey &key, const std::vector<
     return MS_OK;
 }
 
+// ---- resident-team solves ------------------------------------------------------
+
+// LDS a team workgroup may use (160 KB per compute unit, less its static
+// shared variables) and the vector slots per thread the kernels exist for.
+constexpr size_t kTeamLds = 163840 - 1024;
+constexpr int kTeamMaxSpin = 1 << 24;   // polls before a team barrier gives up (seconds)
+
+struct TeamPlan {
+    bool ok = false;
+    int T = 0, q = 0, vz = 0, per_xcd = 0;
+    size_t lds = 0;
+    long long face_stride = 0, team_bytes = 0;
+    std::string why;
+};
+
+// Team shape for the handle's blocks (their overlap boxes when overlap is
+// on) with inner type size tsize: the smallest team (most teams at once)
+// whose members' slabs fit in LDS (p and d) and in the vector slots a
+// thread has.
+TeamPlan team_plan(const ms_handle *h, int tsize) {
+    TeamPlan P;
+    if (h->num_cu < 8 || h->num_cu % 8) { P.why = "compute units not a multiple of 8"; return P; }
+    P.per_xcd = h->num_cu / 8;
+    int vz = std::min(h->vzmax, tsize == 4 ? 4 : 2);
+    if (h->overlap > 0) vz = std::min(vz, h->vzbase);
+    P.vz = vz;
+    int minbx = 1 << 30, maxbx = 0;
+    long long maxplane = 0;
+    for (int b = 0; b < h->nblocks; b++) {
+        BlockInfo B;
+        region_box(h, b, B);
+        minbx = std::min(minbx, B.bx);
+        maxbx = std::max(maxbx, B.bx);
+        maxplane = std::max(maxplane, (long long)B.by * B.bz);
+    }
+    P.face_stride = maxplane;
+    const int nthreads = ms::team_threads();
+    for (int T : {1, 2, 4, 8, 16, 32}) {
+        if (T > P.per_xcd || P.per_xcd % T || T > minbx) continue;
+        long long cells = 0;
+        for (int b = 0; b < h->nblocks; b++) {
+            BlockInfo B;
+            region_box(h, b, B);
+            const long long planes = (B.bx + T - 1) / T;
+            cells = std::max(cells, planes * B.by * B.bz);
+        }
+        // p in LDS with a halo plane on each side (r and d in registers)
+        long long pb = 0;
+        for (int b = 0; b < h->nblocks; b++) {
+            BlockInfo B;
+            region_box(h, b, B);
+            pb = std::max(pb, (long long)((B.bx + T - 1) / T + 2) * B.by * B.bz);
+        }
+        const size_t lds = (size_t)pb * tsize;
+        if (lds > kTeamLds) continue;
+        const long long need = (cells / vz + nthreads - 1) / nthreads;
+        int q = 0;
+        for (int c : {2, 4, 8, 12})   // (16 slots spill registers in FP64)
+            if (c >= need) { q = c; break; }
+        if (!q) continue;
+        P.ok = true;
+        P.T = T;
+        P.q = q;
+        P.lds = std::max<size_t>(lds, 16);
+        // each member's two r face planes
+        P.team_bytes = ((ms::team_face_offset() + 2ll * T * P.face_stride * tsize) + 255) / 256 * 256;
+        return P;
+    }
+    P.why = "a block's slab does not fit a team workgroup";
+    return P;
+}
+
+// Team memory for the current geometry, for both inner types (never shrinks).
+ms_status team_alloc(ms_handle *h) {
+    size_t need = 0;
+    for (int tsize : {4, 8}) {
+        const TeamPlan P = team_plan(h, tsize);
+        if (P.ok) need = std::max(need, (size_t)(8 * P.per_xcd / P.T) * (size_t)P.team_bytes);
+    }
+    if (need <= h->team_mem_bytes) return MS_OK;
+    char *fresh = nullptr;
+    const hipError_t e = hipMalloc(&fresh, need);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return MS_OK;   // the team engine stays unavailable for this geometry
+    }
+    if (h->team_mem) (void)hipFree(h->team_mem);
+    h->team_mem = fresh;
+    h->team_mem_bytes = need;
+    return MS_OK;
+}
+
+// ctr: [0] next block, [1] error code (kept), [2..9] workgroups per XCD,
+// [10] workgroups arrived
+__global__ void k_team_reset(char *mem, long long team_bytes, int nteams, int *ctr) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nteams; t += gridDim.x * blockDim.x)
+        *(int *)(mem + (long long)t * team_bytes) = 0;   // barrier counter
+    if (blockIdx.x == 0 && threadIdx.x < 11 && threadIdx.x != 1) ctr[threadIdx.x] = 0;
+}
+
+// The plan to use for a solve, or !ok (with the reason) for the phase engine.
+TeamPlan team_for_solve(ms_handle *h, int tsize, const ms_opts &o, int nrhs) {
+    TeamPlan P;
+    if (o.engine == MS_ENGINE_PHASE) { P.why = "phase engine requested"; return P; }
+    if (o.engine == MS_ENGINE_AUTO &&
+        (o.group_blocks != 0 || o.x_chunk > 0 || o.rows > 0 || o.z_vector > 0 || o.workers > 0)) {
+        P.why = "a tiling option of the phase engine was set";
+        return P;
+    }
+    if (o.inner_solver != MS_INNER_CG) { P.why = "GMRES inner solves"; return P; }
+    if (nrhs != 1) { P.why = "several right-hand sides"; return P; }
+    P = team_plan(h, tsize);
+    if (P.ok && (size_t)(8 * P.per_xcd / P.T) * (size_t)P.team_bytes > h->team_mem_bytes) {
+        P.ok = false;
+        P.why = "team memory not allocated";
+    }
+    return P;
+}
+
+template <typename T>
+ms_status enqueue_team(ms_handle *h, const TeamPlan &P, const double *b, const double *xa,
+                       double *xb, int m, double inner_tol, bool async, AsyncState as, int S,
+                       int limit, double tol2, hipStream_t st) {
+    const int nteams = 8 * P.per_xcd / P.T;
+    hipLaunchKernelGGL(k_team_reset, dim3((nteams + 63) / 64), dim3(64), 0, st, h->team_mem,
+                       (long long)P.team_bytes, nteams, h->team_ctr);
+    HIPCHK(h, hipGetLastError());
+    ms::TeamArgs a;
+    a.T = P.T;
+    a.per_xcd = P.per_xcd;
+    a.nwork = h->nblocks;
+    a.next = h->team_ctr;
+    a.err = h->team_ctr + 1;
+    a.xcd_count = h->team_ctr + 2;
+    a.arrived = h->team_ctr + 10;
+    a.team_mem = h->team_mem;
+    a.team_bytes = P.team_bytes;
+    a.face_stride = P.face_stride;
+    a.m = m;
+    a.inner_tol = inner_tol;
+    a.b = b;
+    a.xa = xa;
+    a.xb = xb;
+    a.F = faces(h);
+    a.p64 = h->part64;
+    a.max_spin = kTeamMaxSpin;
+    Prof p(h, st, MS_K_OTHER);
+    HIPCHK(h, ms::launch_team<T>(geom(h), P.vz, P.q, a, async, as, S, limit, tol2, h->ctrl,
+                                 8 * P.per_xcd, P.lds, st));
+    return MS_OK;
+}
+
+// Error code the team kernels left (0: none); clears it.  Under MS_LOG
+// prints how the last launch's workgroups fell on the XCDs.
+ms_status team_error(ms_handle *h, hipStream_t st) {
+    int ctr[11] = {0};
+    HIPCHK(h, hipMemcpyAsync(ctr, h->team_ctr, sizeof(ctr), hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    const int err = ctr[1];
+    if (getenv("MS_LOG")) {
+        fprintf(stderr, "[libms] team launch: workgroups per XCD");
+        for (int q = 0; q < 8; q++) fprintf(stderr, " %d", ctr[2 + q]);
+        fprintf(stderr, ", arrived %d, error %d\n", ctr[10], err);
+    }
+    if (err == 0) return MS_OK;
+    const int zero = 0;
+    HIPCHK(h, hipMemcpy(h->team_ctr + 1, &zero, sizeof(int), hipMemcpyHostToDevice));
+    return fail(h, MS_ERR_HIP, err == 1   ? "team engine: an XCD id outside 0..7"
+                               : err == 2 ? "team engine: a team barrier timed out"
+                                          : "team engine: the launch's workgroups did not all start");
+}
+
+// Synchronous solve of one right-hand side on the resident-team engine: per
+// sweep one cooperative launch sweeps every block from one outer buffer into
+// the other (team kernels compute each block's residual, CG and update) and
+// writes each block's own-cell residual of the old iterate; a one-workgroup
+// kernel then sums those in block order and tests convergence.
+template <typename T>
+ms_status solve_sync_team(ms_handle *h, const TeamPlan &P, const double *b, double *x,
+                          double tol, int m, const ms_opts &o, ms_stats *stats, hipStream_t st) {
+    double nbeff = 0.0;
+    ms_status s = beff_norms<T>(h, b, 1, st, &nbeff);
+    if (s != MS_OK) return s;
+    if (!std::isfinite(nbeff)) return fail(h, MS_ERR_NONFINITE, "b_eff is not finite");
+    if (nbeff == 0.0) {
+        s = zero_vec(h, x, h->N, st);
+        if (s != MS_OK) return s;
+    }
+    hipLaunchKernelGGL(k_mark_zero_rhs, dim3(1), dim3(64), 0, st, h->ctrl, 1);
+    HIPCHK(h, hipGetLastError());
+    const long long cells_per_sweep = h->N * (long long)m;
+    const int batch = o.check_every > 0
+                          ? o.check_every
+                          : (int)std::max(2ll, std::min(256ll, (1ll << 31) / std::max(1ll, cells_per_sweep)));
+    s = prof_begin(h, o.profile != 0);
+    if (s != MS_OK) return s;
+    double *X[2] = {x, h->x1};
+    // the final check of x^(max_sweeps) uses the residual kernels over all tiles
+    std::vector<Group> all(1);
+    all[0].b0 = 0; all[0].b1 = h->nblocks; all[0].k0 = 0; all[0].k1 = 1;
+    fill_tiles(h, all);
+    const Batch bt = batch_of(h, 1);
+    AsyncState none{};
+    Ctrl c;
+    int next = 0;
+    for (;;) {
+        const int nb = std::min(batch, o.max_sweeps - next);
+        for (int q = 0; q < nb; q++, next++) {
+            s = enqueue_team<T>(h, P, b, X[next % 2], X[(next + 1) % 2], m, o.inner_tol, false,
+                                none, 0, 0, 0.0, st);
+            if (s != MS_OK) return s;
+            Prof p(h, st, MS_K_CHECK);
+            HIPCHK(h, ms::launch_check(h->part64, h->nblocks, tol, 0, h->history_d, kHistoryCap,
+                                       h->ctrl, bt, st));
+        }
+        if (next == o.max_sweeps) {
+            s = enqueue_sweep<T>(h, all, b, X[next % 2], nullptr, tol, m, o.inner_tol,
+                                 MS_INNER_CG, true, bt, st);
+            if (s != MS_OK) return s;
+        }
+        HIPCHK(h, hipMemcpyAsync(&c, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+        HIPCHK(h, hipStreamSynchronize(st));
+        s = team_error(h, st);
+        if (s != MS_OK) return s;
+        prof_collect(h, stats);
+        if (c.done) break;
+        if (next >= o.max_sweeps) return fail(h, MS_ERR_HIP, "device did not finish the solve");
+    }
+    if (c.final_sweep % 2 == 1)
+        HIPCHK(h, hipMemcpyAsync(x, h->x1, sizeof(double) * h->N, hipMemcpyDeviceToDevice, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    if (stats) {
+        stats->sweeps = c.final_sweep;
+        stats->inner_iters = (int64_t)c.inner_snap;
+        stats->rel_residual = nbeff == 0.0 ? 0.0 : c.last_res;
+        if (stats->block_sweeps)
+            for (int q = 0; q < std::min(h->nblocks, stats->block_sweeps_cap); q++)
+                stats->block_sweeps[q] = c.final_sweep;
+        if (stats->history && stats->history_cap > 0) {
+            const int n = std::min(std::min(stats->history_cap, kHistoryCap), c.final_sweep + 1);
+            if (nbeff == 0.0) {
+                stats->history[0] = 0.0;
+                stats->history_len = 1;
+            } else {
+                HIPCHK(h, hipMemcpy(stats->history, h->history_d, sizeof(double) * n,
+                                    hipMemcpyDeviceToHost));
+                stats->history_len = n;
+            }
+        }
+    }
+    switch (c.status) {
+        case 0: return MS_OK;
+        case 4: return fail(h, MS_ERR_NOT_CONVERGED, "max_sweeps reached above tol");
+        case 5: return fail(h, MS_ERR_NONFINITE, "residual became non-finite");
+        case 6: return fail(h, MS_ERR_DIVERGED, "residual grew by 1e6");
+        default: return fail(h, MS_ERR_HIP, "unknown device status");
+    }
+}
+
 // Synchronous solve of nrhs right-hand sides stored one after another in b
 // and x (each nx*ny*nz).  stats: nrhs entries or NULL.
 template <typename T>
 ms_status solve_sync(ms_handle *h, const double *b, double *x, int nrhs, double tol, int m,
                      const ms_opts &o, ms_stats *stats, hipStream_t st) {
     if (nrhs > h->rhs_cap) return fail(h, MS_ERR_ARG, "more right-hand sides than reserved");
+    {
+        const TeamPlan P = team_for_solve(h, (int)sizeof(T), o, nrhs);
+        if (P.ok) return solve_sync_team<T>(h, P, b, x, tol, m, o, stats, st);
+        if (o.engine == MS_ENGINE_TEAM)
+            return fail(h, MS_ERR_UNSUPPORTED, "team engine unavailable: " + P.why);
+    }
     const bool gmres = o.inner_solver == MS_INNER_GMRES;
     if (gmres && (m > h->kry_M || nrhs > h->kry_rhs || h->inner_n > h->kry_inner ||
                   h->tiles_cap > h->kry_tiles))
@@ -1021,12 +1292,15 @@ ms_status solve_async(ms_handle *h, const double *b, double *x, double tol, int 
         HIPCHK(h, hipStreamSynchronize(st));
         return MS_OK;
     }
+    const TeamPlan TP = team_for_solve(h, (int)sizeof(T), o, 1);
+    if (!TP.ok && o.engine == MS_ENGINE_TEAM)
+        return fail(h, MS_ERR_UNSUPPORTED, "team engine unavailable: " + TP.why);
     int per_cu = 0;
     if (gmres)
         HIPCHK(h, ms::async_gmres_occupancy<T>(vz, h->overlap > 0 ? 1 : 0, &per_cu));
     else
         HIPCHK(h, ms::async_occupancy<T>(vz, rows, h->overlap > 0 ? 1 : 0, &per_cu));
-    if (per_cu < 1) return fail(h, MS_ERR_HIP, "asynchronous kernel cannot be resident");
+    if (per_cu < 1 && !TP.ok) return fail(h, MS_ERR_HIP, "asynchronous kernel cannot be resident");
     int grid = (int)std::min<long long>(h->nblocks, (long long)per_cu * h->num_cu);
     if (o.workers > 0) grid = std::min(grid, o.workers);
     const int nbk = h->nblocks;
@@ -1085,7 +1359,11 @@ ms_status solve_async(ms_handle *h, const double *b, double *x, double tol, int 
                            h->claim_d, h->board_d, nbk, h->finished_d, already, h->ctrl, 0);
         HIPCHK(h, hipGetLastError());
         first = false;
-        {
+        if (TP.ok) {
+            s = enqueue_team<T>(h, TP, b, x, x, m, o.inner_tol, true, as, o.staleness, limit, tol2,
+                                st);
+            if (s != MS_OK) return s;
+        } else {
             Prof p(h, st, MS_K_OTHER);
             if (gmres)
                 HIPCHK(h, ms::launch_async_gmres<T>(geom(h), vz, grid, b, x, faces(h), (T *)h->V,
@@ -1099,6 +1377,10 @@ ms_status solve_async(ms_handle *h, const double *b, double *x, double tol, int 
         HIPCHK(h, hipMemcpyAsync(ver.data(), h->version_d, sizeof(int) * nbk,
                                  hipMemcpyDeviceToHost, st));
         HIPCHK(h, hipStreamSynchronize(st));
+        if (TP.ok) {
+            s = team_error(h, st);
+            if (s != MS_OK) return s;
+        }
         prof_collect(h, stats);
         minv = *std::min_element(ver.begin(), ver.end());
         maxv = *std::max_element(ver.begin(), ver.end());
@@ -1282,6 +1564,7 @@ void ms_default_opts(ms_opts *o) {
     o->slow_sleep = 0;
     o->trace = nullptr;
     o->trace_cap = 0;
+    o->engine = MS_ENGINE_AUTO;
 }
 
 const char *ms_status_string(ms_status s) {
@@ -1382,6 +1665,7 @@ ms_status ms_create(const ms_grid *grid, const ms_blocks *blocks, const ms_bc *b
         {(void **)&h->nbr_d, sizeof(int) * 6 * (size_t)h->nblocks},
         {(void **)&h->finished_d, 64},
         {(void **)&h->board_d, sizeof(double) * (size_t)h->nblocks},
+        {(void **)&h->team_ctr, 64},
     };
     for (auto &a : allocs) {
         e = hipMalloc(a.p, a.n);
@@ -1417,6 +1701,11 @@ ms_status ms_create(const ms_grid *grid, const ms_blocks *blocks, const ms_bc *b
         s = scratch_setup(dev, &h->scratch_d);
         if (s != MS_OK) s = fail(h, s, "hipGetSymbolAddress of the static scratch failed");
     }
+    if (s == MS_OK) {
+        e = hipMemset(h->team_ctr, 0, 64);
+        if (e != hipSuccess) s = hip_fail(h, e, "ms_create setup");
+    }
+    if (s == MS_OK) s = team_alloc(h);
     if (s != MS_OK) {
         g_create_error = h->err;
         free_all(h);
@@ -1473,6 +1762,8 @@ static ms_status check_solve(ms_handle *h, const double *b, double *x, long long
     if (o.slow_sleep > 0 && o.slow_block >= h->nblocks)
         return fail(h, MS_ERR_ARG, "slow_block is not a block of the partition");
     if (o.trace_cap < 0) return fail(h, MS_ERR_ARG, "trace_cap must be >= 0");
+    if (o.engine != MS_ENGINE_AUTO && o.engine != MS_ENGINE_PHASE && o.engine != MS_ENGINE_TEAM)
+        return fail(h, MS_ERR_ARG, "unknown engine");
     if (o.trace_cap > 0 && (!o.trace || !dev_range_ok(o.trace, sizeof(int32_t) * 8 * (size_t)o.trace_cap)))
         return fail(h, MS_ERR_ARG, "trace is not a device buffer of trace_cap records");
     return MS_OK;
@@ -1594,7 +1885,9 @@ ms_status ms_set_overlap(ms_handle *h, int32_t overlap) {
     h->overlap = overlap;
     h->inner_n = inner;
     h->cur_vz = 0;
-    return set_tiling(h, std::min(h->vzmax, 2), 16, 1, nullptr);
+    ms_status st = set_tiling(h, std::min(h->vzmax, 2), 16, 1, nullptr);
+    if (st == MS_OK) st = team_alloc(h);
+    return st;
 }
 
 ms_status ms_reserve_krylov(ms_handle *h, int32_t max_inner) {

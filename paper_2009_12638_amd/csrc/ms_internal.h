@@ -111,6 +111,32 @@ struct AsyncState {
 };
 constexpr int kTraceInts = 8;
 
+// Resident-team block solves (ms_team.hip): T workgroups of one XCD per
+// team, one block per team at a time, the block's inner vectors held in
+// registers and LDS.
+struct TeamArgs {
+    int T;                 // workgroups per team
+    int per_xcd;           // workgroups of the launch per XCD expected (grid / 8)
+    int nwork;             // sync: blocks swept by the launch (all of them)
+    int *next;             // sync: next block to hand out (zeroed before each launch)
+    int *err;              // 0, or 1: an XCD id outside 0..7, 2: a team barrier
+                           // timed out, 3: the launch's workgroups did not all start
+    int *xcd_count;        // [8] workgroups that arrived on each XCD (zeroed per launch)
+    int *arrived;          // workgroups that arrived (zeroed per launch)
+    char *team_mem;        // team_bytes per team: barrier counter, work
+                           // ring, partial sums, slab faces
+    long long team_bytes;
+    long long face_stride; // elements per slab face (>= the largest box's y*z)
+    int m;                 // inner iterations
+    double inner_tol;
+    const double *b;
+    const double *xa;      // x read by the residual
+    double *xb;            // x written by the update (== xa in async mode)
+    Faces F;
+    double *p64;           // sync: own-cell residual^2 per block
+    int max_spin;          // polls before a team barrier gives up
+};
+
 // ---- kernel launches ------------------------------------------------------
 // Profiling: the host sets events that the next launch of this thread
 // records its start and end into.  They are attached to the dispatch itself
@@ -227,6 +253,17 @@ hipError_t launch_gm_finish(const Geom &g, int vz, int t0, int t1, int b0, int b
                             GmArgs a, Ctrl *ctrl, hipStream_t st, int part);
 int gm_record_doubles(int M);
 int gm_max_planes();
+
+// Resident-team sweep (sync: every block from a.xa into a.xb; async: claimed
+// blocks in place) on grid = 8 * a.per_xcd workgroups of team_threads()
+// threads, launched cooperatively; vz: z cells per vector, q: vectors per
+// thread (1, 2, 4 or 8), lds: bytes of dynamic LDS (the largest slab).
+template <typename T>
+hipError_t launch_team(const Geom &g, int vz, int q, const TeamArgs &a, bool async,
+                       AsyncState as, int S, int max_sweeps, double tol2, Ctrl *ctrl, int grid,
+                       size_t lds, hipStream_t st);
+int team_threads();
+int team_face_offset();
 
 // Asynchronous sweeps with GMRES inner solves (persistent workers, as
 // launch_async; Krylov vectors and records of right-hand side 0).

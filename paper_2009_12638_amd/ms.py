@@ -20,6 +20,8 @@ MS_ERR_NOT_CONVERGED, MS_ERR_NONFINITE, MS_ERR_DIVERGED, MS_ERR_UNSUPPORTED = 4,
 MS_SYNC, MS_ASYNC = 0, 1
 MS_FP64, MS_MIXED = 0, 1
 MS_INNER_CG, MS_INNER_GMRES = 0, 1
+MS_ENGINE_AUTO, MS_ENGINE_PHASE, MS_ENGINE_TEAM = 0, 1, 2
+ENGINES = {"auto": MS_ENGINE_AUTO, "phase": MS_ENGINE_PHASE, "team": MS_ENGINE_TEAM}
 KERNEL_CLASSES = ["resid", "stencil", "update", "final", "check", "other", "orth", "hess"]
 
 
@@ -52,7 +54,7 @@ class ms_opts(C.Structure):
                 ("profile", C.c_int32), ("use_graph", C.c_int32), ("rows", C.c_int32),
                 ("workers", C.c_int32), ("inner_solver", C.c_int32), ("z_vector", C.c_int32),
                 ("slow_block", C.c_int32), ("slow_sleep", C.c_int32),
-                ("trace", C.c_void_p), ("trace_cap", C.c_int32)]
+                ("trace", C.c_void_p), ("trace_cap", C.c_int32), ("engine", C.c_int32)]
 
 
 class ms_stats(C.Structure):
@@ -271,7 +273,7 @@ class Stats:
 def _opts(precision="fp64", max_sweeps=100000, inner_tol=0.0, staleness=2, stream=None,
           check_every=0, group_blocks=0, x_chunk=0, profile=False, use_graph=True,
           rows=0, workers=0, inner="cg", z_vector=0, slow_block=-1, slow_sleep=0,
-          trace=None) -> ms_opts:
+          trace=None, engine="auto") -> ms_opts:
     o = ms_default_opts()
     o.max_sweeps = int(max_sweeps)
     o.inner_tol = float(inner_tol)
@@ -289,6 +291,7 @@ def _opts(precision="fp64", max_sweeps=100000, inner_tol=0.0, staleness=2, strea
     o.inner_solver = {"cg": MS_INNER_CG, "gmres": MS_INNER_GMRES}[inner] \
         if isinstance(inner, str) else int(inner)
     o.z_vector = int(z_vector)
+    o.engine = ENGINES[engine] if isinstance(engine, str) else int(engine)
     o.slow_block = int(slow_block)
     o.slow_sleep = int(slow_sleep)
     if trace is not None:

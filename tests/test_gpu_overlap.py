@@ -170,7 +170,8 @@ def test_overlap_batch_matches_single(precision):
     ms.ms_solve_batch(h, B, X, 0.0, 5, max_sweeps=11, precision=precision)
     for k in range(3):
         x = torch.zeros(shape, dtype=torch.float64, device="cuda")
-        ms.ms_solve(h, B[k].contiguous(), x, 0.0, 5, "sync", max_sweeps=11, precision=precision)
+        ms.ms_solve(h, B[k].contiguous(), x, 0.0, 5, "sync", max_sweeps=11, precision=precision,
+                    engine="phase")   # the engine of the batch
         assert torch.equal(x, X[k]), k
     ms.ms_destroy(h)
 

@@ -278,7 +278,8 @@ def test_batch_of_rhs_matches_single_solves(orc):
     sts = ms.ms_solve_batch(h, B, X, 0.0, m, max_sweeps=K, history=K + 1)
     for k in range(4):
         x1 = torch.zeros(shape, dtype=torch.float64, device="cuda")
-        ms.ms_solve(h, dev(bs[k]), x1, 0.0, m, "sync", max_sweeps=K)
+        # the batch runs on the phase engine: compare with the same engine
+        ms.ms_solve(h, dev(bs[k]), x1, 0.0, m, "sync", max_sweeps=K, engine="phase")
         assert torch.equal(X[k], x1), k
         beff = orc.lift_bc(bs[k], faces)
         _, xo, _, _, hist = orc.block_jacobi(beff, np.zeros(shape), cuts, tol=0.0, m=m,
