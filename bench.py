@@ -7,10 +7,15 @@ is one outer sweep (residual with halo reads, 10 inner CG iterations on every
 block, outer update), timed with tol <= 0 so exactly --steps sweeps run.
 Inputs are resident in GPU memory before timing starts.
 
-Prints one JSON line.  `value` is the whole-sweep memory throughput of the
+Prints one JSON line.  `value` is the algorithmic throughput of the
 headline run (synchronous sweeps, mixed precision: FP32 inner CG, FP64
-residual/test/update) in GB/s, from the compulsory bytes per unknown of the
-kernels that make up a sweep (kernel_bytes).  The same line carries the FP64
+residual/test/update) in GB/s: the method's bytes per unknown per sweep (10
+words per unknown per inner CG iteration plus the outer residual and update,
+model_sweep_bytes) over the measured sweep time.  The library runs those
+sweeps on its resident-team engine, which keeps a block's inner vectors on
+chip; the phase-* modes run the same sweeps on the phase engine, whose
+kernels stream every inner vector through memory (their compulsory bytes per
+kernel: kernel_bytes).  The same line carries the FP64
 and asynchronous sweeps, the global CG baseline, sweeps on overlapping blocks
 (ovl-*, depth --ovl-depth), sweeps with GMRES inner solves (gmres-*), the
 16-right-hand-side batched workload (batch-*), per-kernel event timings, the
@@ -41,17 +46,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "time-to-1e-8 residual & stencil/CG HBM GB/s, 512^3 Laplace; mixed vs plain FP64"
-# the sources of the sweep kernels: the traffic counters are only reused while
-# these are unchanged
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2009_12638_amd", "csrc", f)
-                  for f in ("ms_kernels.hip", "ms_device.h", "ms_tiles.h")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_bumps512_sync_mixed.json")
+# counter readings of the sweep kernels, reused only while the kernel
+# sources are unchanged (paper_2009_12638_amd.pmc writes them)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_bumps512.json")
 HBM_PEAK_GBPS = 8000.0
-ALL_MODES = ["sync-mixed", "sync-fp64", "async-mixed", "async-fp64", "cg-fp64",
+# LDS bandwidth of the chip: 256 compute units x 128 bytes per clock x 2.4 GHz
+LDS_PEAK_GBPS = 256 * 128 * 2.4
+# Resident-team sweeps: HBM bytes per unknown a sweep must move (x and b
+# read, x written; the inner vectors stay on chip) and LDS bytes per unknown
+# per inner iteration (two stencil applies of p from LDS: 5 vector loads of VZ
+# cells and 2 single-cell loads per VZ cells; p read and written once),
+# VZ = 4 in FP32 and 2 in FP64.
+TEAM_HBM_BYTES = 24
+
+
+def team_lds_bytes(T: int) -> float:
+    vz = 4 if T == 4 else 2
+    return 2 * (5 + 2 / vz) * T + 2 * T
+ALL_MODES = ["sync-mixed", "sync-fp64", "phase-mixed", "phase-fp64", "async-mixed",
+             "async-fp64", "cg-fp64",
              "batch-mixed", "batch-fp64", "gmres-mixed", "gmres-fp64", "ovl-mixed", "ovl-fp64",
              "grad-fp64", "grad-mixed"]
-DEFAULT_MODES = ("sync-mixed,sync-fp64,async-mixed,cg-fp64,ovl-mixed,gmres-mixed,batch-mixed,"
-                 "grad-fp64")
+DEFAULT_MODES = ("sync-mixed,sync-fp64,phase-mixed,phase-fp64,async-mixed,async-fp64,cg-fp64,"
+                 "ovl-mixed,gmres-mixed,batch-mixed,grad-fp64")
 BATCH_WORKLOAD = "uneven384"   # batched modes: 16 right-hand sides, uneven blocks
 DIFF_WORKLOAD = "diff128"      # grad modes: forward + adjoint solve, 4^3 blocks of 32^3
 
@@ -205,6 +222,12 @@ def grad_mode(args, torch, ms, mode: str):
 
 def run_mode(args, torch, ms, w, mode: str):
     kind, prec = mode.split("-")
+    # phase-*: synchronous sweeps on the phase engine (the HBM-streaming
+    # kernels); every other mode lets the library pick (the resident-team
+    # engine wherever a block fits a team)
+    engine = "auto"
+    if kind == "phase":
+        kind, engine = "sync", "phase"
     shape, cuts = w["shape"], w["cuts"]
     N = shape[0] * shape[1] * shape[2]
     m = args.m
@@ -277,7 +300,7 @@ def run_mode(args, torch, ms, w, mode: str):
             return ms.ms_solve(h, b, x, 0.0, m, "sync", max_sweeps=k, precision=precision,
                                inner="gmres", **kw)
         return ms.ms_solve(h, b, x, 0.0, m, "sync" if kind == "ovl" else kind, max_sweeps=k,
-                           precision=precision, **tile_kw, **kw)
+                           precision=precision, engine=engine, **tile_kw, **kw)
 
     log(f"{mode}: warmup {args.warmup}")
     if args.warmup > 0:
@@ -288,8 +311,10 @@ def run_mode(args, torch, ms, w, mode: str):
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     log(f"{mode}: {args.steps} steps in {sec:.3f} s")
+    team = getattr(st, "engine", "") == "team"
     res = {"mode": mode, "steps": args.steps, "seconds": round(sec, 4),
-           "ms_per_step": round(1e3 * sec / args.steps, 4), "nrhs": nrhs, "inner_iters": m}
+           "ms_per_step": round(1e3 * sec / args.steps, 4), "nrhs": nrhs, "inner_iters": m,
+           "engine": getattr(st, "engine", "") or "phase"}
     if args.inner_tol > 0:
         res["inner_tol"] = args.inner_tol   # GBps assume m iterations: an upper bound here
     if ov:
@@ -303,6 +328,14 @@ def run_mode(args, torch, ms, w, mode: str):
         bpu = sum(CG_BYTES.values())
         res["GBps"] = round(bpu * N * args.steps / sec / 1e9, 1)
         res["bytes_per_unknown_step"] = bpu
+    elif team:
+        # what the sweep moves through HBM (x, b over the inner-solve boxes,
+        # x written)
+        sweep_total = 16 * NR + 8 * N
+        res["GBps"] = round(sweep_total * args.steps / sec / 1e9, 1)
+        res["bytes_per_unknown_step"] = TEAM_HBM_BYTES
+        res["model_GBps"] = round(model_sweep_bytes(m, T == 4) * N * args.steps / sec / 1e9, 1)
+        res["unknown_iters_per_s"] = N * m * args.steps / sec
     else:
         gm = kind == "gmres"
         fin = dict((kernel_bytes_gmres if gm else kernel_bytes)(m, T))["final"]
@@ -313,7 +346,20 @@ def run_mode(args, torch, ms, w, mode: str):
         res["unknown_iters_per_s"] = N * nrhs * m * args.steps / sec
     if kind == "async":
         res["max_staleness_seen"] = st.max_staleness_seen
-    if kind in ("sync", "cg", "batch", "gmres", "ovl"):
+    if team and kind in ("sync", "ovl"):
+        # one cooperative launch per sweep: the method's bytes per unknown
+        # per sweep, and the LDS bytes of the inner iterations
+        prof = step(max(2, min(args.steps, 5)), profile=True)
+        k = per_kernel(prof, N, {"other": [model_sweep_bytes(m, T == 4)]}).get("other")
+        if k:
+            k["bytes_per_unknown"] = [model_sweep_bytes(m, T == 4)]
+            avg = k["avg_us"] * 1e-6
+            k["hbm_GBps"] = round((16 * NR + 8 * N) / avg / 1e9, 1)
+            k["hbm_bytes_per_launch"] = 16 * NR + 8 * N
+            k["lds_bytes_per_launch"] = int(team_lds_bytes(T) * m * NR)
+            k["lds_GBps"] = round(team_lds_bytes(T) * m * NR / avg / 1e9, 1)
+            res["kernels"] = {"team": k}
+    elif kind in ("sync", "cg", "batch", "gmres", "ovl"):
         prof = step(max(2, min(args.steps, 5)), profile=True)
         if kind in ("sync", "batch", "gmres", "ovl"):
             lists = {}
@@ -358,6 +404,8 @@ def run_mode(args, torch, ms, w, mode: str):
             total = inner_total = 0
             extra = {"inner": "gmres"} if kind == "gmres" else dict(tile_kw)
             while True:
+                if kind != "gmres":
+                    extra["engine"] = engine
                 fs = ms.ms_solve(h, b, x, w["tol"], m,
                                  "sync" if kind in ("gmres", "ovl") else kind,
                                  precision=precision, max_sweeps=args.chunk,
@@ -460,7 +508,8 @@ def tol_solve(args, torch, ms, w, precision: str):
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     rel, _ = ms.ms_residual(h, b, x)
-    out = {"mode": f"sync-{precision}", "overlap": args.tol_overlap,
+    out = {"mode": f"sync-{precision}", "engine": fs.engine or "phase",
+           "overlap": args.tol_overlap,
            "inner_iters": args.tol_m, "tol": w["tol"], "sweeps": total,
            "seconds": round(sec, 3), "ms_per_sweep": round(1e3 * sec / max(total, 1), 3),
            "final_rel_residual_gpu": rel}
@@ -509,15 +558,11 @@ def measured_traffic(kernel: str, unknowns_per_launch: int):
     summary (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a
     plain copy of known size), or None when the kernels or the launch size
     changed since the counters were taken."""
-    import hashlib
+    from paper_2009_12638_amd import pmc
     try:
         with open(TRAFFIC_FILE) as f:
             data = json.load(f)
-        h = hashlib.sha1()
-        for src in KERNEL_SOURCES:
-            with open(src, "rb") as f:
-                h.update(f.read())
-        sha = h.hexdigest()
+        sha = pmc.source_sha1()
     except (OSError, ValueError):
         return None
     k = data.get("kernels", {}).get(kernel)
@@ -572,6 +617,83 @@ def cache_copy_peak(torch, mib: int = 48, reps: int = 60) -> float:
     return round(gbps, 1)
 
 
+def team_roofline(head, ceilings):
+    """Roofline of the resident-team sweep kernel (one launch per sweep).
+    achieved: the method's bytes per unknown per sweep (10 words per unknown
+    per CG iteration plus the outer residual and update) times the unknowns,
+    over the launch's average duration; the kernel keeps the inner vectors on
+    chip, so this exceeds what HBM could stream.  Beside it: the bytes the
+    kernel does move through HBM (x and b read, x written) and the LDS bytes
+    of its inner iterations against the chip's LDS bandwidth."""
+    k = head["kernels"]["team"]
+    prec = head["mode"].split("-")[1]
+    tb = measured_traffic(f"team:{prec}", k["unknowns_per_launch"])
+    avg = k["avg_us"] * 1e-6
+    return {
+        "bound": "hbm", "kernel": f"k_team ({head['mode']})",
+        "achieved": k["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+        "frac": round(k["GBps"] / HBM_PEAK_GBPS, 4),
+        "traffic": None if tb is None else round(tb / avg / 1e9, 1),
+        "algorithmic_bytes_per_launch": k["bytes_per_launch"],
+        "traffic_bytes_per_launch": None if tb is None else int(tb),
+        "unknowns_per_launch": k["unknowns_per_launch"],
+        "launch_avg_us": k["avg_us"],
+        "note": ("achieved counts the method's streaming bytes (10 words per unknown per inner "
+                 "iteration plus residual and update); the team kernel keeps r, d and p on chip "
+                 "for all inner iterations, so frac above 1 is the factor by which it beats the "
+                 "HBM roofline of the streaming formulation; traffic is what it does fetch and "
+                 "write past the L2s"),
+        "hbm_moved": {"bytes_per_launch": k["hbm_bytes_per_launch"],
+                      "bytes_per_unknown": TEAM_HBM_BYTES, "achieved": k["hbm_GBps"],
+                      "frac": round(k["hbm_GBps"] / HBM_PEAK_GBPS, 4)},
+        "lds": {"bytes_per_launch": k["lds_bytes_per_launch"], "achieved": k["lds_GBps"],
+                "peak": round(LDS_PEAK_GBPS, 1),
+                "frac": round(k["lds_GBps"] / LDS_PEAK_GBPS, 4)},
+        "ceilings": ceilings,
+    }
+
+
+def phase_roofline(res, results, ceilings):
+    """Roofline of the phase engine's dominant kernel (the HBM-streaming
+    inner-iteration kernels), with the kernels that stream from HBM listed
+    apart."""
+    copy_gbps, cache_gbps = ceilings["hbm_copy_GBps"], ceilings["cache_resident_copy_GBps"]
+    dom_name, dom = max(res["kernels"].items(), key=lambda kv: kv[1]["total_ms"])
+    prec = res["mode"].split("-")[1]
+    tb = (measured_traffic(f"{dom_name}:{prec}", dom["unknowns_per_launch"])
+          if not res.get("overlap") and res.get("nrhs", 1) == 1 else None)
+    roof = {"bound": "hbm", "kernel": f"k_{dom_name} ({res['mode']})",
+            "achieved": dom["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(dom["GBps"] / HBM_PEAK_GBPS, 4),
+            "traffic": None if tb is None else round(tb / (dom["avg_us"] * 1e-6) / 1e9, 1),
+            "algorithmic_bytes_per_launch": dom["bytes_per_launch"],
+            "traffic_bytes_per_launch": None if tb is None else int(tb),
+            "unknowns_per_launch": dom["unknowns_per_launch"],
+            "launch_avg_us": dom["avg_us"],
+            "served_from": ("the inner-iteration kernels (stencil, update) re-read their "
+                            "launch group's vectors, sized to fit the 256 MB on-package "
+                            "cache, so part of their traffic is served by that cache, not "
+                            "HBM; traffic counts L2 misses (cache hits included); DRAM-side "
+                            "bytes are not measured"),
+            "ceilings": ceilings,
+            "frac_of_cache_resident_copy": round(dom["GBps"] / cache_gbps, 4),
+            "frac_of_hbm_copy": round(dom["GBps"] / copy_gbps, 4)}
+    # the kernels that stream from HBM: outer residual, final update, global CG
+    streaming = {}
+    for mo, r in results.items():
+        for kname in ("resid", "final") if mo == res["mode"] else ():
+            k = r.get("kernels", {}).get(kname)
+            if k:
+                streaming[f"k_{kname} ({mo})"] = k["GBps"]
+        if mo.startswith("cg-"):
+            for kname, k in r.get("kernels", {}).items():
+                streaming[f"k_gcg_{kname} ({mo})"] = k["GBps"]
+    roof["hbm_streaming"] = {k: {"achieved": v, "frac_of_hbm_copy": round(v / copy_gbps, 4),
+                                 "frac": round(v / HBM_PEAK_GBPS, 4)}
+                             for k, v in streaming.items()}
+    return roof
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -609,7 +731,7 @@ def cpu_baseline(w, m: int, sweeps: int, to_tol, finals, tol_overlap: int, tol_m
     o.block_jacobi(beff, np.zeros(shape), cuts, tol=0.0, m=m, max_sweeps=sweeps)
     sec = time.perf_counter() - t0
     out = {
-        "value": round(sweep_bytes(m, 8) * N * sweeps / sec / 1e9, 2),
+        "value": round(model_sweep_bytes(m, False) * N * sweeps / sec / 1e9, 2),
         "unit": "GB/s",
         "cores": o.num_threads(),
         "kind": "oracle",
@@ -734,38 +856,15 @@ def main():
     cache_gbps = cache_copy_peak(torch)
     head = results[modes[0]]
     roof = None
-    if "kernels" in head and head["kernels"]:
-        dom_name, dom = max(head["kernels"].items(), key=lambda kv: kv[1]["total_ms"])
-        tb = (measured_traffic(f"{dom_name}:{head['mode']}", dom["unknowns_per_launch"])
-              if not head.get("overlap") else None)
-        roof = {"bound": "hbm", "kernel": f"k_{dom_name} ({head['mode']})",
-                "achieved": dom["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(dom["GBps"] / HBM_PEAK_GBPS, 4),
-                "traffic": None if tb is None else round(tb / (dom["avg_us"] * 1e-6) / 1e9, 1),
-                "algorithmic_bytes_per_launch": dom["bytes_per_launch"],
-                "traffic_bytes_per_launch": None if tb is None else int(tb),
-                "unknowns_per_launch": dom["unknowns_per_launch"],
-                "served_from": ("the inner-iteration kernels (stencil, update) re-read their "
-                                "launch group's vectors, sized to fit the 256 MB on-package "
-                                "cache, so part of their traffic is served by that cache, not "
-                                "HBM; traffic counts L2 misses (cache hits included); DRAM-side "
-                                "bytes are not measured"),
-                "ceilings": {"hbm_copy_GBps": copy_gbps, "cache_resident_copy_GBps": cache_gbps},
-                "frac_of_cache_resident_copy": round(dom["GBps"] / cache_gbps, 4),
-                "frac_of_hbm_copy": round(dom["GBps"] / copy_gbps, 4)}
-        # the kernels that stream from HBM: outer residual, final update, global CG
-        streaming = {}
-        for mo, res in results.items():
-            for kname in ("resid", "final") if mo == head["mode"] else ():
-                k = res.get("kernels", {}).get(kname)
-                if k:
-                    streaming[f"k_{kname} ({mo})"] = k["GBps"]
-            if mo.startswith("cg-"):
-                for kname, k in res.get("kernels", {}).items():
-                    streaming[f"k_gcg_{kname} ({mo})"] = k["GBps"]
-        roof["hbm_streaming"] = {k: {"achieved": v, "frac_of_hbm_copy": round(v / copy_gbps, 4),
-                                     "frac": round(v / HBM_PEAK_GBPS, 4)}
-                                 for k, v in streaming.items()}
+    ceilings = {"hbm_copy_GBps": copy_gbps, "cache_resident_copy_GBps": cache_gbps}
+    hk = head.get("kernels") or {}
+    if "team" in hk:
+        roof = team_roofline(head, ceilings)
+        ph = results.get("phase-" + head["mode"].split("-")[1])
+        if ph and ph.get("kernels"):
+            roof["streaming_engine"] = phase_roofline(ph, results, ceilings)
+    elif hk:
+        roof = phase_roofline(head, results, ceilings)
     cpu = None if args.no_cpu else cpu_baseline(w, args.m, args.cpu_sweeps, to_tol, finals,
                                                  args.tol_overlap, args.tol_m, args.cpu_ovl_sweeps)
     finals.clear()
@@ -775,7 +874,7 @@ def main():
     shape = w["shape"]
     line = {
         "metric": METRIC,
-        "value": head["GBps"],
+        "value": head.get("model_GBps", head["GBps"]),
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -796,6 +895,11 @@ def main():
                          f"{[len(c) - 1 for c in w['cuts']]}, {prec}"),
             "step": "one outer sweep",
             "unknowns": shape[0] * shape[1] * shape[2],
+            "engine": head.get("engine"),
+            "value": ("the method's bytes per unknown per sweep (10 words per unknown per inner "
+                      "CG iteration plus the outer residual and update: "
+                      f"{model_sweep_bytes(args.m, prec == 'mixed')} B at m={args.m}) times the "
+                      "unknowns, over the measured sweep time"),
         },
         "roofline": roof,
         "cpu_baseline": cpu,

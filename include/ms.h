@@ -193,6 +193,8 @@ typedef struct {
                                   to each block, in block order (sync: all
                                   equal to sweeps) */
     int32_t block_sweeps_cap;
+    int32_t engine_used;       /* MS_ENGINE_PHASE or MS_ENGINE_TEAM: the engine
+                                  that ran the solve (0 before one ran)     */
 } ms_stats;
 
 typedef struct ms_handle ms_handle;

@@ -1004,9 +1004,14 @@ ms_status solve_sync(ms_handle *h, const double *b, double *x, int nrhs, double 
     if (nrhs > h->rhs_cap) return fail(h, MS_ERR_ARG, "more right-hand sides than reserved");
     {
         const TeamPlan P = team_for_solve(h, (int)sizeof(T), o, nrhs);
-        if (P.ok) return solve_sync_team<T>(h, P, b, x, tol, m, o, stats, st);
+        if (P.ok) {
+            if (stats) stats->engine_used = MS_ENGINE_TEAM;
+            return solve_sync_team<T>(h, P, b, x, tol, m, o, stats, st);
+        }
         if (o.engine == MS_ENGINE_TEAM)
             return fail(h, MS_ERR_UNSUPPORTED, "team engine unavailable: " + P.why);
+        if (stats)
+            for (int k = 0; k < nrhs; k++) stats[k].engine_used = MS_ENGINE_PHASE;
     }
     const bool gmres = o.inner_solver == MS_INNER_GMRES;
     if (gmres && (m > h->kry_M || nrhs > h->kry_rhs || h->inner_n > h->kry_inner ||
@@ -1295,6 +1300,7 @@ ms_status solve_async(ms_handle *h, const double *b, double *x, double tol, int 
     const TeamPlan TP = team_for_solve(h, (int)sizeof(T), o, 1);
     if (!TP.ok && o.engine == MS_ENGINE_TEAM)
         return fail(h, MS_ERR_UNSUPPORTED, "team engine unavailable: " + TP.why);
+    if (stats) stats->engine_used = TP.ok ? MS_ENGINE_TEAM : MS_ENGINE_PHASE;
     int per_cu = 0;
     if (gmres)
         HIPCHK(h, ms::async_gmres_occupancy<T>(vz, h->overlap > 0 ? 1 : 0, &per_cu));

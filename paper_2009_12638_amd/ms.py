@@ -64,7 +64,8 @@ class ms_stats(C.Structure):
                 ("history_len", C.c_int32), ("history", C.POINTER(C.c_double)),
                 ("history_cap", C.c_int32), ("kernel_ms", C.c_double * 8),
                 ("kernel_launches", C.c_int64 * 8), ("trace_len", C.c_int32),
-                ("block_sweeps", C.POINTER(C.c_int32)), ("block_sweeps_cap", C.c_int32)]
+                ("block_sweeps", C.POINTER(C.c_int32)), ("block_sweeps_cap", C.c_int32),
+                ("engine_used", C.c_int32)]
 
 
 _L = None
@@ -268,6 +269,7 @@ class Stats:
     kernel_launches: dict = field(default_factory=dict)
     trace_len: int = 0
     block_sweeps: list = field(default_factory=list)
+    engine: str = ""
 
 
 def _opts(precision="fp64", max_sweeps=100000, inner_tol=0.0, staleness=2, stream=None,
@@ -309,7 +311,8 @@ def _stats_of(st: int, s: ms_stats, hist, bsw=None) -> Stats:
                  kernel_ms={KERNEL_CLASSES[i]: s.kernel_ms[i] for i in range(8)},
                  kernel_launches={KERNEL_CLASSES[i]: s.kernel_launches[i] for i in range(8)},
                  trace_len=s.trace_len,
-                 block_sweeps=list(bsw) if bsw is not None else [])
+                 block_sweeps=list(bsw) if bsw is not None else [],
+                 engine={1: "phase", 2: "team"}.get(s.engine_used, ""))
 
 
 def _nblocks(h) -> int:

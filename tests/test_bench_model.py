@@ -61,3 +61,51 @@ def test_region_cells(bench):
     x = [4 + 2, 4 + 2 + 2, 4 + 2]
     z = [2 + 2, 3 + 2]
     assert bench.region_cells(shape, cuts, 2) == sum(x) * 4 * sum(z)
+
+
+def test_team_byte_counts(bench):
+    """Resident-team sweeps: x and b read, x written through HBM; per inner
+    iteration two stencil applies from LDS (5 z vectors and 2 single cells
+    per vector of 4 FP32 or 2 FP64 cells) and one read and write of p."""
+    assert bench.TEAM_HBM_BYTES == 24
+    assert bench.team_lds_bytes(4) == 2 * (5 * 4 + 2) * 4 / 4 + 8 == 52
+    assert bench.team_lds_bytes(8) == 2 * (5 * 2 + 2) * 8 / 2 + 16 == 112
+    assert abs(bench.LDS_PEAK_GBPS - 78643.2) < 1e-6
+
+
+def test_counter_summary(tmp_path):
+    """The rocprofv3 counter summary: kernel classes from demangled names,
+    calibration on the 1 GiB copies, bytes per launch with the launch sizes
+    from the bench line."""
+    import json
+    from paper_2009_12638_amd import pmc
+    assert pmc.kernel_class("ms::k_update<float, 4, 1, true, false>") == ("final", "mixed")
+    assert pmc.kernel_class("ms::k_update<double, 2, 1, false, false>") == ("update", "fp64")
+    assert pmc.kernel_class("ms::k_resid<float, 4, 1, false, false>") is None
+    assert pmc.kernel_class("ms::k_team<double, 2, 8, false, false>") == ("team", "fp64")
+    assert pmc.short_name("void ms::k_stencil<float, 4, 1>(ms::Geom, int)") == \
+        "ms::k_stencil<float, 4, 1>"
+    hdr = "Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n"
+    for counter, copy_kib, team_kib in (("FETCH_SIZE", 524288.0, 1000.0),
+                                        ("WRITE_SIZE", 1048576.0, 3000.0)):
+        d = tmp_path / counter
+        d.mkdir()
+        rows = [f"1,void __amd_rocclr_copyBuffer(),{counter},{copy_kib}",
+                f"2,void __amd_rocclr_copyBuffer(),{counter},{copy_kib / 64}",
+                f"3,\"void ms::k_team<float, 4, 8, false, false>(ms::Geom, int)\",{counter},"
+                f"{team_kib}"]
+        (d / "run_counter_collection.csv").write_text(hdr + "\n".join(rows) + "\n")
+    line = {"config": {"workload": "w"},
+            "modes": {"sync-mixed": {"kernels": {"team": {"unknowns_per_launch": 1024}}}}}
+    bj = tmp_path / "bench.json"
+    bj.write_text("[bench] log\n" + json.dumps(line) + "\n")
+    out = tmp_path / "t.json"
+    pmc.traffic(str(tmp_path / "FETCH_SIZE"), str(tmp_path / "WRITE_SIZE"), str(bj), str(out),
+                str(tmp_path / "t.md"), "cmd")
+    data = json.loads(out.read_text())
+    assert abs(data["fetch_scale"] - 2.0) < 1e-12 and data["write_scale"] == 1.0
+    k = data["kernels"]["team:mixed"]
+    assert k["fetch_bytes_per_launch"] == 2 * 1000.0 * 1024
+    assert k["write_bytes_per_launch"] == 3000.0 * 1024
+    assert k["unknowns_per_launch"] == 1024
+    assert data["kernel_source_sha1"] == pmc.source_sha1()

@@ -43,7 +43,7 @@ def test_team_matched_sweeps_fp64(orc, case):
     x = torch.zeros(shape, dtype=torch.float64, device="cuda")
     say("team matched sweeps", shape, "overlap", ov)
     st = ms.ms_solve(h, dev(b), x, 0.0, m, "sync", max_sweeps=K, engine="team", history=K + 1)
-    assert st.status == 0 and st.sweeps == K
+    assert st.status == 0 and st.sweeps == K and st.engine == "team"
     beff = orc.lift_bc(b, faces)
     _, xo, sw, _, hist = orc.multisplit(beff, np.zeros(shape), cuts, tol=0.0, m=m, overlap=ov,
                                         max_sweeps=K)
@@ -52,7 +52,8 @@ def test_team_matched_sweeps_fp64(orc, case):
     np.testing.assert_allclose(st.history, hist, rtol=0, atol=1e-12)
     # the phase engine gives the same iterate to rounding
     xp = torch.zeros_like(x)
-    ms.ms_solve(h, dev(b), xp, 0.0, m, "sync", max_sweeps=K, engine="phase")
+    sp = ms.ms_solve(h, dev(b), xp, 0.0, m, "sync", max_sweeps=K, engine="phase")
+    assert sp.engine == "phase"
     assert rel(host(x), host(xp)) <= 1e-12
     print(f"team {shape} overlap {ov}: {e:.2e} to the oracle")
 
@@ -110,7 +111,7 @@ def test_team_async_trace_and_bound(orc):
     say("team async with trace")
     st = ms.ms_solve(h, dev(b), x, 1e-8, 10, "async", staleness=2, engine="team", trace=trace,
                      slow_block=21, slow_sleep=20)
-    assert st.status == 0
+    assert st.status == 0 and st.engine == "team"
     rec = trace[: st.trace_len].cpu().numpy().astype(np.int64)
     bs = np.asarray(st.block_sweeps)
     assert bs.sum() == st.trace_len
@@ -139,7 +140,7 @@ def test_team_refusals():
     assert e.value.status == ms.MS_ERR_UNSUPPORTED
     # auto falls back to the phase engine
     st = ms.ms_solve(h, b, x, 0.0, 5, "sync", max_sweeps=2)
-    assert st.status == 0
+    assert st.status == 0 and st.engine == "phase"
     with pytest.raises(ms.MsError) as e:
         ms.ms_solve(h, b, x, 1e-6, 5, "sync", engine=7)
     assert e.value.status == ms.MS_ERR_ARG
