@@ -831,9 +831,14 @@ ms_status team_alloc(ms_handle *h) {
 
 // ctr: [0] next block, [1] error code (kept), [2..9] workgroups per XCD,
 // [10] workgroups arrived
-__global__ void k_team_reset(char *mem, long long team_bytes, int nteams, int *ctr) {
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nteams; t += gridDim.x * blockDim.x)
-        *(int *)(mem + (long long)t * team_bytes) = 0;   // barrier counter
+// Every team's header (barrier counter, work ring, partial-sum slots: the
+// first clear_ints ints of its memory) to zero.
+__global__ void k_team_reset(char *mem, long long team_bytes, int nteams, int clear_ints,
+                             int *ctr) {
+    const long long n = (long long)nteams * clear_ints;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        ((int *)(mem + (i / clear_ints) * team_bytes))[i % clear_ints] = 0;
     if (blockIdx.x == 0 && threadIdx.x < 11 && threadIdx.x != 1) ctr[threadIdx.x] = 0;
 }
 
@@ -861,8 +866,10 @@ ms_status enqueue_team(ms_handle *h, const TeamPlan &P, const double *b, const d
                        double *xb, int m, double inner_tol, bool async, AsyncState as, int S,
                        int limit, double tol2, hipStream_t st) {
     const int nteams = 8 * P.per_xcd / P.T;
-    hipLaunchKernelGGL(k_team_reset, dim3((nteams + 63) / 64), dim3(64), 0, st, h->team_mem,
-                       (long long)P.team_bytes, nteams, h->team_ctr);
+    const int clear_ints = ms::team_face_offset() / (int)sizeof(int);
+    const int rgrid = (int)std::min<long long>(256, ((long long)nteams * clear_ints + 255) / 256);
+    hipLaunchKernelGGL(k_team_reset, dim3(rgrid), dim3(256), 0, st, h->team_mem,
+                       (long long)P.team_bytes, nteams, clear_ints, h->team_ctr);
     HIPCHK(h, hipGetLastError());
     ms::TeamArgs a;
     a.T = P.T;

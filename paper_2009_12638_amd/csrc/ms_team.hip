@@ -474,6 +474,11 @@ __global__ __launch_bounds__(kTeamThreads) void k_team(Geom g, TeamArgs a, Async
             }
         };
         bool ok = true;
+        // A p of the sigma pass, kept in registers for the update pass on the
+        // first QK slots (32 registers, 16 when there are more than 8 slots);
+        // later slots apply the stencil again
+        constexpr int QK = Q * VZ * (int)sizeof(T) <= 128 ? Q : 64 / (VZ * (int)sizeof(T));
+        T qr[QK][VZ];
         // the iterations, with the slot loops free of per-slot branches when
         // every slot of every thread holds a vector (FULL)
         auto cg_loop = [&](auto fullc) {
@@ -489,7 +494,10 @@ __global__ __launch_bounds__(kTeamThreads) void k_team(Geom g, TeamArgs a, Async
                         T pc[VZ], qv[VZ];
                         apply(s, E(s), pc, qv);
 #pragma unroll
-                        for (int v = 0; v < VZ; v++) sig += pc[v] * qv[v];
+                        for (int v = 0; v < VZ; v++) {
+                            sig += pc[v] * qv[v];
+                            if (s < QK) qr[s < QK ? s : 0][v] = qv[v];
+                        }
                         // slots go in pairs: the loads of two slots in flight
                         // together, without holding all slots' in registers
                         if (s % kSlotGroup == kSlotGroup - 1) __builtin_amdgcn_sched_barrier(0);
@@ -507,7 +515,13 @@ __global__ __launch_bounds__(kTeamThreads) void k_team(Geom g, TeamArgs a, Async
                         const int es = E(s);
                         if (!FULL && es >= nE) continue;
                         T pc[VZ], qv[VZ], dd[VZ];
-                        apply(s, E(s), pc, qv);
+                        if (s < QK) {
+                            vload<T, VZ>(lp + es, pc);
+#pragma unroll
+                            for (int v = 0; v < VZ; v++) qv[v] = qr[s < QK ? s : 0][v];
+                        } else {
+                            apply(s, es, pc, qv);
+                        }
                         if (DREG) {
 #pragma unroll
                             for (int v = 0; v < VZ; v++) dd[v] = dr[DREG ? s : 0][v];
@@ -653,10 +667,16 @@ hipError_t launch_team(const Geom &g, int vz, int q, const TeamArgs &a, bool asy
     } else {                                                                                 \
         if (async) { MS_TEAM_Q(T, VZ_, false, true) } else { MS_TEAM_Q(T, VZ_, false, false) } \
     }
+    // FP64 runs on vectors of at most 2 cells (4 would not leave registers
+    // for the slots)
     switch (vz) {
         case 1: MS_TEAM_VZ(1)
         case 2: MS_TEAM_VZ(2)
-        case 4: MS_TEAM_VZ(4)
+        case 4:
+            if constexpr (sizeof(T) == 4) {
+                MS_TEAM_VZ(4)
+            }
+            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 #undef MS_TEAM_VZ

@@ -110,7 +110,7 @@ def test_team_async_trace_and_bound(orc):
     trace = torch.full((cap, 8), -7, dtype=torch.int32, device="cuda")
     say("team async with trace")
     st = ms.ms_solve(h, dev(b), x, 1e-8, 10, "async", staleness=2, engine="team", trace=trace,
-                     slow_block=21, slow_sleep=20)
+                     slow_block=21, slow_sleep=200)
     assert st.status == 0 and st.engine == "team"
     rec = trace[: st.trace_len].cpu().numpy().astype(np.int64)
     bs = np.asarray(st.block_sweeps)
