@@ -274,7 +274,16 @@ def run_mode(args, torch, ms, w, mode: str):
                            for r in table]}
         log(f"{mode}: tuned overlap {ov}, m {m} in {tuned['tune_seconds']} s")
     NR = region_cells(shape, cuts, ov)   # cells the residual and inner kernels touch
-    if kind in ("ovl", "batch") and args.autotune:
+    team_ok = False
+    if kind == "ovl" and args.autotune:
+        # the tile search concerns the phase engine (setting a tile option
+        # selects it); skip it when the tuned pair runs on the team engine
+        team_ok = ms.ms_solve(h, b, x, 0.0, m, "sync", max_sweeps=1,
+                              precision=precision).engine == "team"
+        x.zero_()
+        if team_ok:
+            log(f"{mode}: overlap {ov}, m {m} runs on the team engine: no tile search")
+    if kind in ("ovl", "batch") and args.autotune and not team_ok:
         # tile shape with blocks per launch, on the real problem with the tuned m
         lay, lays = tune.tune_layout(
             h, b, x, precision, m=m, sweeps=2,
