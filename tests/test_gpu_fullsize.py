@@ -175,12 +175,15 @@ def test_uneven384_batch_sampled_blocks(orc):
     print(f"uneven384 batch: worst block correction error {worst:.2e}")
 
 
-@pytest.mark.parametrize("name,precision,K", [("poisson256", "fp64", 50), ("bumps512", "fp64", 8),
-                                              ("bumps512", "mixed", 8)])
-def test_wholegrid_matched_sweeps(orc, name, precision, K):
+@pytest.mark.parametrize("name,precision,K,engine",
+                         [("poisson256", "fp64", 50, "auto"), ("bumps512", "fp64", 8, "auto"),
+                          ("bumps512", "mixed", 8, "auto"), ("bumps512", "fp64", 4, "phase"),
+                          ("bumps512", "mixed", 4, "phase")])
+def test_wholegrid_matched_sweeps(orc, name, precision, K, engine):
     """K synchronous sweeps from x = 0 in the benchmark's launch
     configuration against the oracle's K FP64 sweeps, on every cell, with
-    the residual histories.  Mixed precision is held to the correction bar
+    the residual histories, on the default engine (the team engine here)
+    and on the phase engine.  Mixed precision is held to the correction bar
     (the iterate is a sum of corrections, each refined by the next FP64
     residual)."""
     torch = torch_cuda()
@@ -189,9 +192,10 @@ def test_wholegrid_matched_sweeps(orc, name, precision, K):
     h = ms.ms_create(shape, cuts=[list(map(int, c)) for c in cuts], faces=None)
     b = dev(w["b"])
     x = torch.zeros(shape, dtype=torch.float64, device="cuda")
-    say("wholegrid", name, precision, "K", K)
+    say("wholegrid", name, precision, "K", K, engine)
     st = ms.ms_solve(h, b, x, 0.0, w["m"], "sync", max_sweeps=K, precision=precision,
-                     history=K + 1)
+                     history=K + 1, engine=engine)
+    assert st.engine == ("team" if engine == "auto" else engine)
     xg = host(x)
     del x, b
     ms.ms_destroy(h)
@@ -208,7 +212,7 @@ def test_wholegrid_matched_sweeps(orc, name, precision, K):
     # at most ||A|| ||delta x|| / ||b_eff|| (||A|| <= 12)
     atol = 12 * max(e, 1e-13) * np.linalg.norm(xo) / np.linalg.norm(beff) + 1e-14
     np.testing.assert_allclose(st.history, hist, rtol=0, atol=atol)
-    print(f"{name} {precision} K={K}: whole grid relative L2 {e:.2e}, final residual "
+    print(f"{name} {precision} K={K} {st.engine}: whole grid relative L2 {e:.2e}, final residual "
           f"{hist[-1]:.3e}")
 
 
