@@ -24,10 +24,12 @@ ceilings (a device copy through HBM, and a copy of buffers that stay in the
 256 MB on-package cache) with the HBM-streaming kernels listed apart, and
 the CPU oracle timed on this host over a bounded sample of the same
 workload (the only use of the oracle here).  After the timed region one
-configuration (overlap 6, m = 30) is solved to the 1e-8 relative residual in
-mixed precision and in plain FP64 and timed (time_to_tol; --no-tol-solve
-skips it); the oracle then evaluates the FP64 residual of both final
-iterates on the host, as part of the CPU-baseline leg.  With
+configuration (overlap 6, m = 30) is solved to the 1e-8 relative residual
+with synchronous sweeps in mixed precision and in plain FP64, and with
+asynchronous sweeps in mixed precision, and timed (time_to_tol; --tol-modes
+picks them, --no-tol-solve skips them); the oracle then evaluates the FP64
+residual of every final iterate on the host, as part of the CPU-baseline
+leg.  With
 --full-solve every mode is also run to 1e-8 and timed; the final residuals are
 the library's own FP64 evaluation.
 
@@ -489,10 +491,11 @@ def overlap_study(args, torch, ms, inputs):
     return out
 
 
-def tol_solve(args, torch, ms, w, precision: str):
-    """Time to the workload's tolerance for one configuration (synchronous,
-    overlap --tol-overlap, m = --tol-m, given precision), from x = 0.
-    Returns (record, final iterate on the host or None)."""
+def tol_solve(args, torch, ms, w, precision: str, mode: str = "sync"):
+    """Time to the workload's tolerance for one configuration (overlap
+    --tol-overlap, m = --tol-m, given precision and sweep mode; async with
+    staleness 2), from x = 0.  Returns (record, final iterate on the host or
+    None)."""
     shape, cuts = w["shape"], w["cuts"]
     b = torch.from_numpy(w["b"]).to("cuda")
     h = ms.ms_create(shape, cuts=[list(map(int, c)) for c in cuts], faces=None)
@@ -501,12 +504,12 @@ def tol_solve(args, torch, ms, w, precision: str):
     x = torch.zeros_like(b)
     ms.ms_solve(h, b, x, 0.0, args.tol_m, "sync", max_sweeps=2, precision=precision)
     x.zero_()
-    log(f"time to {w['tol']}: overlap {args.tol_overlap}, m {args.tol_m}, {precision}")
+    log(f"time to {w['tol']}: overlap {args.tol_overlap}, m {args.tol_m}, {mode} {precision}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     total = 0
     while True:
-        fs = ms.ms_solve(h, b, x, w["tol"], args.tol_m, "sync", precision=precision,
+        fs = ms.ms_solve(h, b, x, w["tol"], args.tol_m, mode, precision=precision,
                          max_sweeps=200, raise_on_error=False)
         total += fs.sweeps
         if fs.status == ms.MS_OK:
@@ -517,12 +520,14 @@ def tol_solve(args, torch, ms, w, precision: str):
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     rel, _ = ms.ms_residual(h, b, x)
-    out = {"mode": f"sync-{precision}", "engine": fs.engine or "phase",
+    out = {"mode": f"{mode}-{precision}", "engine": fs.engine or "phase",
            "overlap": args.tol_overlap,
            "inner_iters": args.tol_m, "tol": w["tol"], "sweeps": total,
            "seconds": round(sec, 3), "ms_per_sweep": round(1e3 * sec / max(total, 1), 3),
            "final_rel_residual_gpu": rel}
-    log(f"time to tol ({precision}): {total} sweeps, {sec:.2f} s, residual {rel:.3e}")
+    if mode == "async":
+        out["sweeps_note"] = "async: sweeps of the block that did most, summed over the calls"
+    log(f"time to tol ({mode} {precision}): {total} sweeps, {sec:.2f} s, residual {rel:.3e}")
     xh = None if args.no_cpu else x.cpu().numpy()
     ms.ms_destroy(h)
     del x, b
@@ -805,8 +810,9 @@ def main():
                     help="skip the time-to-tolerance solve of the default line")
     ap.add_argument("--tol-overlap", type=int, default=6)
     ap.add_argument("--tol-m", type=int, default=30)
-    ap.add_argument("--tol-precision", default="mixed,fp64",
-                    help="comma list of precisions solved to tolerance (mixed, fp64)")
+    ap.add_argument("--tol-modes", default="sync-mixed,sync-fp64,async-mixed",
+                    help="comma list of sweep mode and precision pairs solved to tolerance "
+                         "(sync-mixed, sync-fp64, async-mixed, async-fp64)")
     ap.add_argument("--cpu-ovl-sweeps", type=int, default=2,
                     help="oracle sweeps of the time-to-tolerance configuration timed for its "
                          "extrapolated time to tolerance (0: skip)")
@@ -853,8 +859,10 @@ def main():
             results[mo] = run_mode(args, torch, ms, w, mo)
     to_tol, finals = {}, {}
     if not args.no_tol_solve:
-        for prec in [p for p in args.tol_precision.split(",") if p]:
-            to_tol[prec], finals[prec] = tol_solve(args, torch, ms, w, prec)
+        for tm in [p for p in args.tol_modes.split(",") if p]:
+            mode, prec = tm.split("-")
+            key = prec if mode == "sync" else tm
+            to_tol[key], finals[key] = tol_solve(args, torch, ms, w, prec, mode)
         if "mixed" in to_tol and "fp64" in to_tol:
             to_tol["fp64_over_mixed_time"] = round(to_tol["fp64"]["seconds"] /
                                                    to_tol["mixed"]["seconds"], 3)
