@@ -95,9 +95,11 @@ __device__ __forceinline__ bool team_sync(TeamCtx &c) {
 
 // Sum over the team, in member order, of two values summed over the
 // workgroup (wave sums, then the waves in order); every thread gets the
-// results.  One team barrier; the partial slots alternate with the
-// barrier count, so a member writes a slot only after every member has read
-// it two barriers earlier.
+// results.  One team barrier: the first wavefront stores the workgroup's
+// partials, arrives on the counter, polls it, and then loads every member's
+// partials (one per lane) and adds them in member order.  The partial slots
+// alternate with the barrier count, so a member writes a slot only after
+// every member has read it two barriers earlier.
 template <typename A, typename B>
 __device__ __forceinline__ bool team_reduce2(TeamCtx &c, A &a, B &b) {
     constexpr int NW = kTeamThreads / 64;
@@ -113,34 +115,30 @@ __device__ __forceinline__ bool team_reduce2(TeamCtx &c, A &a, B &b) {
     __syncthreads();   // also completes the workgroup's global stores
     c.bars++;
     const int slot = c.bars & 1;
-    if (threadIdx.x == 0) {
-        A ma = A(0);
-        B mb = B(0);
-        for (int w = 0; w < NW; w++) {
-            ma += (A)wsum[0][w];
-            mb += (B)wsum[1][w];
-        }
-        double *part = (double *)(c.mem + kPartOff) + (size_t)slot * 64;
-        part[c.member] = (double)ma;
-        part[32 + c.member] = (double)mb;
-        __builtin_amdgcn_s_waitcnt(0);   // the partials are in L2 before arriving
-        int *cnt = (int *)(c.mem + kBarOff);
-        __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int target = c.bars * c.T;
-        int spins = 0;
-        while (ld_acq(cnt) < target && spins < c.max_spin) {
-            __builtin_amdgcn_s_sleep(1);
-            spins++;
-        }
-        ok = spins < c.max_spin;
-        if (!ok) atomicCAS(c.err, 0, 2);
-    }
-    __syncthreads();
     if (threadIdx.x < 64) {
-        // the first wavefront loads the partials in parallel, one per lane,
-        // and every lane adds them in member order
         const int lane = threadIdx.x;
-        const double *part = (const double *)(c.mem + kPartOff) + (size_t)slot * 64;
+        double *part = (double *)(c.mem + kPartOff) + (size_t)slot * 64;
+        if (lane == 0) {
+            A ma = A(0);
+            B mb = B(0);
+            for (int w = 0; w < NW; w++) {
+                ma += (A)wsum[0][w];
+                mb += (B)wsum[1][w];
+            }
+            part[c.member] = (double)ma;
+            part[32 + c.member] = (double)mb;
+            __builtin_amdgcn_s_waitcnt(0);   // the partials are in L2 before arriving
+            int *cnt = (int *)(c.mem + kBarOff);
+            __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int target = c.bars * c.T;
+            int spins = 0;
+            while (ld_acq(cnt) < target && spins < c.max_spin) spins++;
+            ok = spins < c.max_spin;
+            if (!ok) atomicCAS(c.err, 0, 2);
+        }
+        // the lanes load the partials once lane 0 has seen every member arrive
+        // (the compiler keeps the loads after the poll)
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
         const double va = lane < c.T ? ld_sh(part + lane) : 0.0;
         const double vb = lane < c.T ? ld_sh(part + 32 + lane) : 0.0;
         A sa = A(0);
