@@ -820,7 +820,7 @@ def main():
                     help="also run a plain 1 GiB device copy (reference for hardware counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               f"(asked for --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
     modes = [m for m in args.modes.split(",") if m]

@@ -51,7 +51,7 @@ typedef enum {
     MS_ERR_NOT_CONVERGED = 4, /* max_sweeps reached above tol; x = last iterate */
     MS_ERR_NONFINITE = 5,     /* residual became NaN/Inf; x unspecified     */
     MS_ERR_DIVERGED = 6,      /* residual grew 1e6x over its start; x unspecified */
-    MS_ERR_UNSUPPORTED = 7    /* valid but not supported by this build      */
+    MS_ERR_UNSUPPORTED = 7    /* valid but not supported by the library     */
 } ms_status;
 
 typedef enum { MS_SYNC = 0, MS_ASYNC = 1 } ms_mode;
