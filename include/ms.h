@@ -149,7 +149,13 @@ typedef struct {
  *     inner iterations (synchronous and asynchronous mode, single
  *     right-hand side).  Needs every block's box to fit: with 512-thread
  *     workgroups of 160 KB LDS, about 20K cells per workgroup (FP32 inner)
- *     or 10K (FP64), a team being at most 32 workgroups.
+ *     or 10K (FP64), a team being at most 32 workgroups.  Each sweep is one
+ *     cooperative launch that occupies every compute unit: work on other
+ *     streams of the device delays it, and if its workgroups do not all
+ *     start within the wait bound, or a team barrier does not complete, the
+ *     solve returns MS_ERR_HIP (x unspecified).  Team sums add per-member
+ *     partials in member order, so results are deterministic; they differ
+ *     from the phase engine's in rounding only.
  *   MS_ENGINE_AUTO: TEAM when it fits, else PHASE; setting any tiling
  *     option of the phase engine (group_blocks, x_chunk, rows, z_vector,
  *     workers) selects PHASE.
