@@ -357,6 +357,11 @@ def run_mode(args, torch, ms, w, mode: str):
         res["unknown_iters_per_s"] = N * nrhs * m * args.steps / sec
     if kind == "async":
         res["max_staleness_seen"] = st.max_staleness_seen
+        if st.block_sweeps:
+            # sweeps each block did in the timed call (asynchronous blocks
+            # need not end level)
+            res["block_sweeps_min"] = int(min(st.block_sweeps))
+            res["block_sweeps_max"] = int(max(st.block_sweeps))
     if team and kind in ("sync", "ovl"):
         # one cooperative launch per sweep: the method's bytes per unknown
         # per sweep, and the LDS bytes of the inner iterations
@@ -527,6 +532,7 @@ def tol_solve(args, torch, ms, w, precision: str, mode: str = "sync"):
            "final_rel_residual_gpu": rel}
     if mode == "async":
         out["sweeps_note"] = "async: sweeps of the block that did most, summed over the calls"
+        out["max_staleness_seen_last_call"] = fs.max_staleness_seen
     log(f"time to tol ({mode} {precision}): {total} sweeps, {sec:.2f} s, residual {rel:.3e}")
     xh = None if args.no_cpu else x.cpu().numpy()
     ms.ms_destroy(h)

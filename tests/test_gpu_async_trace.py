@@ -160,24 +160,24 @@ def test_trace_without_slow_block_and_sync_block_counts():
         assert e.value.status == ms.MS_ERR_ARG
 
 
-def test_async_fullsize_launch_shape(orc):
-    """The asynchronous workers in their full-size launch shape: 256^3,
-    4x4x4 blocks of 64^3 (the one-GPU share of the 512^3 problem), mixed
-    precision, a fixed number of sweeps.  Every block does exactly that many
-    sweeps, the trace satisfies the bound, and the oracle's residual of the
-    result is of the quality of the synchronous method after as many
-    sweeps (the oracle's)."""
+@pytest.mark.parametrize("name,K", [("poisson256", 40), ("bumps512", 6)])
+def test_async_fullsize_launch_shape(orc, name, K):
+    """The asynchronous sweeps in their full-size launch shapes: 256^3 with
+    4x4x4 blocks of 64^3 (the one-GPU share of the 512^3 problem) and the
+    512^3 problem itself with 8x8x8 blocks of 64^3, mixed precision, a fixed
+    number of sweeps.  Every block does exactly that many sweeps, the trace
+    satisfies the bound, and the oracle's residual of the result is of the
+    quality of the synchronous method after as many sweeps (the oracle's)."""
     torch = torch_cuda()
-    w = inputs.workload("poisson256")
+    w = inputs.workload(name)
     shape, cuts = w["shape"], w["cuts"]
     g = len(cuts[0]) - 1
     h = ms.ms_create(shape, cuts=[list(map(int, c)) for c in cuts], faces=None)
     b = dev(w["b"])
     x = torch.zeros(shape, dtype=torch.float64, device="cuda")
-    K = 40
     cap = K * g ** 3
     trace = torch.full((cap, 8), -7, dtype=torch.int32, device="cuda")
-    say("async 256^3 fixed sweeps, mixed")
+    say(f"async {name} {K} fixed sweeps, mixed")
     st = ms.ms_solve(h, b, x, 0.0, w["m"], "async", max_sweeps=K, staleness=2,
                      precision="mixed", trace=trace)
     assert st.status == 0 and st.sweeps == K and st.trace_len == cap
@@ -196,10 +196,14 @@ def test_async_fullsize_launch_shape(orc):
     _, _, _, _, hs = orc.block_jacobi(beff, np.zeros(shape), cuts, tol=0.0, m=w["m"],
                                       max_sweeps=K)
     assert np.isfinite(xa).all()
-    assert ra < 0.5 * hs[0]
-    assert ra <= 10.0 * hs[K], (ra, hs[K])
-    print(f"async 256^3 mixed, {K} sweeps: oracle residual {ra:.3e}, synchronous {hs[K]:.3e}, "
-          f"staleness {st.max_staleness_seen}")
+    if name == "poisson256":
+        # a rough source: the residual falls from the first sweeps on
+        assert ra < 0.5 * hs[0]
+    # (the smooth 512^3 source first raises the relative residual to about
+    # 4 and lowers it slowly: block-boundary jumps dominate it at first)
+    assert ra <= 2.0 * hs[K], (ra, hs[K])
+    print(f"async {name} mixed, {K} sweeps ({st.engine}): oracle residual {ra:.3e}, synchronous "
+          f"{hs[K]:.3e}, staleness {st.max_staleness_seen}")
 
 
 def test_async_c5_shape_to_tolerance(orc):
