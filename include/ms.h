@@ -138,6 +138,11 @@ typedef struct {
     int32_t trace_cap;
     int32_t engine;       /* how CG inner solves run (ms_engine, default
                              MS_ENGINE_AUTO) */
+    int32_t team_spin;    /* debugging: polls a team-engine wait (the launch's
+                             start, a team barrier) makes before it gives up
+                             and the solve fails with MS_ERR_HIP; 0 (default)
+                             = 2^24.  A tiny value forces that failure path;
+                             every kernel still exits.  >= 0 */
 } ms_opts;
 
 /* Kernels that carry out the CG inner solves.

@@ -864,7 +864,7 @@ TeamPlan team_for_solve(ms_handle *h, int tsize, const ms_opts &o, int nrhs) {
 template <typename T>
 ms_status enqueue_team(ms_handle *h, const TeamPlan &P, const double *b, const double *xa,
                        double *xb, int m, double inner_tol, bool async, AsyncState as, int S,
-                       int limit, double tol2, hipStream_t st) {
+                       int limit, double tol2, int spin, hipStream_t st) {
     const int nteams = 8 * P.per_xcd / P.T;
     const int clear_ints = ms::team_face_offset() / (int)sizeof(int);
     const int rgrid = (int)std::min<long long>(256, ((long long)nteams * clear_ints + 255) / 256);
@@ -889,7 +889,7 @@ ms_status enqueue_team(ms_handle *h, const TeamPlan &P, const double *b, const d
     a.xb = xb;
     a.F = faces(h);
     a.p64 = h->part64;
-    a.max_spin = kTeamMaxSpin;
+    a.max_spin = spin > 0 ? spin : kTeamMaxSpin;
     Prof p(h, st, MS_K_OTHER);
     HIPCHK(h, ms::launch_team<T>(geom(h), P.vz, P.q, a, async, as, S, limit, tol2, h->ctrl,
                                  8 * P.per_xcd, P.lds, st));
@@ -953,7 +953,7 @@ ms_status solve_sync_team(ms_handle *h, const TeamPlan &P, const double *b, doub
         const int nb = std::min(batch, o.max_sweeps - next);
         for (int q = 0; q < nb; q++, next++) {
             s = enqueue_team<T>(h, P, b, X[next % 2], X[(next + 1) % 2], m, o.inner_tol, false,
-                                none, 0, 0, 0.0, st);
+                                none, 0, 0, 0.0, o.team_spin, st);
             if (s != MS_OK) return s;
             Prof p(h, st, MS_K_CHECK);
             HIPCHK(h, ms::launch_check(h->part64, h->nblocks, tol, 0, h->history_d, kHistoryCap,
@@ -1374,7 +1374,7 @@ ms_status solve_async(ms_handle *h, const double *b, double *x, double tol, int 
         first = false;
         if (TP.ok) {
             s = enqueue_team<T>(h, TP, b, x, x, m, o.inner_tol, true, as, o.staleness, limit, tol2,
-                                st);
+                                o.team_spin, st);
             if (s != MS_OK) return s;
         } else {
             Prof p(h, st, MS_K_OTHER);
@@ -1770,6 +1770,7 @@ static ms_status check_solve(ms_handle *h, const double *b, double *x, long long
     if (o.inner_solver != MS_INNER_CG && o.inner_solver != MS_INNER_GMRES)
         return fail(h, MS_ERR_ARG, "unknown inner solver");
     if (o.z_vector < 0) return fail(h, MS_ERR_ARG, "z_vector must be >= 0");
+    if (o.team_spin < 0) return fail(h, MS_ERR_ARG, "team_spin must be >= 0");
     if (o.slow_sleep < 0 || o.slow_sleep > 100000)
         return fail(h, MS_ERR_ARG, "slow_sleep must be in [0, 100000]");
     if (o.slow_sleep > 0 && o.slow_block >= h->nblocks)

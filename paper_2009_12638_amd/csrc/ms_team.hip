@@ -70,7 +70,16 @@ struct TeamCtx {
     int bars;         // barriers this workgroup has passed
     int max_spin;
     int *err;
+    int *stop;        // async: set when a barrier fails, so other teams stop claiming
 };
+
+// A team barrier gave up: record the error; in async mode also stop every
+// team from claiming more blocks (a block this team holds would never be
+// published, and teams waiting for it would wait for ever).
+__device__ __forceinline__ void team_fail(TeamCtx &c) {
+    atomicCAS(c.err, 0, 2);   // 2: team barrier timed out
+    if (c.stop) __hip_atomic_store(c.stop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Team barrier: returns false (every thread) when it timed out.
 __device__ __forceinline__ bool team_sync(TeamCtx &c) {
@@ -87,7 +96,7 @@ __device__ __forceinline__ bool team_sync(TeamCtx &c) {
             spins++;
         }
         ok = spins < c.max_spin;
-        if (!ok) atomicCAS(c.err, 0, 2);   // 2: team barrier timed out
+        if (!ok) team_fail(c);
     }
     __syncthreads();
     return ok;
@@ -134,7 +143,7 @@ __device__ __forceinline__ bool team_reduce2(TeamCtx &c, A &a, B &b) {
             int spins = 0;
             while (ld_acq(cnt) < target && spins < c.max_spin) spins++;
             ok = spins < c.max_spin;
-            if (!ok) atomicCAS(c.err, 0, 2);
+            if (!ok) team_fail(c);
         }
         // the lanes load the partials once lane 0 has seen every member arrive
         // (the compiler keeps the loads after the poll)
@@ -226,6 +235,7 @@ __global__ __launch_bounds__(kTeamThreads) void k_team(Geom g, TeamArgs a, Async
     c.bars = 0;
     c.max_spin = a.max_spin;
     c.err = a.err;
+    c.stop = ASYNC ? &ctrl->stop : nullptr;
     const long long fs = a.face_stride;
     T *faces = reinterpret_cast<T *>(c.mem + kFaceOff);            // [T][2][fs], shared
     int *work = (int *)(c.mem + kWorkOff);

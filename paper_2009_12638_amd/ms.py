@@ -54,7 +54,8 @@ class ms_opts(C.Structure):
                 ("profile", C.c_int32), ("use_graph", C.c_int32), ("rows", C.c_int32),
                 ("workers", C.c_int32), ("inner_solver", C.c_int32), ("z_vector", C.c_int32),
                 ("slow_block", C.c_int32), ("slow_sleep", C.c_int32),
-                ("trace", C.c_void_p), ("trace_cap", C.c_int32), ("engine", C.c_int32)]
+                ("trace", C.c_void_p), ("trace_cap", C.c_int32), ("engine", C.c_int32),
+                ("team_spin", C.c_int32)]
 
 
 class ms_stats(C.Structure):
@@ -275,7 +276,7 @@ class Stats:
 def _opts(precision="fp64", max_sweeps=100000, inner_tol=0.0, staleness=2, stream=None,
           check_every=0, group_blocks=0, x_chunk=0, profile=False, use_graph=True,
           rows=0, workers=0, inner="cg", z_vector=0, slow_block=-1, slow_sleep=0,
-          trace=None, engine="auto") -> ms_opts:
+          trace=None, engine="auto", team_spin=0) -> ms_opts:
     o = ms_default_opts()
     o.max_sweeps = int(max_sweeps)
     o.inner_tol = float(inner_tol)
@@ -294,6 +295,7 @@ def _opts(precision="fp64", max_sweeps=100000, inner_tol=0.0, staleness=2, strea
         if isinstance(inner, str) else int(inner)
     o.z_vector = int(z_vector)
     o.engine = ENGINES[engine] if isinstance(engine, str) else int(engine)
+    o.team_spin = int(team_spin)
     o.slow_block = int(slow_block)
     o.slow_sleep = int(slow_sleep)
     if trace is not None:

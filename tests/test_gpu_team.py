@@ -144,3 +144,36 @@ def test_team_refusals():
     with pytest.raises(ms.MsError) as e:
         ms.ms_solve(h, b, x, 1e-6, 5, "sync", engine=7)
     assert e.value.status == ms.MS_ERR_ARG
+
+
+@pytest.mark.parametrize("mode", ["sync", "async"])
+def test_team_bounded_waits_fail_cleanly(orc, mode):
+    """A team-engine wait that gives up (forced from the host with a spin
+    limit of one poll: the launch's start or a team barrier cannot complete
+    in time) ends every workgroup, fails the solve with MS_ERR_HIP and leaves
+    the handle usable: the next solve on it matches the oracle."""
+    torch = torch_cuda()
+    n, g = 48, 3
+    shape = (n, n, n)
+    cuts = [inputs.uniform_cuts(n, g)] * 3
+    b = inputs.poisson_randn(shape, 540)
+    h, _ = make(ms, shape, cuts, [None] * 6)
+    x = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    say("team forced wait failure", mode)
+    with pytest.raises(ms.MsError) as e:
+        ms.ms_solve(h, dev(b), x, 1e-8, 10, mode, engine="team", team_spin=1, max_sweeps=50)
+    assert e.value.status == ms.MS_ERR_HIP
+    assert "team engine" in str(e.value)
+    with pytest.raises(ms.MsError) as e:
+        ms.ms_solve(h, dev(b), x, 1e-8, 10, mode, engine="team", team_spin=-1)
+    assert e.value.status == ms.MS_ERR_ARG
+    x.zero_()
+    st = ms.ms_solve(h, dev(b), x, 1e-8, 10, mode, engine="team")
+    assert st.status == 0 and st.engine == "team"
+    beff = orc.lift_bc(b, [None] * 6)
+    assert orc.residual(beff, host(x)) / np.linalg.norm(beff) <= 1e-8 * (1 + 1e-9)
+    if mode == "sync":
+        _, xo, sw, _, _ = orc.block_jacobi(beff, np.zeros(shape), cuts, tol=1e-8, m=10)
+        assert sw == st.sweeps
+        assert rel(host(x), xo) <= 1e-10
+    print(f"team {mode}: forced wait failure reported, next solve {st.sweeps} sweeps")
