@@ -1322,9 +1322,15 @@ ms_status solve_async(ms_handle *h, const double *b, double *x, double tol, int 
     HIPCHK(h, hipGetLastError());
     const double tol2 = tol > 0.0 ? (tol * nbeff) * (tol * nbeff) : 0.0;
     const long long per_sweep = std::max(1ll, h->N * (long long)m);
+    // sweeps per launch: about 2^33 cell-iterations for the phase engine's
+    // workers, 2^38 for teams (a team launch ends with its blocks at
+    // different sweep counts, and the teams idle through that tail, so it
+    // pays to relaunch rarely; the launch still ends as soon as the residual
+    // estimate is below tol)
+    const long long budget = TP.ok ? (256ll << 30) : (8ll << 30);
     const int chunk = o.check_every > 0
                           ? o.check_every
-                          : (int)std::max(8ll, std::min(1000ll, (8ll << 30) / per_sweep));
+                          : (int)std::max(8ll, std::min(1000ll, budget / per_sweep));
     AsyncState as;
     as.version = h->version_d;
     as.claim = h->claim_d;

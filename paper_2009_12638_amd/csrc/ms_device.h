@@ -281,14 +281,24 @@ __device__ __forceinline__ void async_publish(AsyncState as, int blk, int max_sw
         atomicAdd(&ctrl->inner_iters, (unsigned long long)iters);
         atomicAdd(&ctrl->work_items, 1ull);
         atomicMax(&ctrl->max_stale, sh.gap);
-        if (tol2 > 0.0) {
-            // residual estimate from the latest published block residuals
-            // (Section 3: an estimate that may be some sweeps old)
+    }
+    if (tol2 > 0.0) {
+        // residual estimate from the latest published block residuals
+        // (Section 3: an estimate that may be some sweeps old), summed by
+        // the whole workgroup: its threads load the board in parallel
+        __shared__ double est_w[kAsyncThreads / 64];
+        double e = 0.0;
+        for (int q = tid; q < nb; q += (int)blockDim.x)
+            e += __hip_atomic_load(&as.board[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        e = wave_sum(e);
+        if ((tid & 63) == 0) est_w[tid >> 6] = e;
+        __syncthreads();
+        if (tid == 0) {
             double est = 0.0;
-            for (int q = 0; q < nb; q++)
-                est += __hip_atomic_load(&as.board[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int w = 0; w < (int)blockDim.x / 64; w++) est += est_w[w];
             if (est <= tol2) __hip_atomic_store(&ctrl->stop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+        __syncthreads();   // est_w is free for the next call
     }
 }
 
