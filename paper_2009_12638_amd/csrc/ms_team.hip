@@ -39,6 +39,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 
 namespace ms {
 
@@ -272,10 +273,14 @@ __global__ __launch_bounds__(kTeamThreads) void k_team(Geom g, TeamArgs a, Async
         const int P = B.by * tpr;               // z vectors per plane
         const int V = np * P;                   // z vectors of this member
         const int PB = B.by * B.bz;             // cells per plane
+        // FP64: d in registers (LDS holds p only, so twice the cells fit);
+        // FP32: d after p in LDS
         // LDS: the lower halo plane (the previous member's last plane of p,
         // zero at the box's edge), the member's np planes of p, the upper
-        // halo plane; r and d stay in registers
+        // halo plane; d stays in registers with r
+        constexpr bool DREG = true;
         T *lp = lds + PB;                         // p of member-local element e at lp[e]
+        T *ldd = lp;                              // (d in LDS: unused)
         T *hlo = lds;                             // lower halo plane
         T *hhi = lds + (long long)(np + 1) * PB;  // upper halo plane
         // Vector slot s of this thread is vector tid + s * kTeamThreads of the
@@ -321,9 +326,9 @@ __global__ __launch_bounds__(kTeamThreads) void k_team(Geom g, TeamArgs a, Async
         }
         // ---- residual r = b_eff - A x on the member's cells (FP64); p = r in
         //      LDS, d = 0 ----
-        T r[Q][VZ], dr[Q][VZ];
+        T r[Q][VZ], dr[DREG ? Q : 1][VZ];
 #pragma unroll
-        for (int s = 0; s < Q; s++)
+        for (int s = 0; s < (DREG ? Q : 1); s++)
 #pragma unroll
             for (int v = 0; v < VZ; v++) dr[s][v] = T(0);
         double acc64 = 0.0;
@@ -379,6 +384,7 @@ __global__ __launch_bounds__(kTeamThreads) void k_team(Geom g, TeamArgs a, Async
                 }
                 if (K == 0 && a.F.f[4]) bb[0] += a.F.f[4][I * ny + J];
                 if (K + VZ == nz && a.F.f[5]) bb[VZ - 1] += a.F.f[5][I * ny + J];
+                T zero[VZ];
 #pragma unroll
                 for (int v = 0; v < VZ; v++) {
                     const double left = v == 0 ? zm : xc[v - 1];
@@ -394,8 +400,10 @@ __global__ __launch_bounds__(kTeamThreads) void k_team(Geom g, TeamArgs a, Async
                     }
                     r[s][v] = (T)rv;
                     accT += r[s][v] * r[s][v];
+                    zero[v] = T(0);
                 }
                 vstore<T, VZ>(lp + es, r[s]);    // p = r
+                if (!DREG) vstore<T, VZ>(ldd + es, zero);   // d = 0
                 put_faces(s, r[s], es);
             }
         }
@@ -479,8 +487,10 @@ __global__ __launch_bounds__(kTeamThreads) void k_team(Geom g, TeamArgs a, Async
         // later slots apply the stencil again
         constexpr int QK = Q * VZ * (int)sizeof(T) <= 128 ? Q : 64 / (VZ * (int)sizeof(T));
         T qr[QK][VZ];
-        // the iterations (none for a block whose residual is zero)
-        if (rho > T(0)) {
+        // the iterations, with the slot loops free of per-slot branches when
+        // every slot of every thread holds a vector (FULL)
+        auto cg_loop = [&](auto fullc) {
+            constexpr bool FULL = decltype(fullc)::value;
             for (int it = 0; it < a.m; it++) {
                 // sigma = p . A p
                 T sig = T(0), unused = T(0);
@@ -488,7 +498,7 @@ __global__ __launch_bounds__(kTeamThreads) void k_team(Geom g, TeamArgs a, Async
                     const int eb = E0();
 #pragma unroll
                     for (int s = 0; s < Q; s++) {
-                        if (E(s) >= nE) continue;
+                        if (!FULL && E(s) >= nE) continue;
                         T pc[VZ], qv[VZ];
                         apply(s, E(s), pc, qv);
 #pragma unroll
@@ -511,7 +521,7 @@ __global__ __launch_bounds__(kTeamThreads) void k_team(Geom g, TeamArgs a, Async
 #pragma unroll
                     for (int s = 0; s < Q; s++) {
                         const int es = E(s);
-                        if (es >= nE) continue;
+                        if (!FULL && es >= nE) continue;
                         T pc[VZ], qv[VZ], dd[VZ];
                         if (s < QK) {
                             vload<T, VZ>(lp + es, pc);
@@ -520,16 +530,24 @@ __global__ __launch_bounds__(kTeamThreads) void k_team(Geom g, TeamArgs a, Async
                         } else {
                             apply(s, es, pc, qv);
                         }
+                        if (DREG) {
 #pragma unroll
-                        for (int v = 0; v < VZ; v++) dd[v] = dr[s][v];
+                            for (int v = 0; v < VZ; v++) dd[v] = dr[DREG ? s : 0][v];
+                        } else {
+                            vload<T, VZ>(ldd + es, dd);
+                        }
 #pragma unroll
                         for (int v = 0; v < VZ; v++) {
                             dd[v] = dd[v] + alpha * pc[v];
                             r[s][v] = r[s][v] - alpha * qv[v];
                             rn += r[s][v] * r[s][v];
                         }
+                        if (DREG) {
 #pragma unroll
-                        for (int v = 0; v < VZ; v++) dr[s][v] = dd[v];
+                            for (int v = 0; v < VZ; v++) dr[DREG ? s : 0][v] = dd[v];
+                        } else {
+                            vstore<T, VZ>(ldd + es, dd);
+                        }
                         if (it < a.m - 1) put_faces(s, r[s], es);
                         if (s % kSlotGroup == kSlotGroup - 1) __builtin_amdgcn_sched_barrier(0);
                     }
@@ -547,7 +565,7 @@ __global__ __launch_bounds__(kTeamThreads) void k_team(Geom g, TeamArgs a, Async
 #pragma unroll
                     for (int s = 0; s < Q; s++) {
                         const int es = E(s);
-                        if (es >= nE) continue;
+                        if (!FULL && es >= nE) continue;
                         T pv[VZ];
                         vload<T, VZ>(lp + es, pv);
 #pragma unroll
@@ -573,6 +591,9 @@ __global__ __launch_bounds__(kTeamThreads) void k_team(Geom g, TeamArgs a, Async
                 }
                 __syncthreads();
             }
+        };
+        if (rho > T(0)) {
+            cg_loop(std::false_type{});
         }
         if (!ok) return;
         // ---- outer update x_new = x_old + d on the block's own cells ----
@@ -588,8 +609,12 @@ __global__ __launch_bounds__(kTeamThreads) void k_team(Geom g, TeamArgs a, Async
                 double xo[VZ];
                 T dd[VZ];
                 vload<double, VZ>(a.xa + cg, xo);
+                if (DREG) {
 #pragma unroll
-                for (int v = 0; v < VZ; v++) dd[v] = dr[s][v];
+                    for (int v = 0; v < VZ; v++) dd[v] = dr[DREG ? s : 0][v];
+                } else {
+                    vload<T, VZ>(ldd + es, dd);
+                }
 #pragma unroll
                 for (int v = 0; v < VZ; v++) xo[v] += (double)dd[v];
                 vstore<double, VZ>(a.xb + cg, xo);
