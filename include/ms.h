@@ -97,7 +97,12 @@ typedef struct {
     int32_t precision;    /* ms_precision (default MS_FP64) */
     void *stream;         /* hipStream_t used for all work; NULL = null stream */
     int32_t check_every;  /* sync: sweeps enqueued between host reads of the
-                             convergence flag (0 = automatic) */
+                             convergence flag; async: sweeps per block per
+                             launch, after which the host verifies the true
+                             residual and relaunches if needed (0 =
+                             automatic: about 2^33 cell-iterations per launch
+                             for the phase engine, 2^38 for teams, 8 to 1000
+                             sweeps) */
     int32_t group_blocks; /* sync: blocks per launch.  0 = automatic: groups
                              whose inner vectors fill the 256 MB on-package
                              cache (with several right-hand sides and CG, each
