@@ -663,6 +663,9 @@ def team_roofline(head, ceilings):
                  "for all inner iterations, so frac above 1 is the factor by which it beats the "
                  "HBM roofline of the streaming formulation; traffic is what it does fetch and "
                  "write past the L2s"),
+        "limited_by": ("the latency of the team sums (two per inner iteration, each a round trip "
+                       "through the XCD's L2 for every team member) and LDS traffic; the x and b "
+                       "reads run near the HBM share of a compute unit"),
         "hbm_moved": {"bytes_per_launch": k["hbm_bytes_per_launch"],
                       "bytes_per_unknown": TEAM_HBM_BYTES, "achieved": k["hbm_GBps"],
                       "frac": round(k["hbm_GBps"] / HBM_PEAK_GBPS, 4)},
